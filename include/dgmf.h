@@ -1,0 +1,176 @@
+/*
+ * dgmf.h - C ABI of the MI355X matrix-free DG operator library (libdgmf.so).
+ *
+ * Operators of the discontinuous Galerkin discretisation of Sec. 3.2 on
+ * periodic Cartesian hexahedral meshes with tensor-product Lagrange bases on
+ * Legendre-Gauss-Lobatto (LGL) nodes of degree k and Gauss quadrature, and
+ * the preconditioned CG solver of Sec. 3.3.  All compute runs in HIP kernels
+ * for gfx950.
+ *
+ * Mesh and layout (every entry point)
+ *   - elements per direction n_el[d], box edge length[d]; element size
+ *     h_d = length[d] / n_el[d]; periodic in all three directions.
+ *   - element e = ex + Nx*(ey + Ny*ez); n = k+1; local node i = a + n*(b + n*c),
+ *     a the x index (fastest); node (a,b,c) sits at reference point
+ *     (xi_a, xi_b, xi_c) of the LGL nodes xi on [0, 1].
+ *   - scalar field: [N_el][n^3]; vector field: [3][N_el][n^3] (component major).
+ *   - element arrays are contiguous; 256-byte aligned device pointers are
+ *     recommended (any 8-byte (f64) / 4-byte (f32) alignment is accepted).
+ *
+ * Ownership and synchronisation
+ *   - every array pointer is a caller-owned DEVICE pointer, except where a
+ *     parameter says "host".  The library owns only its own small caches
+ *     (1D tables, solver work vectors).
+ *   - apply / vjp / divergence calls are asynchronous on `hip_stream`
+ *     (a hipStream_t; NULL = the default stream).  dg_cg_solve blocks until
+ *     it returns.
+ *   - outputs are overwritten, never accumulated.  Inputs and outputs must
+ *     not overlap (DG_ERR_ALIAS).
+ *
+ * Errors
+ *   - 0 = DG_OK.  Negative codes are hard errors: nothing was launched and
+ *     outputs are untouched.  Positive codes are soft solver failures: x holds
+ *     the last iterate and the report is filled.  No C++ exception crosses the
+ *     ABI.  dg_last_error() gives a per-thread message for the last failure.
+ */
+#ifndef DGMF_H
+#define DGMF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  DG_OK = 0,
+  DG_ERR_INVALID_ARG = -1,   /* null pointer, bad size, non-finite parameter */
+  DG_ERR_UNSUPPORTED = -2,   /* degree or quadrature count without a kernel   */
+  DG_ERR_ALIAS = -3,         /* an output overlaps an input                   */
+  DG_ERR_HIP = -4,           /* a HIP runtime call failed                     */
+  DG_NOT_CONVERGED = 1,      /* CG hit max_iter before the tolerance          */
+  DG_ERR_BREAKDOWN = 2       /* CG met p.Ap <= 0, or a NaN/Inf residual       */
+};
+
+typedef enum { DG_F64 = 0, DG_F32 = 1 } dg_dtype;
+
+/* Operator descriptor.  All fields are used exactly as given. */
+typedef struct {
+  int32_t degree;          /* k, 1..11 (n = k+1 LGL nodes per direction)            */
+  int32_t n_el[3];         /* elements per direction, each >= 1                      */
+  double  length[3];       /* box edge per direction, > 0 (2*pi for [-pi, pi]^3)     */
+  int32_t n_q;             /* 1D Gauss points; 0 = default: k+1 for the Laplace and
+                              divergence forms, floor(3k/2)+1 (the 3/2 rule of
+                              Sec. 3.2) for the convective form                      */
+  double  penalty_factor;  /* SIPG penalty tau = penalty_factor*(k+1)^2/h_d on faces
+                              normal to d (the paper gives no formula; 1 is usual)  */
+  double  scale;           /* multiplies the Laplace form (nu for the viscous v_h)  */
+  int32_t n_comp;          /* Laplace: 1 (pressure) or 3 (velocity, per component)  */
+  double  lf_factor;       /* coefficient of the Lax-Friedrichs jump term; the
+                              paper's c_h has 1 (no factor 1/2)                     */
+} dg_op_desc;
+
+/*
+ * SIPG negative Laplacian l_h (Sec. 3.2, weak form of l_h; v_h is `scale`
+ * times it per component):
+ *   dst_i = scale * [ (grad phi_i, grad u)_K
+ *                     + sum_faces ( -1/2 (grad phi_i . n)(u- - u+)
+ *                                   -1/2 phi_i (grad u- + grad u+) . n
+ *                                   + tau phi_i (u- - u+) ) ]
+ * with n the outward normal of the element that owns phi_i.
+ *   src, dst: [n_comp][N_el][n^3] of `dtype` (double or float).
+ * Degrees 1..11; any n_q in 1..32 (k+1 integrates exactly on these cells).
+ * The operator is symmetric, so it is also its own vector-Jacobian product.
+ */
+int dg_apply_laplace(const dg_op_desc* desc, dg_dtype dtype, const void* src, void* dst,
+                     void* hip_stream);
+
+/*
+ * Convective term c_h with the local Lax-Friedrichs flux (Sec. 3.2, weak form
+ * of c_h, F_c(u) = u (x) u):
+ *   r_{c,i} = -(d_j phi_i, u_c u_j)_K
+ *             + sum_faces (phi_i, 1/2 (u-_c (u-.n) + u+_c (u+.n))
+ *                                 + lf_factor * max(|u-.n|, |u+.n|) (u-_c - u+_c))
+ * with the maximum taken pointwise at each face quadrature point.
+ *   u, r: [3][N_el][n^3] of `dtype`.  n_q must be 0 or floor(3k/2)+1.
+ */
+int dg_apply_convective(const dg_op_desc* desc, dg_dtype dtype, const void* u, void* r,
+                        void* hip_stream);
+
+/*
+ * Vector-Jacobian product of dg_apply_convective: grad_u = J(u)^T w.
+ * Cell part g_j = -(phi, sum_m u_m d_m w_j + sum_i u_i d_j w_i).  Face part
+ * (each element from its own side, no atomics): (phi, sum_i (w-_i - w+_i)
+ * dF*_i/du-_j).  At kinks of the max the derivative takes 1/2 from each side
+ * on exact ties |u-.n| = |u+.n|, and sign(0) = 0.
+ *   u, w, grad_u: [3][N_el][n^3] of `dtype`; grad_u must not overlap u or w.
+ */
+int dg_vjp_convective(const dg_op_desc* desc, dg_dtype dtype, const void* u, const void* w,
+                      void* grad_u, void* hip_stream);
+
+/*
+ * Velocity divergence d_h with central flux (Sec. 3.2, weak form of d_h), the
+ * right-hand side of the pressure Poisson step without its -gamma_0/dt factor:
+ *   b_i = -(grad phi_i, u)_K + sum_faces (phi_i, 1/2 (u- + u+) . n)
+ *   u: [3][N_el][n^3], b: [N_el][n^3] of `dtype`.  Uses n_q (default k+1).
+ */
+int dg_apply_divergence(const dg_op_desc* desc, dg_dtype dtype, const void* u, void* b,
+                        void* hip_stream);
+
+enum { DG_PC_JACOBI_F64 = 0, DG_PC_CHEB_F32 = 1 };
+
+typedef struct {
+  int32_t precond;       /* DG_PC_JACOBI_F64: z = D^-1 r in double;
+                            DG_PC_CHEB_F32: Chebyshev smoother of D^-1 A in float
+                            (Sec. 3.3: degree 5, smoothing range 20), started at 0  */
+  int32_t cheb_degree;   /* error-polynomial degree; degree-1 float applies per call */
+  double  cheb_range;    /* lambda_min = lambda_max / cheb_range                     */
+  double  rtol, atol;    /* stop when ||r||_2 <= max(rtol*||b||_2, atol)             */
+  int32_t max_iter;
+  int32_t project_mean;  /* 1: keep r and z at zero coefficient mean (periodic)     */
+} dg_cg_opts;
+
+typedef struct {
+  int32_t iterations;    /* CG iterations done                                       */
+  int32_t matvec_f64;    /* double-precision operator applications                   */
+  int32_t matvec_f32;    /* single-precision operator applications (preconditioner)  */
+  double  rel_res;       /* recursive ||r||/||b|| at exit                             */
+  double  true_rel_res;  /* ||b - A x||/||b|| recomputed in double at exit           */
+  double  lambda_max;    /* estimate of the largest eigenvalue of D^-1 A (Chebyshev) */
+  double  seconds_solve; /* wall time of the iteration (setup excluded)              */
+  double  seconds_setup; /* diagonal, eigenvalue estimate, work vectors              */
+} dg_cg_report;
+
+/*
+ * Solve A x = b with the SIPG form of dg_apply_laplace (n_comp must be 1) by
+ * flexible preconditioned CG (Sec. 3.3) in double precision: residuals, dot
+ * products and the updates of x, r and p stay in double on the GPU; with
+ * DG_PC_CHEB_F32 the preconditioner runs single-precision operator applies.
+ *   b: [N_el][n^3] double (device); x: [N_el][n^3] double (device), initial
+ *   guess in, solution out; report: host pointer, may be NULL.
+ * Returns DG_OK, DG_NOT_CONVERGED or DG_ERR_BREAKDOWN (x holds the last
+ * iterate), or a negative error.  Blocks the calling thread.
+ */
+int dg_cg_solve(const dg_op_desc* desc, const dg_cg_opts* opts, const double* b, double* x,
+                dg_cg_report* report, void* hip_stream);
+
+/*
+ * diag(A) of the SIPG form on one element (identical on every element of a
+ * uniform periodic mesh with at least 2 elements per direction): host array of
+ * n^3 doubles.  Setup for the Jacobi and Chebyshev preconditioners (Sec. 3.3:
+ * the diagonal is precomputed in the setup phase).
+ */
+int dg_laplace_diagonal(const dg_op_desc* desc, double* diag_host);
+
+/* The k+1 LGL nodes of degree k on [0, 1] (Sec. 3.2), into a host array. */
+int dg_lgl_nodes(int32_t degree, double* nodes_host);
+
+const char* dg_error_string(int code);
+/* Message of the last failing call on this thread ("" if none). */
+const char* dg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DGMF_H */

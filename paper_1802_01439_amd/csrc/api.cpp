@@ -1,0 +1,210 @@
+// C ABI of libdgmf: argument validation, 1D tables, dispatch to the kernels.
+#include "dgmf.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+
+#include "api_internal.h"
+#include "basis1d.h"
+#include "ops.h"
+
+namespace dgmf {
+
+namespace {
+thread_local std::string g_last_error;
+std::mutex g_basis_mutex;
+std::map<std::pair<int, int>, Basis1D> g_basis;
+}  // namespace
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+int ok() {
+  g_last_error.clear();
+  return DG_OK;
+}
+
+int hip_fail(hipError_t e, const char* where) {
+  return fail(DG_ERR_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+const Basis1D& basis(int k, int m) {
+  std::lock_guard<std::mutex> lock(g_basis_mutex);
+  auto key = std::make_pair(k, m);
+  auto it = g_basis.find(key);
+  if (it == g_basis.end()) it = g_basis.emplace(key, make_basis(k, m)).first;
+  return it->second;
+}
+
+int validate_desc(const dg_op_desc* d) {
+  if (!d) return fail(DG_ERR_INVALID_ARG, "descriptor is NULL");
+  if (d->degree < 1 || d->degree > kMaxDegree)
+    return fail(DG_ERR_UNSUPPORTED, "degree " + std::to_string(d->degree) + " outside 1.." +
+                                        std::to_string(kMaxDegree));
+  long long nel = 1;
+  for (int i = 0; i < 3; ++i) {
+    if (d->n_el[i] < 1) return fail(DG_ERR_INVALID_ARG, "n_el must be >= 1 in every direction");
+    if (!(std::isfinite(d->length[i]) && d->length[i] > 0))
+      return fail(DG_ERR_INVALID_ARG, "length must be finite and > 0");
+    nel *= d->n_el[i];
+  }
+  const long long n3 = (long long)(d->degree + 1) * (d->degree + 1) * (d->degree + 1);
+  if (nel * 3 > (1LL << 31) - 1 || nel * 3 * n3 > (1LL << 40))
+    return fail(DG_ERR_INVALID_ARG, "mesh too large");
+  if (d->n_q < 0 || d->n_q > kMaxNq) return fail(DG_ERR_UNSUPPORTED, "n_q outside 0..32");
+  if (!std::isfinite(d->penalty_factor) || !std::isfinite(d->scale) || !std::isfinite(d->lf_factor))
+    return fail(DG_ERR_INVALID_ARG, "penalty_factor, scale and lf_factor must be finite");
+  return DG_OK;
+}
+
+long long num_elements(const dg_op_desc* d) {
+  return (long long)d->n_el[0] * d->n_el[1] * d->n_el[2];
+}
+
+long long dofs_per_element(const dg_op_desc* d) {
+  const long long n = d->degree + 1;
+  return n * n * n;
+}
+
+bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+  const char* pa = (const char*)a;
+  const char* pb = (const char*)b;
+  return pa < pb + nb && pb < pa + na;
+}
+
+MeshArgs mesh_args(const dg_op_desc* d) {
+  MeshArgs m;
+  m.nx = d->n_el[0];
+  m.ny = d->n_el[1];
+  m.nz = d->n_el[2];
+  m.n_el = m.nx * m.ny * m.nz;
+  return m;
+}
+
+LaplacePlan make_laplace_plan(const dg_op_desc* d, int n_comp) {
+  const int k = d->degree;
+  const int m = d->n_q ? d->n_q : k + 1;
+  const Basis1D& B = basis(k, m);
+  const double sigma = d->penalty_factor * (k + 1.0) * (k + 1.0);
+  Sipg1D S = make_sipg_1d(B, sigma);
+  LaplacePlan P;
+  P.k = k;
+  P.n_comp = n_comp;
+  P.mesh = mesh_args(d);
+  P.Mref = B.Mref;
+  P.Kown = S.Kown;
+  P.D = B.D;
+  double h[3], vol = 1.0;
+  for (int i = 0; i < 3; ++i) {
+    h[i] = d->length[i] / d->n_el[i];
+    vol *= h[i];
+  }
+  for (int i = 0; i < 3; ++i) P.c[i] = d->scale * vol / (h[i] * h[i]);
+  P.sigma = sigma;
+  return P;
+}
+
+}  // namespace dgmf
+
+using namespace dgmf;
+
+extern "C" {
+
+const char* dg_error_string(int code) {
+  switch (code) {
+    case DG_OK: return "success";
+    case DG_ERR_INVALID_ARG: return "invalid argument";
+    case DG_ERR_UNSUPPORTED: return "unsupported degree or quadrature";
+    case DG_ERR_ALIAS: return "output overlaps an input";
+    case DG_ERR_HIP: return "HIP runtime error";
+    case DG_NOT_CONVERGED: return "solver did not converge";
+    case DG_ERR_BREAKDOWN: return "solver breakdown";
+    default: return "unknown error code";
+  }
+}
+
+const char* dg_last_error(void) { return g_last_error.c_str(); }
+
+int dg_lgl_nodes(int32_t degree, double* nodes_host) {
+  if (!nodes_host) return fail(DG_ERR_INVALID_ARG, "nodes_host is NULL");
+  if (degree < 1 || degree > 64) return fail(DG_ERR_UNSUPPORTED, "degree outside 1..64");
+  lgl_nodes(degree, nodes_host);
+  return ok();
+}
+
+int dg_laplace_diagonal(const dg_op_desc* desc, double* diag_host) {
+  int rc = validate_desc(desc);
+  if (rc) return rc;
+  if (!diag_host) return fail(DG_ERR_INVALID_ARG, "diag_host is NULL");
+  const int k = desc->degree, n = k + 1;
+  const int m = desc->n_q ? desc->n_q : k + 1;
+  const Basis1D& B = basis(k, m);
+  const double sigma = desc->penalty_factor * (k + 1.0) * (k + 1.0);
+  Sipg1D S = make_sipg_1d(B, sigma);
+  LaplacePlan P = make_laplace_plan(desc, 1);
+  // 1D diagonals per direction; with a single element in a direction the
+  // element is its own neighbour and the couplings land on the diagonal.
+  std::vector<double> kd(3 * n), md(n);
+  for (int i = 0; i < n; ++i) md[i] = B.Mref[i * n + i];
+  for (int d = 0; d < 3; ++d)
+    for (int i = 0; i < n; ++i) {
+      double v = S.Kown[i * n + i];
+      if (desc->n_el[d] == 1) v += S.Kl[i * n + i] + S.Kr[i * n + i];
+      kd[d * n + i] = v;
+    }
+  for (int c = 0; c < n; ++c)
+    for (int b = 0; b < n; ++b)
+      for (int a = 0; a < n; ++a)
+        diag_host[a + n * (b + n * c)] = P.c[0] * kd[0 * n + a] * md[b] * md[c] +
+                                         P.c[1] * md[a] * kd[1 * n + b] * md[c] +
+                                         P.c[2] * md[a] * md[b] * kd[2 * n + c];
+  return ok();
+}
+
+int dg_apply_laplace(const dg_op_desc* desc, dg_dtype dtype, const void* src, void* dst,
+                     void* hip_stream) {
+  int rc = validate_desc(desc);
+  if (rc) return rc;
+  if (dtype != DG_F64 && dtype != DG_F32) return fail(DG_ERR_INVALID_ARG, "dtype must be DG_F64 or DG_F32");
+  if (desc->n_comp != 1 && desc->n_comp != 3) return fail(DG_ERR_INVALID_ARG, "n_comp must be 1 or 3");
+  if (!src || !dst) return fail(DG_ERR_INVALID_ARG, "src/dst is NULL");
+  const size_t bytes = (size_t)desc->n_comp * num_elements(desc) * dofs_per_element(desc) *
+                       (dtype == DG_F64 ? 8 : 4);
+  if (overlaps(src, bytes, dst, bytes)) return fail(DG_ERR_ALIAS, "dst overlaps src");
+  LaplacePlan P = make_laplace_plan(desc, desc->n_comp);
+  hipError_t e = launch_laplace(P, dtype == DG_F32, src, dst, (hipStream_t)hip_stream);
+  if (e != hipSuccess) return hip_fail(e, "laplace kernel launch");
+  return ok();
+}
+
+int dg_apply_convective(const dg_op_desc* desc, dg_dtype dtype, const void* u, void* r, void* s) {
+  (void)desc; (void)dtype; (void)u; (void)r; (void)s;
+  return fail(DG_ERR_UNSUPPORTED, "convective operator not available in this build");
+}
+
+int dg_vjp_convective(const dg_op_desc* desc, dg_dtype dtype, const void* u, const void* w,
+                      void* g, void* s) {
+  (void)desc; (void)dtype; (void)u; (void)w; (void)g; (void)s;
+  return fail(DG_ERR_UNSUPPORTED, "convective VJP not available in this build");
+}
+
+int dg_apply_divergence(const dg_op_desc* desc, dg_dtype dtype, const void* u, void* b, void* s) {
+  (void)desc; (void)dtype; (void)u; (void)b; (void)s;
+  return fail(DG_ERR_UNSUPPORTED, "divergence operator not available in this build");
+}
+
+int dg_cg_solve(const dg_op_desc* desc, const dg_cg_opts* opts, const double* b, double* x,
+                dg_cg_report* report, void* s) {
+  (void)desc; (void)opts; (void)b; (void)x; (void)report; (void)s;
+  return fail(DG_ERR_UNSUPPORTED, "CG solver not available in this build");
+}
+
+}  // extern "C"

@@ -1,0 +1,27 @@
+// Internal launch interface between the C ABI layer and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "common.h"
+
+namespace dgmf {
+
+// Everything a Laplace launch needs, in double; kernels cast to their type.
+struct LaplacePlan {
+  int k = 0;
+  int n_comp = 1;
+  MeshArgs mesh{};
+  std::vector<double> Mref;  // n x n 1D mass on [0,1]
+  std::vector<double> Kown;  // n x n 1D SIPG own-element part on [0,1]
+  std::vector<double> D;     // n x n l_j'(xi_i) at the LGL nodes
+  double c[3] = {0, 0, 0};   // scale * vol / h_d^2
+  double sigma = 0;          // penalty_factor * (k+1)^2
+};
+
+hipError_t launch_laplace(const LaplacePlan& P, bool f32, const void* src, void* dst,
+                          hipStream_t stream);
+
+}  // namespace dgmf

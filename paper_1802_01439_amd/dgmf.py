@@ -1,0 +1,233 @@
+"""Thin ctypes binding of libdgmf.so (the C ABI in include/dgmf.h).
+
+Argument marshalling only: every step of every operator runs in the HIP
+library.  Tensors must be contiguous CUDA (ROCm) tensors of float64 or
+float32; the call is enqueued on torch's current stream.  If the library has
+not been built, every entry point raises.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libdgmf.so")
+
+DG_OK = 0
+DG_ERR_INVALID_ARG = -1
+DG_ERR_UNSUPPORTED = -2
+DG_ERR_ALIAS = -3
+DG_ERR_HIP = -4
+DG_NOT_CONVERGED = 1
+DG_ERR_BREAKDOWN = 2
+DG_F64, DG_F32 = 0, 1
+DG_PC_JACOBI_F64, DG_PC_CHEB_F32 = 0, 1
+
+EXPORTS = ("dg_apply_laplace", "dg_apply_convective", "dg_vjp_convective", "dg_apply_divergence",
+           "dg_cg_solve", "dg_laplace_diagonal", "dg_lgl_nodes", "dg_error_string", "dg_last_error")
+
+
+class OpDesc(ctypes.Structure):
+    _fields_ = [("degree", ctypes.c_int32), ("n_el", ctypes.c_int32 * 3), ("length", ctypes.c_double * 3),
+                ("n_q", ctypes.c_int32), ("penalty_factor", ctypes.c_double), ("scale", ctypes.c_double),
+                ("n_comp", ctypes.c_int32), ("lf_factor", ctypes.c_double)]
+
+
+class CgOpts(ctypes.Structure):
+    _fields_ = [("precond", ctypes.c_int32), ("cheb_degree", ctypes.c_int32), ("cheb_range", ctypes.c_double),
+                ("rtol", ctypes.c_double), ("atol", ctypes.c_double), ("max_iter", ctypes.c_int32),
+                ("project_mean", ctypes.c_int32)]
+
+
+class CgReport(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("matvec_f64", ctypes.c_int32), ("matvec_f32", ctypes.c_int32),
+                ("rel_res", ctypes.c_double), ("true_rel_res", ctypes.c_double), ("lambda_max", ctypes.c_double),
+                ("seconds_solve", ctypes.c_double), ("seconds_setup", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class DgError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libdgmf error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Load libdgmf.so (once).  Raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: run __graft_entry__.build() "
+                               "(python -m paper_1802_01439_amd.build) first")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, dp, i32 = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int32
+        pd = ctypes.POINTER(OpDesc)
+        L.dg_apply_laplace.argtypes = [pd, ctypes.c_int, vp, vp, vp]
+        L.dg_apply_convective.argtypes = [pd, ctypes.c_int, vp, vp, vp]
+        L.dg_vjp_convective.argtypes = [pd, ctypes.c_int, vp, vp, vp, vp]
+        L.dg_apply_divergence.argtypes = [pd, ctypes.c_int, vp, vp, vp]
+        L.dg_cg_solve.argtypes = [pd, ctypes.POINTER(CgOpts), vp, vp, ctypes.POINTER(CgReport), vp]
+        L.dg_laplace_diagonal.argtypes = [pd, dp]
+        L.dg_lgl_nodes.argtypes = [i32, dp]
+        L.dg_error_string.argtypes = [ctypes.c_int]
+        L.dg_error_string.restype = ctypes.c_char_p
+        L.dg_last_error.argtypes = []
+        L.dg_last_error.restype = ctypes.c_char_p
+        for name in ("dg_apply_laplace", "dg_apply_convective", "dg_vjp_convective", "dg_apply_divergence",
+                     "dg_cg_solve", "dg_laplace_diagonal", "dg_lgl_nodes"):
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc, soft_ok=False):
+    if rc == DG_OK or (soft_ok and rc > 0):
+        return rc
+    L = lib()
+    raise DgError(rc, f"{L.dg_error_string(rc).decode()}: {L.dg_last_error().decode()}")
+
+
+def make_desc(degree, n_el, length=None, n_q=0, penalty_factor=1.0, scale=1.0, n_comp=1, lf_factor=1.0):
+    if isinstance(n_el, int):
+        n_el = (n_el, n_el, n_el)
+    if length is None:
+        length = (2 * np.pi,) * 3
+    elif np.isscalar(length):
+        length = (float(length),) * 3
+    d = OpDesc()
+    d.degree = int(degree)
+    for i in range(3):
+        d.n_el[i] = int(n_el[i])
+        d.length[i] = float(length[i])
+    d.n_q = int(n_q)
+    d.penalty_factor = float(penalty_factor)
+    d.scale = float(scale)
+    d.n_comp = int(n_comp)
+    d.lf_factor = float(lf_factor)
+    return d
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dtype_code(t):
+    torch = _torch()
+    if t.dtype == torch.float64:
+        return DG_F64
+    if t.dtype == torch.float32:
+        return DG_F32
+    raise TypeError(f"unsupported dtype {t.dtype}; use float64 or float32")
+
+
+def _check_tensor(t, name, shape):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+
+
+def _stream(t):
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def _nel(desc):
+    return desc.n_el[0] * desc.n_el[1] * desc.n_el[2]
+
+
+def apply_laplace(desc, u, out=None):
+    """SIPG Laplace apply; u: [N_el, n^3] (n_comp=1) or [3, N_el, n^3] (n_comp=3)."""
+    torch = _torch()
+    n3 = (desc.degree + 1) ** 3
+    shape = (_nel(desc), n3) if desc.n_comp == 1 else (3, _nel(desc), n3)
+    _check_tensor(u, "u", shape)
+    if out is None:
+        out = torch.empty_like(u)
+    _check_tensor(out, "out", shape)
+    _check(lib().dg_apply_laplace(ctypes.byref(desc), _dtype_code(u), ctypes.c_void_p(u.data_ptr()),
+                                  ctypes.c_void_p(out.data_ptr()), _stream(u)))
+    return out
+
+
+def apply_convective(desc, u, out=None):
+    """Convective LLF apply; u, out: [3, N_el, n^3]."""
+    torch = _torch()
+    shape = (3, _nel(desc), (desc.degree + 1) ** 3)
+    _check_tensor(u, "u", shape)
+    if out is None:
+        out = torch.empty_like(u)
+    _check_tensor(out, "out", shape)
+    _check(lib().dg_apply_convective(ctypes.byref(desc), _dtype_code(u), ctypes.c_void_p(u.data_ptr()),
+                                     ctypes.c_void_p(out.data_ptr()), _stream(u)))
+    return out
+
+
+def vjp_convective(desc, u, w, out=None):
+    """J(u)^T w for the convective apply; all [3, N_el, n^3]."""
+    torch = _torch()
+    shape = (3, _nel(desc), (desc.degree + 1) ** 3)
+    _check_tensor(u, "u", shape)
+    _check_tensor(w, "w", shape)
+    if w.dtype != u.dtype:
+        raise TypeError("u and w must have the same dtype")
+    if out is None:
+        out = torch.empty_like(u)
+    _check_tensor(out, "out", shape)
+    _check(lib().dg_vjp_convective(ctypes.byref(desc), _dtype_code(u), ctypes.c_void_p(u.data_ptr()),
+                                   ctypes.c_void_p(w.data_ptr()), ctypes.c_void_p(out.data_ptr()), _stream(u)))
+    return out
+
+
+def apply_divergence(desc, u, out=None):
+    """Central-flux divergence d_h(phi_i, u); u: [3, N_el, n^3] -> [N_el, n^3]."""
+    torch = _torch()
+    n3 = (desc.degree + 1) ** 3
+    _check_tensor(u, "u", (3, _nel(desc), n3))
+    if out is None:
+        out = torch.empty((_nel(desc), n3), dtype=u.dtype, device=u.device)
+    _check_tensor(out, "out", (_nel(desc), n3))
+    _check(lib().dg_apply_divergence(ctypes.byref(desc), _dtype_code(u), ctypes.c_void_p(u.data_ptr()),
+                                     ctypes.c_void_p(out.data_ptr()), _stream(u)))
+    return out
+
+
+def cg_solve(desc, b, x=None, precond=DG_PC_CHEB_F32, cheb_degree=5, cheb_range=20.0, rtol=1e-10,
+             atol=0.0, max_iter=5000, project_mean=True):
+    """FP64 CG on the SIPG Laplacian; returns (x, report dict, return code)."""
+    torch = _torch()
+    n3 = (desc.degree + 1) ** 3
+    _check_tensor(b, "b", (_nel(desc), n3))
+    if b.dtype != torch.float64:
+        raise TypeError("b must be float64")
+    if x is None:
+        x = torch.zeros_like(b)
+    _check_tensor(x, "x", (_nel(desc), n3))
+    o = CgOpts()
+    o.precond, o.cheb_degree, o.cheb_range = int(precond), int(cheb_degree), float(cheb_range)
+    o.rtol, o.atol, o.max_iter, o.project_mean = float(rtol), float(atol), int(max_iter), int(project_mean)
+    rep = CgReport()
+    rc = _check(lib().dg_cg_solve(ctypes.byref(desc), ctypes.byref(o), ctypes.c_void_p(b.data_ptr()),
+                                  ctypes.c_void_p(x.data_ptr()), ctypes.byref(rep), _stream(b)), soft_ok=True)
+    return x, rep.as_dict(), rc
+
+
+def laplace_diagonal(desc):
+    n3 = (desc.degree + 1) ** 3
+    out = np.zeros(n3)
+    _check(lib().dg_laplace_diagonal(ctypes.byref(desc), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return out
+
+
+def lgl_nodes(degree):
+    out = np.zeros(degree + 1)
+    _check(lib().dg_lgl_nodes(int(degree), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return out
