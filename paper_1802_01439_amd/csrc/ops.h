@@ -24,4 +24,21 @@ struct LaplacePlan {
 hipError_t launch_laplace(const LaplacePlan& P, bool f32, const void* src, void* dst,
                           hipStream_t stream);
 
+// Convective form and its VJP: 1D tables on [0,1] and the cell/face scalings.
+struct ConvPlan {
+  int k = 0;
+  int m = 0;                 // Gauss points per direction (floor(3k/2)+1)
+  MeshArgs mesh{};
+  std::vector<double> S;     // m x n: l_a(z_q)
+  std::vector<double> G;     // m x n: l_a'(z_q)
+  std::vector<double> w;     // m Gauss weights
+  double cell[3] = {0, 0, 0};   // -vol/h_j
+  double area[3] = {0, 0, 0};   // vol/h_d
+  double lf = 1.0;
+};
+
+hipError_t launch_convective(const ConvPlan& P, bool f32, const void* u, void* r, hipStream_t s);
+hipError_t launch_convective_vjp(const ConvPlan& P, bool f32, const void* u, const void* w,
+                                 void* g, hipStream_t s);
+
 }  // namespace dgmf
