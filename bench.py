@@ -1,0 +1,287 @@
+#!/usr/bin/env python3
+"""Throughput of the matrix-free DG operator applies on one MI355X.
+
+Metric: DoFs/s per operator apply against degree k, FP64 and FP32, with the
+fraction of the HBM roofline.  One step is one pass over the degree sweep:
+for k = 2..11 on a periodic cube of N = round(256/(k+1)) elements per
+direction (about 1.7e7 DoFs per component), the SIPG Laplace apply and the
+convective (LLF) apply, each in FP64 and FP32.  Inputs are seeded U[-1,1]
+fields resident in HBM before timing starts.  `value` is the total DoFs
+processed in a step divided by the step time.
+
+Also measured once, outside the timed steps: the convective VJP on 32^3
+elements at k=4 (FP64, FP32) and the pressure-Poisson CG (k=7, 24^3) with the
+FP32 Chebyshev preconditioner against FP64 Jacobi-CG.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--kmin 2 --kmax 11]
+                    [--ops laplace,convective] [--no-cpu-baseline] [--no-extras]
+                    [--sweep-out FILE] [--only OP:K:DTYPE]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "DoFs/sec per operator apply vs degree k (FP64, FP32); % HBM roofline"
+HBM_PEAK_GBS = 8000.0
+# algorithmic bytes per DoF of one apply: read the input once, write the output once
+BYTES_PER_DOF = {("laplace", "f64"): 16, ("laplace", "f32"): 8,
+                 ("convective", "f64"): 16, ("convective", "f32"): 8,
+                 ("vjp", "f64"): 24, ("vjp", "f32"): 12}
+KERNEL_NAME = {"laplace": "laplace_kernel", "convective": "convective_kernel", "vjp": "convective_vjp_kernel"}
+SOURCES = {"laplace": "laplace.hip", "convective": "convective.hip", "vjp": "convective_vjp.hip"}
+
+
+def sweep_mesh(k):
+    return int(round(256.0 / (k + 1)))
+
+
+def source_hash(op):
+    p = os.path.join(ROOT, "paper_1802_01439_amd", "csrc", SOURCES[op])
+    with open(p, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def load_traffic(op, k, dtype):
+    """HBM traffic per launch from the committed rocprofv3 counter summary,
+    or None if there is none for this kernel or its source has changed."""
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(p):
+        return None
+    with open(p) as f:
+        tab = json.load(f)
+    e = tab.get(f"{op}:k{k}:{dtype}")
+    if not e or e.get("source_sha") != source_hash(op):
+        return None
+    return e.get("bytes_per_launch")
+
+
+class Case:
+    def __init__(self, op, k, N, dtype, dgmf, torch, base):
+        self.op, self.k, self.N, self.dtype = op, k, N, dtype
+        ncomp = 1 if op == "laplace" else 3
+        self.desc = dgmf.make_desc(k, N, n_comp=1)
+        tdt = torch.float64 if dtype == "f64" else torch.float32
+        n3 = (k + 1) ** 3
+        src = base[:ncomp].reshape(ncomp, N ** 3, n3) if ncomp == 3 else base[0]
+        self.u = src.to(tdt).contiguous()
+        self.out = torch.empty_like(self.u)
+        self.dofs = ncomp * N ** 3 * n3
+        self.bytes = BYTES_PER_DOF[(op, dtype)] * self.dofs
+        self.fn = dgmf.apply_laplace if op == "laplace" else dgmf.apply_convective
+        self.times = []
+
+    def launch(self):
+        self.fn(self.desc, self.u, self.out)
+
+    def name(self):
+        return f"{self.op}:k{self.k}:{self.dtype}"
+
+
+def build_cases(args, torch, dgmf, inputs, dev):
+    cases = []
+    only = set(args.only.split(",")) if args.only else None
+    for k in range(args.kmin, args.kmax + 1):
+        N = sweep_mesh(k)
+        n3 = (k + 1) ** 3
+        need3 = "convective" in args.ops
+        shape = (3 if need3 else 1, N ** 3, n3)
+        # seeded U[-1,1] (the degree-sweep input), generated once per degree
+        base = torch.from_numpy(inputs.uniform(shape, seed=inputs.FIELD_SEED_BASE + 2 + 10 * k)).to(dev)
+        for op in args.ops:
+            for dtype in ("f64", "f32"):
+                c = Case(op, k, N, dtype, dgmf, torch, base)
+                if only and c.name() not in only:
+                    continue
+                cases.append(c)
+        del base
+    return cases
+
+
+def cpu_baseline(args):
+    """The oracle (plain NumPy, explicit 3D tables) on a bounded sample of the
+    sweep: every degree, both operators, a fixed number of elements each."""
+    from oracle import mesh as M
+    from oracle.convective import convective_apply
+    from oracle.laplace import laplace_apply
+    from paper_1802_01439_amd import inputs
+    try:
+        import threadpoolctl
+        cores = max([i.get("num_threads", 1) for i in threadpoolctl.threadpool_info()] or [os.cpu_count()])
+    except Exception:
+        cores = os.cpu_count()
+    tot_dofs, tot_t, parts = 0, 0.0, []
+    for k in range(args.kmin, args.kmax + 1):
+        N = sweep_mesh(k)
+        msh = M.cube(N)
+        n3 = (k + 1) ** 3
+        ne_l = max(16, int(2.0e6 / n3))            # ~2e6 DoFs of Laplace per degree
+        ne_c = max(4, int(0.6e6 / (3 * n3)))       # ~6e5 DoFs of convective per degree
+        u = inputs.uniform((3, msh.N, n3), seed=inputs.FIELD_SEED_BASE + 2 + 10 * k)
+        for op, ne in (("laplace", ne_l), ("convective", ne_c)):
+            if op not in args.ops:
+                continue
+            E = np.arange(min(ne, msh.N))
+            t0 = time.perf_counter()
+            if op == "laplace":
+                laplace_apply(u[0], k, msh, elems=E)
+                d = len(E) * n3
+            else:
+                convective_apply(u, k, msh, elems=E)
+                d = 3 * len(E) * n3
+            dt = time.perf_counter() - t0
+            tot_dofs += d
+            tot_t += dt
+            parts.append(f"{op} k={k}: {len(E)} el")
+    return {"value": tot_dofs / tot_t, "unit": "DoFs/s", "cores": int(cores), "kind": "oracle",
+            "sample": (f"oracle (float64, explicit 3D tables) FP64 applies on the first elements of each "
+                       f"degree-sweep mesh, k={args.kmin}..{args.kmax}: ~2e6 Laplace DoFs and ~6e5 "
+                       f"convective DoFs per degree ({tot_dofs} DoFs, {tot_t:.1f} s)")}
+
+
+def extras(torch, dgmf, inputs, dev, args):
+    out = {}
+    # convective VJP, k=4, 32^3, TGV + noise velocity and N(0,1) cotangent
+    try:
+        k, N = 4, 32
+        d = dgmf.make_desc(k, N)
+        nodes = dgmf.lgl_nodes(k)
+        u = inputs.tgv_plus_noise(nodes, (N, N, N), (2 * np.pi,) * 3, seed=inputs.FIELD_SEED_BASE + 3)
+        w = inputs.normal(u.shape, seed=inputs.FIELD_SEED_BASE + 3 + inputs.COTANGENT_OFFSET)
+        res = {}
+        for dtype, tdt in (("f64", torch.float64), ("f32", torch.float32)):
+            ut, wt = torch.from_numpy(u).to(dev, tdt), torch.from_numpy(w).to(dev, tdt)
+            g = torch.empty_like(ut)
+            for _ in range(3):
+                dgmf.vjp_convective(d, ut, wt, g)
+            torch.cuda.synchronize()
+            s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            reps = 20
+            s.record()
+            for _ in range(reps):
+                dgmf.vjp_convective(d, ut, wt, g)
+            e.record()
+            torch.cuda.synchronize()
+            t = s.elapsed_time(e) / 1e3 / reps
+            dofs = u.size
+            res[dtype] = {"dofs_per_s": dofs / t, "us": t * 1e6,
+                          "hbm_frac": BYTES_PER_DOF[("vjp", dtype)] * dofs / t / (HBM_PEAK_GBS * 1e9)}
+        out["vjp_k4_32cubed"] = res
+    except dgmf.DgError as ex:
+        out["vjp_k4_32cubed"] = {"error": str(ex)}
+    # pressure Poisson CG, k=7, 24^3, rhs = d_h(TGV + noise), zero mean
+    try:
+        k, N = 7, 24
+        d = dgmf.make_desc(k, N)
+        nodes = dgmf.lgl_nodes(k)
+        u = inputs.tgv_plus_noise(nodes, (N, N, N), (2 * np.pi,) * 3, seed=inputs.FIELD_SEED_BASE + 4)
+        b = dgmf.apply_divergence(d, torch.from_numpy(u).to(dev))
+        b -= b.mean()
+        res = {}
+        for name, pc in (("jacobi_f64", dgmf.DG_PC_JACOBI_F64), ("chebyshev5_f32", dgmf.DG_PC_CHEB_F32)):
+            x, rep, rc = dgmf.cg_solve(d, b, precond=pc, rtol=1e-10, max_iter=20000)
+            rep["rc"] = rc
+            res[name] = rep
+        res["speedup_solve"] = res["jacobi_f64"]["seconds_solve"] / res["chebyshev5_f32"]["seconds_solve"]
+        out["cg_k7_24cubed"] = res
+    except dgmf.DgError as ex:
+        out["cg_k7_24cubed"] = {"error": str(ex)}
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--kmin", type=int, default=2)
+    ap.add_argument("--kmax", type=int, default=11)
+    ap.add_argument("--ops", default="laplace,convective")
+    ap.add_argument("--only", default="", help="comma list of op:kK:dtype cases to run")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--sweep-out", default="")
+    args = ap.parse_args()
+    args.ops = [o for o in args.ops.split(",") if o]
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1802_01439_amd import dgmf, inputs
+    dgmf.lib()   # fail loudly if the HIP library is missing
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    print(f"[bench] building inputs for k={args.kmin}..{args.kmax} ops={args.ops}", file=sys.stderr, flush=True)
+    cases = build_cases(args, torch, dgmf, inputs, dev)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    for w in range(args.warmup):
+        for c in cases:
+            c.launch()
+    torch.cuda.synchronize()
+    print(f"[bench] {len(cases)} applies per step; warmup done", file=sys.stderr, flush=True)
+    evs = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in cases]
+           for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        for c, (a, b) in zip(cases, evs[s]):
+            a.record(stream)
+            c.launch()
+            b.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    for s in range(args.steps):
+        for c, (a, b) in zip(cases, evs[s]):
+            c.times.append(a.elapsed_time(b) / 1e3)
+    dofs_step = sum(c.dofs for c in cases)
+    ms_step = wall / args.steps * 1e3
+    sweep = []
+    for c in cases:
+        t = float(np.mean(c.times))
+        sweep.append({"op": c.op, "k": c.k, "N": c.N, "dtype": c.dtype, "dofs": c.dofs, "us": t * 1e6,
+                      "dofs_per_s": c.dofs / t, "gbs": c.bytes / t / 1e9,
+                      "hbm_frac": c.bytes / t / 1e9 / HBM_PEAK_GBS})
+    dom = max(cases, key=lambda c: np.mean(c.times))
+    tdom = float(np.mean(dom.times))
+    traffic = load_traffic(dom.op, dom.k, dom.dtype)
+    roofline = {"bound": "hbm", "achieved": dom.bytes / tdom / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": dom.bytes / tdom / 1e9 / HBM_PEAK_GBS, "traffic": traffic,
+                "kernel": f"{KERNEL_NAME[dom.op]} k={dom.k} {dom.dtype} N={dom.N}",
+                "algorithmic_bytes_per_launch": dom.bytes, "avg_launch_us": tdom * 1e6}
+    res = {"metric": METRIC, "value": dofs_step / (ms_step / 1e3), "unit": "DoFs/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32", "data": "synthetic",
+           "config": {"workload": (f"degree sweep k={args.kmin}..{args.kmax}: SIPG Laplace and LLF convective "
+                                   f"applies, FP64 and FP32, periodic cube N=round(256/(k+1)), ~1.7e7 "
+                                   f"DoFs per component, seeded U[-1,1]"),
+                      "ops": args.ops, "applies_per_step": len(cases), "dofs_per_step": dofs_step},
+           "roofline": roofline}
+    if args.sweep_out:
+        with open(args.sweep_out, "w") as f:
+            json.dump(sweep, f, indent=1)
+    res["sweep"] = [{k_: (round(v, 4) if isinstance(v, float) else v) for k_, v in r.items()} for r in sweep]
+    del cases
+    torch.cuda.empty_cache()
+    if not args.no_extras:
+        print("[bench] extras: VJP and CG", file=sys.stderr, flush=True)
+        res["extras"] = extras(torch, dgmf, inputs, dev, args)
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        res["cpu_baseline"] = cpu_baseline(args)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

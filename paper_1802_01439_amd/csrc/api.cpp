@@ -112,6 +112,59 @@ LaplacePlan make_laplace_plan(const dg_op_desc* d, int n_comp) {
   return P;
 }
 
+int default_conv_nq(int k) { return (3 * k) / 2 + 1; }
+
+int make_conv_plan(const dg_op_desc* d, ConvPlan& P) {
+  const int k = d->degree;
+  const int m = default_conv_nq(k);
+  if (d->n_q != 0 && d->n_q != m)
+    return fail(DG_ERR_UNSUPPORTED, "convective form is built for n_q = floor(3k/2)+1 = " + std::to_string(m));
+  const Basis1D& B = basis(k, m);
+  P.k = k;
+  P.m = m;
+  P.mesh = mesh_args(d);
+  P.S = B.S;
+  P.G = B.G;
+  P.w = B.wq;
+  double h[3], vol = 1.0;
+  for (int i = 0; i < 3; ++i) {
+    h[i] = d->length[i] / d->n_el[i];
+    vol *= h[i];
+  }
+  for (int i = 0; i < 3; ++i) {
+    P.cell[i] = -vol / h[i];
+    P.area[i] = vol / h[i];
+  }
+  P.lf = d->lf_factor;
+  return DG_OK;
+}
+
+DivPlan make_div_plan(const dg_op_desc* d) {
+  const int k = d->degree, n = k + 1;
+  const int m = d->n_q ? d->n_q : k + 1;
+  const Basis1D& B = basis(k, m);
+  DivPlan P;
+  P.k = k;
+  P.mesh = mesh_args(d);
+  P.Mref = B.Mref;
+  P.Bown.assign(n * n, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      double s = 0;
+      for (int q = 0; q < m; ++q) s += B.wq[q] * B.G[q * n + i] * B.S[q * n + j];
+      P.Bown[i * n + j] = -s;
+    }
+  P.Bown[(n - 1) * n + (n - 1)] += 0.5;
+  P.Bown[0] -= 0.5;
+  double h[3], vol = 1.0;
+  for (int i = 0; i < 3; ++i) {
+    h[i] = d->length[i] / d->n_el[i];
+    vol *= h[i];
+  }
+  for (int i = 0; i < 3; ++i) P.c[i] = vol / h[i];
+  return P;
+}
+
 }  // namespace dgmf
 
 using namespace dgmf;
@@ -185,26 +238,57 @@ int dg_apply_laplace(const dg_op_desc* desc, dg_dtype dtype, const void* src, vo
   return ok();
 }
 
-int dg_apply_convective(const dg_op_desc* desc, dg_dtype dtype, const void* u, void* r, void* s) {
-  (void)desc; (void)dtype; (void)u; (void)r; (void)s;
-  return fail(DG_ERR_UNSUPPORTED, "convective operator not available in this build");
+int dg_apply_convective(const dg_op_desc* desc, dg_dtype dtype, const void* u, void* r,
+                        void* hip_stream) {
+  int rc = validate_desc(desc);
+  if (rc) return rc;
+  if (dtype != DG_F64 && dtype != DG_F32) return fail(DG_ERR_INVALID_ARG, "dtype must be DG_F64 or DG_F32");
+  if (!u || !r) return fail(DG_ERR_INVALID_ARG, "u/r is NULL");
+  const size_t bytes = (size_t)3 * num_elements(desc) * dofs_per_element(desc) * (dtype == DG_F64 ? 8 : 4);
+  if (overlaps(u, bytes, r, bytes)) return fail(DG_ERR_ALIAS, "r overlaps u");
+  ConvPlan P;
+  rc = make_conv_plan(desc, P);
+  if (rc) return rc;
+  hipError_t e = launch_convective(P, dtype == DG_F32, u, r, (hipStream_t)hip_stream);
+  if (e != hipSuccess) return hip_fail(e, "convective kernel launch");
+  return ok();
 }
 
 int dg_vjp_convective(const dg_op_desc* desc, dg_dtype dtype, const void* u, const void* w,
-                      void* g, void* s) {
-  (void)desc; (void)dtype; (void)u; (void)w; (void)g; (void)s;
-  return fail(DG_ERR_UNSUPPORTED, "convective VJP not available in this build");
+                      void* grad_u, void* hip_stream) {
+  int rc = validate_desc(desc);
+  if (rc) return rc;
+  if (dtype != DG_F64 && dtype != DG_F32) return fail(DG_ERR_INVALID_ARG, "dtype must be DG_F64 or DG_F32");
+  if (!u || !w || !grad_u) return fail(DG_ERR_INVALID_ARG, "u/w/grad_u is NULL");
+  const int kmax = vjp_max_degree(dtype == DG_F32);
+  if (desc->degree > kmax)
+    return fail(DG_ERR_UNSUPPORTED, "convective VJP is built for degree <= " + std::to_string(kmax) +
+                                        (dtype == DG_F32 ? " in FP32" : " in FP64"));
+  const size_t bytes = (size_t)3 * num_elements(desc) * dofs_per_element(desc) * (dtype == DG_F64 ? 8 : 4);
+  if (overlaps(u, bytes, grad_u, bytes) || overlaps(w, bytes, grad_u, bytes))
+    return fail(DG_ERR_ALIAS, "grad_u overlaps u or w");
+  ConvPlan P;
+  rc = make_conv_plan(desc, P);
+  if (rc) return rc;
+  hipError_t e = launch_convective_vjp(P, dtype == DG_F32, u, w, grad_u, (hipStream_t)hip_stream);
+  if (e != hipSuccess) return hip_fail(e, "convective VJP kernel launch");
+  return ok();
 }
 
-int dg_apply_divergence(const dg_op_desc* desc, dg_dtype dtype, const void* u, void* b, void* s) {
-  (void)desc; (void)dtype; (void)u; (void)b; (void)s;
-  return fail(DG_ERR_UNSUPPORTED, "divergence operator not available in this build");
+int dg_apply_divergence(const dg_op_desc* desc, dg_dtype dtype, const void* u, void* b,
+                        void* hip_stream) {
+  int rc = validate_desc(desc);
+  if (rc) return rc;
+  if (dtype != DG_F64 && dtype != DG_F32) return fail(DG_ERR_INVALID_ARG, "dtype must be DG_F64 or DG_F32");
+  if (!u || !b) return fail(DG_ERR_INVALID_ARG, "u/b is NULL");
+  const size_t es = dtype == DG_F64 ? 8 : 4;
+  const size_t nb = (size_t)num_elements(desc) * dofs_per_element(desc) * es;
+  if (overlaps(u, 3 * nb, b, nb)) return fail(DG_ERR_ALIAS, "b overlaps u");
+  DivPlan P = make_div_plan(desc);
+  hipError_t e = launch_divergence(P, dtype == DG_F32, u, b, (hipStream_t)hip_stream);
+  if (e != hipSuccess) return hip_fail(e, "divergence kernel launch");
+  return ok();
 }
 
-int dg_cg_solve(const dg_op_desc* desc, const dg_cg_opts* opts, const double* b, double* x,
-                dg_cg_report* report, void* s) {
-  (void)desc; (void)opts; (void)b; (void)x; (void)report; (void)s;
-  return fail(DG_ERR_UNSUPPORTED, "CG solver not available in this build");
-}
 
 }  // extern "C"

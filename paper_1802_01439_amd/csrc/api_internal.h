@@ -22,5 +22,7 @@ long long dofs_per_element(const dg_op_desc* d);
 bool overlaps(const void* a, size_t na, const void* b, size_t nb);
 MeshArgs mesh_args(const dg_op_desc* d);
 LaplacePlan make_laplace_plan(const dg_op_desc* d, int n_comp);
+int default_conv_nq(int k);
+int make_conv_plan(const dg_op_desc* d, ConvPlan& P);
 
 }  // namespace dgmf

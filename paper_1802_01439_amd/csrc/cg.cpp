@@ -1,0 +1,332 @@
+// Preconditioned CG for the SIPG pressure Poisson problem (Sec. 3.3), host
+// driver.  Everything of size N_DoFs lives on the GPU: the FP64 operator
+// applies, residuals, dot products and the x, r, p updates; with the
+// Chebyshev preconditioner the smoother runs FP32 operator applies.  The host
+// only holds the few scalars of each iteration (two device-to-host reads per
+// iteration).
+//
+// Variant: flexible (Polak-Ribiere) CG, beta = r+.(z+ - z)/(r.z), so that a
+// single-precision preconditioner that is symmetric only up to rounding keeps
+// convergence.  On periodic meshes (project_mean) the residual and the
+// preconditioned residual are kept at zero coefficient mean, the subspace on
+// which the SIPG operator is invertible.
+//
+// Preconditioners: Jacobi (D^-1 in FP64), and the Chebyshev iteration of
+// Adams et al. (2003) on D^-1 A (Sec. 3.3: degree 5, smoothing range 20)
+// started from zero in FP32: theta = (lmax+lmin)/2, delta = (lmax-lmin)/2,
+// x1 = D^-1 r / theta, rho_0 = delta/theta, then for each further step
+// rho_k = 1/(2 theta/delta - rho_{k-1}),
+// d_k = rho_k rho_{k-1} d_{k-1} + (2 rho_k/delta) D^-1 (r - A x_k), x += d_k.
+// lmax is 1.1x the largest Ritz value of 25 Lanczos steps (plain Jacobi-PCG
+// on a hashed random zero-mean vector); lmin = lmax / range.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <map>
+#include <mutex>
+#include <vector>
+
+#include "api_internal.h"
+#include "cg_kernels.h"
+#include "dgmf.h"
+#include "ops.h"
+
+namespace dgmf {
+
+namespace {
+
+struct Workspace {
+  long long n = 0;
+  double *r = nullptr, *p = nullptr, *q = nullptr, *z = nullptr, *zold = nullptr, *tmp = nullptr;
+  float *r32 = nullptr, *x32 = nullptr, *d32 = nullptr, *t32 = nullptr;
+  double* partial = nullptr;   // 8 * kCgBlocks
+  double* res = nullptr;       // 8 results (device)
+  double* host = nullptr;      // 8 results (pinned host)
+  double* dinv = nullptr;      // n3
+  float* dinv32 = nullptr;     // n3
+};
+
+std::mutex g_ws_mutex;
+std::map<int, Workspace> g_ws;
+
+hipError_t ensure(Workspace& w, long long n) {
+  hipError_t e;
+  if (!w.partial && (e = hipMalloc((void**)&w.partial, 8 * kCgBlocks * sizeof(double))) != hipSuccess) return e;
+  if (!w.res && (e = hipMalloc((void**)&w.res, 8 * sizeof(double))) != hipSuccess) return e;
+  if (!w.host && (e = hipHostMalloc((void**)&w.host, 8 * sizeof(double), 0)) != hipSuccess) return e;
+  if (!w.dinv && (e = hipMalloc((void**)&w.dinv, 1728 * sizeof(double))) != hipSuccess) return e;
+  if (!w.dinv32 && (e = hipMalloc((void**)&w.dinv32, 1728 * sizeof(float))) != hipSuccess) return e;
+  if (w.n >= n) return hipSuccess;
+  double** d8[] = {&w.r, &w.p, &w.q, &w.z, &w.zold, &w.tmp};
+  float** d4[] = {&w.r32, &w.x32, &w.d32, &w.t32};
+  for (double** pp : d8) {
+    if (*pp) (void)hipFree(*pp);
+    *pp = nullptr;
+  }
+  for (float** pp : d4) {
+    if (*pp) (void)hipFree(*pp);
+    *pp = nullptr;
+  }
+  w.n = 0;
+  for (double** pp : d8)
+    if ((e = hipMalloc((void**)pp, (size_t)n * 8)) != hipSuccess) return e;
+  for (float** pp : d4)
+    if ((e = hipMalloc((void**)pp, (size_t)n * 4)) != hipSuccess) return e;
+  w.n = n;
+  return hipSuccess;
+}
+
+double now() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// largest eigenvalue of the symmetric tridiagonal (a diag, b off-diag) by bisection
+double tridiag_max_eig(const std::vector<double>& a, const std::vector<double>& b) {
+  const int m = (int)a.size();
+  double lo = 0, hi = 0;
+  for (int i = 0; i < m; ++i) {
+    double rad = (i > 0 ? std::fabs(b[i - 1]) : 0) + (i + 1 < m ? std::fabs(b[i]) : 0);
+    hi = std::fmax(hi, a[i] + rad);
+    lo = std::fmin(lo, a[i] - rad);
+  }
+  auto count_below = [&](double x) {   // eigenvalues < x (Sturm sequence)
+    int c = 0;
+    double d = 1.0;
+    for (int i = 0; i < m; ++i) {
+      d = a[i] - x - (i > 0 ? b[i - 1] * b[i - 1] / d : 0.0);
+      if (d == 0.0) d = -1e-300;
+      if (d < 0) ++c;
+    }
+    return c;
+  };
+  for (int it = 0; it < 200; ++it) {
+    double mid = 0.5 * (lo + hi);
+    if (count_below(mid) == m) hi = mid; else lo = mid;
+  }
+  return hi;
+}
+
+struct Solver {
+  const dg_op_desc* desc;
+  LaplacePlan P;
+  Workspace* w;
+  hipStream_t s;
+  long long n;
+  int n3;
+  bool project;
+  int matvec64 = 0, matvec32 = 0;
+  hipError_t err = hipSuccess;
+
+  bool ok(hipError_t e) {
+    if (e != hipSuccess && err == hipSuccess) err = e;
+    return e == hipSuccess;
+  }
+  // reduce nq partials and read them on the host
+  bool fetch(int nq) {
+    if (!ok(cg_finalize(w->partial, nq, w->res, s))) return false;
+    if (!ok(hipMemcpyAsync(w->host, w->res, nq * sizeof(double), hipMemcpyDeviceToHost, s))) return false;
+    return ok(hipStreamSynchronize(s));
+  }
+  bool apply64(const double* in, double* out) {
+    ++matvec64;
+    return ok(launch_laplace(P, false, in, out, s));
+  }
+  bool apply32(const float* in, float* out) {
+    ++matvec32;
+    return ok(launch_laplace(P, true, in, out, s));
+  }
+};
+
+}  // namespace
+
+}  // namespace dgmf
+
+using namespace dgmf;
+
+extern "C" int dg_cg_solve(const dg_op_desc* desc, const dg_cg_opts* opts, const double* b, double* x,
+                           dg_cg_report* report, void* hip_stream) {
+  const double t_start = now();
+  int rc = validate_desc(desc);
+  if (rc) return rc;
+  if (!opts) return fail(DG_ERR_INVALID_ARG, "opts is NULL");
+  if (!b || !x) return fail(DG_ERR_INVALID_ARG, "b/x is NULL");
+  if (desc->n_comp != 1) return fail(DG_ERR_INVALID_ARG, "dg_cg_solve needs n_comp = 1");
+  if (opts->precond != DG_PC_JACOBI_F64 && opts->precond != DG_PC_CHEB_F32)
+    return fail(DG_ERR_INVALID_ARG, "unknown preconditioner");
+  const bool cheb = opts->precond == DG_PC_CHEB_F32;
+  if (cheb && (opts->cheb_degree < 1 || opts->cheb_degree > 64 || !(opts->cheb_range > 1.0) ||
+               !std::isfinite(opts->cheb_range)))
+    return fail(DG_ERR_INVALID_ARG, "cheb_degree must be 1..64 and cheb_range finite > 1");
+  if (!(opts->rtol >= 0) || !(opts->atol >= 0) || !std::isfinite(opts->rtol) || !std::isfinite(opts->atol))
+    return fail(DG_ERR_INVALID_ARG, "rtol/atol must be finite and >= 0");
+  if (opts->max_iter < 1) return fail(DG_ERR_INVALID_ARG, "max_iter must be >= 1");
+  const long long n3 = dofs_per_element(desc);
+  const long long n = num_elements(desc) * n3;
+  if (overlaps(b, (size_t)n * 8, x, (size_t)n * 8)) return fail(DG_ERR_ALIAS, "x overlaps b");
+  if (report) *report = dg_cg_report{};
+
+  std::lock_guard<std::mutex> lock(g_ws_mutex);
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  Workspace& W = g_ws[dev];
+  if ((e = ensure(W, n)) != hipSuccess) return hip_fail(e, "CG workspace allocation");
+
+  Solver S;
+  S.desc = desc;
+  S.P = make_laplace_plan(desc, 1);
+  S.w = &W;
+  S.s = (hipStream_t)hip_stream;
+  S.n = n;
+  S.n3 = (int)n3;
+  S.project = opts->project_mean != 0;
+
+  // ---- setup: diagonal, eigenvalue estimate ----
+  std::vector<double> diag(n3), dinv(n3);
+  std::vector<float> dinv32(n3);
+  rc = dg_laplace_diagonal(desc, diag.data());
+  if (rc) return rc;
+  for (long long i = 0; i < n3; ++i) {
+    if (!(diag[i] > 0)) return fail(DG_ERR_BREAKDOWN, "operator diagonal is not positive");
+    dinv[i] = 1.0 / diag[i];
+    dinv32[i] = (float)dinv[i];
+  }
+  if (!S.ok(hipMemcpyAsync(W.dinv, dinv.data(), n3 * 8, hipMemcpyHostToDevice, S.s)) ||
+      !S.ok(hipMemcpyAsync(W.dinv32, dinv32.data(), n3 * 4, hipMemcpyHostToDevice, S.s)))
+    return hip_fail(S.err, "diagonal upload");
+  double* H = W.host;
+  const double dn = (double)n;
+  double lmax = 0, theta = 0, delta = 0;
+  if (cheb) {
+    // Lanczos coefficients of plain Jacobi-PCG on a random zero-mean vector
+    const int L = 25;
+    S.ok(cg_hash_fill(W.tmp, 12345ULL, n, W.partial, S.s));
+    if (!S.fetch(1)) return hip_fail(S.err, "Lanczos start");
+    const double mu0 = S.project ? H[0] / dn : 0.0;
+    S.ok(cg_axpb(W.r, W.tmp, 1.0, -mu0, n, S.s));
+    S.ok(cg_fill(W.zold, 0.0, n, S.s));
+    S.ok(cg_jacobi(W.r, W.z, W.zold, W.dinv, S.n3, 0.0, n, W.partial, S.s));
+    if (!S.fetch(4)) return hip_fail(S.err, "Lanczos start");
+    double muz = S.project ? H[0] / dn : 0.0, rz = H[1];
+    S.ok(cg_update_p(W.z, W.p, W.zold, muz, 0.0, n, S.s));
+    std::vector<double> al, be;
+    for (int it = 0; it < L; ++it) {
+      S.apply64(W.p, W.q);
+      S.ok(cg_dot(W.p, W.q, n, W.partial, S.s));
+      if (!S.fetch(1)) return hip_fail(S.err, "Lanczos");
+      const double pq = H[0];
+      if (!(pq > 0) || !(rz > 0)) break;
+      const double alpha = rz / pq;
+      S.ok(cg_update_xr(W.tmp, W.r, W.p, W.q, alpha, n, W.partial, S.s));
+      if (!S.fetch(1)) return hip_fail(S.err, "Lanczos");
+      const double mur = S.project ? H[0] / dn : 0.0;
+      S.ok(cg_jacobi(W.r, W.z, W.zold, W.dinv, S.n3, mur, n, W.partial, S.s));
+      if (!S.fetch(4)) return hip_fail(S.err, "Lanczos");
+      muz = S.project ? H[0] / dn : 0.0;
+      const double rz_new = H[1];
+      const double beta = rz_new / rz;
+      al.push_back(alpha);
+      be.push_back(beta);
+      S.ok(cg_update_p(W.z, W.p, W.zold, muz, beta, n, S.s));
+      rz = rz_new;
+      if (!(rz > 0)) break;
+    }
+    const int m = (int)al.size();
+    if (m == 0) return fail(DG_ERR_BREAKDOWN, "eigenvalue estimate failed (operator not positive definite?)");
+    std::vector<double> ta(m), tb(m > 1 ? m - 1 : 0);
+    for (int i = 0; i < m; ++i) {
+      ta[i] = 1.0 / al[i] + (i > 0 ? be[i - 1] / al[i - 1] : 0.0);
+      if (i + 1 < m) tb[i] = std::sqrt(be[i]) / al[i];
+    }
+    lmax = 1.1 * tridiag_max_eig(ta, tb);
+    const double lmin = lmax / opts->cheb_range;
+    theta = 0.5 * (lmax + lmin);
+    delta = 0.5 * (lmax - lmin);
+    S.matvec64 = 0;
+  }
+  if (!S.ok(hipStreamSynchronize(S.s))) return hip_fail(S.err, "setup");
+  const double t_setup = now();
+
+  // ---- preconditioner: z = M^-1 r (r projected in place), returns partials
+  // sum z, r.z, r.zold, r.r in H[0..3] ----
+  auto precondition = [&](double mu_r) -> bool {
+    if (!cheb) {
+      S.ok(cg_jacobi(W.r, W.z, W.zold, W.dinv, S.n3, mu_r, n, W.partial, S.s));
+      return S.fetch(4);
+    }
+    S.ok(cg_cheb_init(W.r, W.r32, W.x32, W.d32, W.dinv32, S.n3, mu_r, (float)(1.0 / theta), n, S.s));
+    double rho_prev = delta / theta;
+    for (int k = 1; k < opts->cheb_degree; ++k) {
+      const double rho = 1.0 / (2.0 * theta / delta - rho_prev);
+      S.apply32(W.x32, W.t32);
+      S.ok(cg_cheb_step(W.x32, W.d32, W.r32, W.t32, W.dinv32, S.n3, (float)(rho * rho_prev),
+                        (float)(2.0 * rho / delta), n, S.s));
+      rho_prev = rho;
+    }
+    S.ok(cg_cheb_final(W.r, W.z, W.zold, W.x32, n, W.partial, S.s));
+    return S.fetch(4);
+  };
+
+  // ---- CG ----
+  int status = DG_OK;
+  int it = 0;
+  double rel = 0, bnorm = 0;
+  S.apply64(x, W.q);
+  S.ok(cg_residual(b, W.q, W.r, n, W.partial, S.s));
+  if (!S.fetch(4)) return hip_fail(S.err, "initial residual");
+  const double sum_r = H[0], sum_b = H[2], sum_bb = H[3];
+  bnorm = std::sqrt(std::fmax(0.0, S.project ? sum_bb - sum_b * sum_b / dn : sum_bb));
+  const double tol = std::fmax(opts->rtol * bnorm, opts->atol);
+  S.ok(cg_fill(W.zold, 0.0, n, S.s));
+  if (!precondition(S.project ? sum_r / dn : 0.0)) return hip_fail(S.err, "preconditioner");
+  double muz = S.project ? H[0] / dn : 0.0;
+  double rz = H[1];
+  double rnorm = std::sqrt(H[3]);
+  S.ok(cg_update_p(W.z, W.p, W.zold, muz, 0.0, n, S.s));
+  rel = bnorm > 0 ? rnorm / bnorm : rnorm;
+  for (;;) {
+    if (!std::isfinite(rnorm) || !std::isfinite(rz)) { status = DG_ERR_BREAKDOWN; break; }
+    if (rnorm <= tol) break;
+    if (it >= opts->max_iter) { status = DG_NOT_CONVERGED; break; }
+    S.apply64(W.p, W.q);
+    S.ok(cg_dot(W.p, W.q, n, W.partial, S.s));
+    if (!S.fetch(1)) return hip_fail(S.err, "p.Ap");
+    const double pq = H[0];
+    if (!(pq > 0) || !std::isfinite(pq)) { status = DG_ERR_BREAKDOWN; break; }
+    const double alpha = rz / pq;
+    S.ok(cg_update_xr(x, W.r, W.p, W.q, alpha, n, W.partial, S.s));
+    if (!S.fetch(1)) return hip_fail(S.err, "update");
+    const double mur = S.project ? H[0] / dn : 0.0;
+    if (!precondition(mur)) return hip_fail(S.err, "preconditioner");
+    muz = S.project ? H[0] / dn : 0.0;
+    const double rz_new = H[1], rzold = H[2];
+    rnorm = std::sqrt(H[3]);
+    const double beta = (rz_new - rzold) / rz;
+    S.ok(cg_update_p(W.z, W.p, W.zold, muz, beta, n, S.s));
+    rz = rz_new;
+    ++it;
+    rel = bnorm > 0 ? rnorm / bnorm : rnorm;
+  }
+  if (!S.ok(hipStreamSynchronize(S.s))) return hip_fail(S.err, "solve");
+  const double t_solve = now();
+  // true residual in FP64
+  S.apply64(x, W.q);
+  S.ok(cg_residual(b, W.q, W.tmp, n, W.partial, S.s));
+  if (!S.fetch(4)) return hip_fail(S.err, "true residual");
+  const double tr2 = S.project ? H[1] - H[0] * H[0] / dn : H[1];
+  const double true_rel = std::sqrt(std::fmax(0.0, tr2)) / (bnorm > 0 ? bnorm : 1.0);
+  if (report) {
+    report->iterations = it;
+    report->matvec_f64 = S.matvec64;
+    report->matvec_f32 = S.matvec32;
+    report->rel_res = rel;
+    report->true_rel_res = true_rel;
+    report->lambda_max = lmax;
+    report->seconds_setup = t_setup - t_start;
+    report->seconds_solve = t_solve - t_setup;
+  }
+  if (status == DG_ERR_BREAKDOWN) return fail(status, "CG breakdown (p.Ap <= 0 or non-finite residual)");
+  if (status == DG_NOT_CONVERGED) return fail(status, "CG reached max_iter");
+  return ok();
+}

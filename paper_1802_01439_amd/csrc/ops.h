@@ -41,4 +41,17 @@ hipError_t launch_convective(const ConvPlan& P, bool f32, const void* u, void* r
 hipError_t launch_convective_vjp(const ConvPlan& P, bool f32, const void* u, const void* w,
                                  void* g, hipStream_t s);
 
+// Central-flux divergence: 1D mass and the 1D divergence operator on [0,1].
+struct DivPlan {
+  int k = 0;
+  MeshArgs mesh{};
+  std::vector<double> Mref;  // n x n
+  std::vector<double> Bown;  // n x n: -sum_q w l_i' l_j + own central-flux end terms
+  double c[3] = {0, 0, 0};   // vol/h_d
+};
+
+hipError_t launch_divergence(const DivPlan& P, bool f32, const void* u, void* b, hipStream_t s);
+
+int vjp_max_degree(bool f32);
+
 }  // namespace dgmf
