@@ -209,6 +209,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--sweep-out", default="")
+    ap.add_argument("--calib-copy", type=int, default=0,
+                    help="also run one plain device copy of this many bytes (counter calibration)")
     args = ap.parse_args()
     args.ops = [o for o in args.ops.split(",") if o]
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -225,6 +227,12 @@ def main():
     print(f"[bench] building inputs for k={args.kmin}..{args.kmax} ops={args.ops}", file=sys.stderr, flush=True)
     cases = build_cases(args, torch, dgmf, inputs, dev)
     torch.cuda.synchronize()
+    if args.calib_copy:
+        a = torch.ones(args.calib_copy // 8, dtype=torch.float64, device=dev)
+        c = torch.empty_like(a)
+        c.copy_(a)
+        torch.cuda.synchronize()
+        del a, c
     stream = torch.cuda.current_stream()
     for w in range(args.warmup):
         for c in cases:
