@@ -79,7 +79,8 @@ typedef struct {
  *                                   + tau phi_i (u- - u+) ) ]
  * with n the outward normal of the element that owns phi_i.
  *   src, dst: [n_comp][N_el][n^3] of `dtype` (double or float).
- * Degrees 1..11; any n_q in 1..32 (k+1 integrates exactly on these cells).
+ * Degrees 1..11; n_q in k+1..32 (k+1 already integrates exactly on these
+ * affine cells, Sec. 3.2; fewer points return DG_ERR_UNSUPPORTED).
  * The operator is symmetric, so it is also its own vector-Jacobian product.
  */
 int dg_apply_laplace(const dg_op_desc* desc, dg_dtype dtype, const void* src, void* dst,

@@ -20,7 +20,28 @@ namespace {
 thread_local std::string g_last_error;
 std::mutex g_basis_mutex;
 std::map<std::pair<int, int>, Basis1D> g_basis;
+std::mutex g_table_mutex;
+std::map<std::pair<int, std::string>, void*> g_tables;
 }  // namespace
+
+const void* device_table(const std::string& key, const void* host, size_t bytes, hipError_t* err) {
+  *err = hipSuccess;
+  int dev = 0;
+  if ((*err = hipGetDevice(&dev)) != hipSuccess) return nullptr;
+  std::string full = key + "/" + std::to_string(bytes);
+  std::lock_guard<std::mutex> lock(g_table_mutex);
+  auto k = std::make_pair(dev, full);
+  auto it = g_tables.find(k);
+  if (it != g_tables.end()) return it->second;
+  void* d = nullptr;
+  if ((*err = hipMalloc(&d, bytes)) != hipSuccess) return nullptr;
+  if ((*err = hipMemcpy(d, host, bytes, hipMemcpyHostToDevice)) != hipSuccess) {
+    (void)hipFree(d);
+    return nullptr;
+  }
+  g_tables[k] = d;
+  return d;
+}
 
 int fail(int code, const std::string& msg) {
   g_last_error = msg;
@@ -89,6 +110,36 @@ MeshArgs mesh_args(const dg_op_desc* d) {
   return m;
 }
 
+// X = A^-1 R for a small SPD matrix A (n x n, row major) and m right-hand
+// sides R (n x m, row major), by Cholesky factorisation.
+std::vector<double> solve_spd(const std::vector<double>& A, int n, const std::vector<double>& R, int m) {
+  std::vector<double> Lc(n * n, 0.0);
+  for (int j = 0; j < n; ++j) {
+    double s = A[j * n + j];
+    for (int k = 0; k < j; ++k) s -= Lc[j * n + k] * Lc[j * n + k];
+    Lc[j * n + j] = std::sqrt(s);
+    for (int i = j + 1; i < n; ++i) {
+      double t = A[i * n + j];
+      for (int k = 0; k < j; ++k) t -= Lc[i * n + k] * Lc[j * n + k];
+      Lc[i * n + j] = t / Lc[j * n + j];
+    }
+  }
+  std::vector<double> X(R);
+  for (int c = 0; c < m; ++c) {
+    for (int i = 0; i < n; ++i) {   // forward: Lc y = r
+      double t = X[i * m + c];
+      for (int k = 0; k < i; ++k) t -= Lc[i * n + k] * X[k * m + c];
+      X[i * m + c] = t / Lc[i * n + i];
+    }
+    for (int i = n - 1; i >= 0; --i) {   // backward: Lc^T x = y
+      double t = X[i * m + c];
+      for (int k = i + 1; k < n; ++k) t -= Lc[k * n + i] * X[k * m + c];
+      X[i * m + c] = t / Lc[i * n + i];
+    }
+  }
+  return X;
+}
+
 LaplacePlan make_laplace_plan(const dg_op_desc* d, int n_comp) {
   const int k = d->degree;
   const int m = d->n_q ? d->n_q : k + 1;
@@ -109,6 +160,32 @@ LaplacePlan make_laplace_plan(const dg_op_desc* d, int n_comp) {
   }
   for (int i = 0; i < 3; ++i) P.c[i] = d->scale * vol / (h[i] * h[i]);
   P.sigma = sigma;
+  // mass-factored form: L = M^-1 Kown and M^-1 times the coupling columns
+  // (right end value hd1 - sigma e_{n-1}, left end value -hd0 - sigma e_0,
+  // right half slope -e_{n-1}, left half slope e_0)
+  const int n = k + 1;
+  std::vector<double> rhs(n * (n + 4), 0.0);   // columns: Kown (n), cR, cL, gR, gL
+  for (int i = 0; i < n; ++i) {
+    for (int j = 0; j < n; ++j) rhs[i * (n + 4) + j] = S.Kown[i * n + j];
+    const double hd0 = 0.5 * B.D[i], hd1 = 0.5 * B.D[(n - 1) * n + i];
+    rhs[i * (n + 4) + n + 0] = hd1 - (i == n - 1 ? sigma : 0.0);
+    rhs[i * (n + 4) + n + 1] = -hd0 - (i == 0 ? sigma : 0.0);
+    rhs[i * (n + 4) + n + 2] = (i == n - 1) ? -1.0 : 0.0;
+    rhs[i * (n + 4) + n + 3] = (i == 0) ? 1.0 : 0.0;
+  }
+  std::vector<double> sol = solve_spd(B.Mref, n, rhs, n + 4);
+  P.Lown.assign(n * n, 0.0);
+  P.cR.assign(n, 0.0);
+  P.cL.assign(n, 0.0);
+  P.gR.assign(n, 0.0);
+  P.gL.assign(n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    for (int j = 0; j < n; ++j) P.Lown[i * n + j] = sol[i * (n + 4) + j];
+    P.cR[i] = sol[i * (n + 4) + n + 0];
+    P.cL[i] = sol[i * (n + 4) + n + 1];
+    P.gR[i] = sol[i * (n + 4) + n + 2];
+    P.gL[i] = sol[i * (n + 4) + n + 3];
+  }
   return P;
 }
 
@@ -197,6 +274,8 @@ int dg_laplace_diagonal(const dg_op_desc* desc, double* diag_host) {
   int rc = validate_desc(desc);
   if (rc) return rc;
   if (!diag_host) return fail(DG_ERR_INVALID_ARG, "diag_host is NULL");
+  if (desc->n_q != 0 && desc->n_q < desc->degree + 1)
+    return fail(DG_ERR_UNSUPPORTED, "the Laplace form needs n_q >= k+1 (exact Gauss integration)");
   const int k = desc->degree, n = k + 1;
   const int m = desc->n_q ? desc->n_q : k + 1;
   const Basis1D& B = basis(k, m);
@@ -229,6 +308,8 @@ int dg_apply_laplace(const dg_op_desc* desc, dg_dtype dtype, const void* src, vo
   if (dtype != DG_F64 && dtype != DG_F32) return fail(DG_ERR_INVALID_ARG, "dtype must be DG_F64 or DG_F32");
   if (desc->n_comp != 1 && desc->n_comp != 3) return fail(DG_ERR_INVALID_ARG, "n_comp must be 1 or 3");
   if (!src || !dst) return fail(DG_ERR_INVALID_ARG, "src/dst is NULL");
+  if (desc->n_q != 0 && desc->n_q < desc->degree + 1)
+    return fail(DG_ERR_UNSUPPORTED, "the Laplace form needs n_q >= k+1 (exact Gauss integration)");
   const size_t bytes = (size_t)desc->n_comp * num_elements(desc) * dofs_per_element(desc) *
                        (dtype == DG_F64 ? 8 : 4);
   if (overlaps(src, bytes, dst, bytes)) return fail(DG_ERR_ALIAS, "dst overlaps src");

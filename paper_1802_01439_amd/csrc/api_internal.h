@@ -26,3 +26,21 @@ int default_conv_nq(int k);
 int make_conv_plan(const dg_op_desc* d, ConvPlan& P);
 
 }  // namespace dgmf
+
+namespace dgmf {
+
+// Device copy of a small constant table (1D matrices of one operator
+// configuration), uploaded once per (key, device) and kept until exit.
+// Kernels read it with uniform addresses through the scalar cache.
+const void* device_table(const std::string& key, const void* host, size_t bytes, hipError_t* err);
+
+// Content-addressed variant: the key is the table's own FNV-1a hash.
+template <typename Tab>
+const Tab* device_table_of(const char* kind, const Tab& host, hipError_t* err) {
+  unsigned long long h = 1469598103934665603ULL;
+  const unsigned char* p = reinterpret_cast<const unsigned char*>(&host);
+  for (size_t i = 0; i < sizeof(Tab); ++i) h = (h ^ p[i]) * 1099511628211ULL;
+  return static_cast<const Tab*>(device_table(std::string(kind) + ":" + std::to_string(h), &host, sizeof(Tab), err));
+}
+
+}  // namespace dgmf

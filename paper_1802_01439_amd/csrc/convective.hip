@@ -20,6 +20,7 @@
 // is a loop of the workgroup's threads over the pencils of that phase, with
 // LDS buffers between phases (aliased by lifetime so that even k = 11 in FP64
 // fits one element in the 160 KB LDS).
+#include "api_internal.h"
 #include "common.h"
 #include "ops.h"
 
@@ -30,6 +31,10 @@ struct ConvTab {
   T S[Q][N];   // l_a(z_q)
   T G[Q][N];   // l_a'(z_q)
   T w[Q];      // Gauss weights on [0,1]
+};
+
+template <typename T>
+struct ConvScal {
   T cell[3];   // -vol/h_j
   T area[3];   // vol/h_d
   T lf;
@@ -58,7 +63,9 @@ __device__ __forceinline__ int face_node(int d, int dv, int t1, int t2) {
 
 template <int N, int Q, typename T>
 __global__ void __launch_bounds__((ConvCfg<N, Q, T>::THREADS))
-convective_kernel(const T* __restrict__ u, T* __restrict__ r, MeshArgs mesh, ConvTab<N, Q, T> t) {
+convective_kernel(const T* __restrict__ u, T* __restrict__ r, MeshArgs mesh,
+                  const ConvTab<N, Q, T>* __restrict__ tab, ConvScal<T> sc) {
+  const ConvTab<N, Q, T>& t = *tab;
   using C = ConvCfg<N, Q, T>;
   constexpr int N2 = C::N2, N3 = C::N3, E = C::E, TH = C::THREADS;
   __shared__ T RA[E * C::RA];
@@ -66,7 +73,7 @@ convective_kernel(const T* __restrict__ u, T* __restrict__ r, MeshArgs mesh, Con
   __shared__ T FRb[E * C::FR];
 
   const int tid = threadIdx.x;
-  const int e0 = blockIdx.x * E;
+  const int e0 = xcd_remap(blockIdx.x, gridDim.x) * E;
   const int ne = min(E, mesh.n_el - e0);
   const size_t cstride = (size_t)mesh.n_el * N3;   // component stride in global arrays
 
@@ -128,7 +135,7 @@ convective_kernel(const T* __restrict__ u, T* __restrict__ r, MeshArgs mesh, Con
 #pragma unroll
         for (int j = 0; j < N; ++j) acc[c][j] = 0;
       const T sgn = s ? T(1) : T(-1);
-      const T wq1 = t.w[q1] * t.area[d];
+      const T wq1 = t.w[q1] * sc.area[d];
 #pragma unroll
       for (int q2 = 0; q2 < Q; ++q2) {
         T um[3], up[3];
@@ -148,7 +155,7 @@ convective_kernel(const T* __restrict__ u, T* __restrict__ r, MeshArgs mesh, Con
         const T wgt = wq1 * t.w[q2];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          const T F = wgt * (T(0.5) * (um[c] * unm + up[c] * unp) + t.lf * lam * (um[c] - up[c]));
+          const T F = wgt * (T(0.5) * (um[c] * unm + up[c] * unp) + sc.lf * lam * (um[c] - up[c]));
 #pragma unroll
           for (int j = 0; j < N; ++j) acc[c][j] = fmadd(t.S[q2][j], F, acc[c][j]);
         }
@@ -266,9 +273,9 @@ convective_kernel(const T* __restrict__ u, T* __restrict__ r, MeshArgs mesh, Con
 #pragma unroll
         for (int q3 = 0; q3 < Q; ++q3) {
           const T uc = w12 * t.w[q3] * Uz[pp][c][q3];
-          const T fx = t.cell[0] * uc * Uz[pp][0][q3];
-          const T fy = t.cell[1] * uc * Uz[pp][1][q3];
-          const T fz = t.cell[2] * uc * Uz[pp][2][q3];
+          const T fx = sc.cell[0] * uc * Uz[pp][0][q3];
+          const T fy = sc.cell[1] * uc * Uz[pp][1][q3];
+          const T fz = sc.cell[2] * uc * Uz[pp][2][q3];
 #pragma unroll
           for (int cz = 0; cz < N; ++cz) {
             ox[cz] = fmadd(t.S[q3][cz], fx, ox[cz]);
@@ -359,14 +366,18 @@ static hipError_t launch_conv_nq(const ConvPlan& P, const void* u, void* r, hipS
     }
     t.w[q] = (T)P.w[q];
   }
+  ConvScal<T> sc;
   for (int d = 0; d < 3; ++d) {
-    t.cell[d] = (T)P.cell[d];
-    t.area[d] = (T)P.area[d];
+    sc.cell[d] = (T)P.cell[d];
+    sc.area[d] = (T)P.area[d];
   }
-  t.lf = (T)P.lf;
+  sc.lf = (T)P.lf;
+  hipError_t err;
+  const ConvTab<N, Q, T>* dt = device_table_of("convective", t, &err);
+  if (!dt) return err;
   const int grid = (P.mesh.n_el + C::E - 1) / C::E;
   hipLaunchKernelGGL((convective_kernel<N, Q, T>), dim3(grid), dim3(C::THREADS), 0, s,
-                     (const T*)u, (T*)r, P.mesh, t);
+                     (const T*)u, (T*)r, P.mesh, dt, sc);
   return hipGetLastError();
 }
 

@@ -19,6 +19,7 @@
 // Faces as in the forward operator: per direction, own/neighbour traces of u
 // and w are interpolated to the face Gauss points, combined pointwise and
 // integrated back onto the face nodes.
+#include "api_internal.h"
 #include "common.h"
 #include "ops.h"
 
@@ -29,6 +30,10 @@ struct VjpTab {
   T S[Q][N];
   T G[Q][N];
   T w[Q];
+};
+
+template <typename T>
+struct VjpScal {
   T cell[3];   // -vol/h_j
   T area[3];   // vol/h_d
   T lf;
@@ -59,7 +64,8 @@ __device__ __forceinline__ int vface_node(int d, int dv, int t1, int t2) {
 template <int N, int Q, typename T>
 __global__ void __launch_bounds__(256)
 convective_vjp_kernel(const T* __restrict__ u, const T* __restrict__ wv, T* __restrict__ g,
-                      MeshArgs mesh, VjpTab<N, Q, T> t) {
+                      MeshArgs mesh, const VjpTab<N, Q, T>* __restrict__ tab, VjpScal<T> sc) {
+  const VjpTab<N, Q, T>& t = *tab;
   using C = VjpCfg<N, Q, T>;
   constexpr int N2 = C::N2, N3 = C::N3, E = C::E, TH = C::THREADS;
   __shared__ T RA[E * C::RA];
@@ -67,7 +73,7 @@ convective_vjp_kernel(const T* __restrict__ u, const T* __restrict__ wv, T* __re
   __shared__ T FRb[E * C::FR];
 
   const int tid = threadIdx.x;
-  const int e0 = blockIdx.x * E;
+  const int e0 = xcd_remap(blockIdx.x, gridDim.x) * E;
   const int ne = min(E, mesh.n_el - e0);
   const size_t cs = (size_t)mesh.n_el * N3;
 
@@ -123,7 +129,7 @@ convective_vjp_kernel(const T* __restrict__ u, const T* __restrict__ wv, T* __re
 #pragma unroll
         for (int j = 0; j < N; ++j) acc[k][j] = 0;
       const T sgn = s ? T(1) : T(-1);
-      const T wq1 = t.w[q1] * t.area[d];
+      const T wq1 = t.w[q1] * sc.area[d];
 #pragma unroll 1
       for (int q2 = 0; q2 < Q; ++q2) {
         T v[12];
@@ -148,8 +154,8 @@ convective_vjp_kernel(const T* __restrict__ u, const T* __restrict__ wv, T* __re
           sdj = fmadd(dw[i], v[i] - v[3 + i], sdj);
         }
         const T wgt = wq1 * t.w[q2];
-        const T diag = T(0.5) * unm + t.lf * lam;
-        const T extra = sgn * (T(0.5) * sdu + t.lf * sm * sg * sdj);
+        const T diag = T(0.5) * unm + sc.lf * lam;
+        const T extra = sgn * (T(0.5) * sdu + sc.lf * sm * sg * sdj);
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
           const T Gk = wgt * (dw[k] * diag + (k == d ? extra : T(0)));
@@ -270,7 +276,7 @@ convective_vjp_kernel(const T* __restrict__ u, const T* __restrict__ wv, T* __re
         dz[c] = a3;
       }
       const T wq = w12 * t.w[q3];
-      const T cu[3] = {t.cell[0] * uu[0], t.cell[1] * uu[1], t.cell[2] * uu[2]};
+      const T cu[3] = {sc.cell[0] * uu[0], sc.cell[1] * uu[1], sc.cell[2] * uu[2]};
       // sum_c u_c d_k w_c for k = x, y, z
       const T ux = uu[0] * dx[0] + uu[1] * dx[1] + uu[2] * dx[2];
       const T uy = uu[0] * dy[0] + uu[1] * dy[1] + uu[2] * dy[2];
@@ -278,9 +284,9 @@ convective_vjp_kernel(const T* __restrict__ u, const T* __restrict__ wv, T* __re
       T P[3];
 #pragma unroll
       for (int k = 0; k < 3; ++k) P[k] = cu[0] * dx[k] + cu[1] * dy[k] + cu[2] * dz[k];
-      P[0] += t.cell[0] * ux;
-      P[1] += t.cell[1] * uy;
-      P[2] += t.cell[2] * uz;
+      P[0] += sc.cell[0] * ux;
+      P[1] += sc.cell[1] * uy;
+      P[2] += sc.cell[2] * uz;
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
         const T pk = wq * P[k];
@@ -368,14 +374,18 @@ static hipError_t launch_vjp_nq(const ConvPlan& P, const void* u, const void* w,
       }
       t.w[q] = (T)P.w[q];
     }
+    VjpScal<T> sc;
     for (int d = 0; d < 3; ++d) {
-      t.cell[d] = (T)P.cell[d];
-      t.area[d] = (T)P.area[d];
+      sc.cell[d] = (T)P.cell[d];
+      sc.area[d] = (T)P.area[d];
     }
-    t.lf = (T)P.lf;
+    sc.lf = (T)P.lf;
+    hipError_t err;
+    const VjpTab<N, Q, T>* dt = device_table_of("convective_vjp", t, &err);
+    if (!dt) return err;
     const int grid = (P.mesh.n_el + C::E - 1) / C::E;
     hipLaunchKernelGGL((convective_vjp_kernel<N, Q, T>), dim3(grid), dim3(C::THREADS), 0, s,
-                       (const T*)u, (const T*)w, (T*)g, P.mesh, t);
+                       (const T*)u, (const T*)w, (T*)g, P.mesh, dt, sc);
     return hipGetLastError();
   }
 }

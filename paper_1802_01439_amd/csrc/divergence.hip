@@ -12,6 +12,7 @@
 // the neighbour coupling 1/2 uR(0) at the right end, -1/2 uL(1) at the left.
 // Same GPU mapping as the Laplace kernel: E elements per workgroup, one pencil
 // per thread per phase, LDS between phases.
+#include "api_internal.h"
 #include "common.h"
 #include "ops.h"
 
@@ -21,7 +22,11 @@ template <int N, typename T>
 struct DivTab {
   T M[N][N];
   T B[N][N];
-  T c[3];
+};
+
+template <typename T>
+struct DivScal {
+  T c[3];   // vol/h_d
 };
 
 template <int N>
@@ -44,7 +49,9 @@ __device__ __forceinline__ void dmv(const T (&A)[N][N], const T* x, T* y) {
 
 template <int N, typename T>
 __global__ void __launch_bounds__(DivCfg<N>::THREADS)
-divergence_kernel(const T* __restrict__ u, T* __restrict__ b, MeshArgs mesh, DivTab<N, T> t) {
+divergence_kernel(const T* __restrict__ u, T* __restrict__ b, MeshArgs mesh,
+                  const DivTab<N, T>* __restrict__ tab, DivScal<T> sc) {
+  const DivTab<N, T>& t = *tab;
   using C = DivCfg<N>;
   constexpr int N2 = C::N2, N3 = C::N3, E = C::E;
   __shared__ T U[3][E * N3];
@@ -52,7 +59,7 @@ divergence_kernel(const T* __restrict__ u, T* __restrict__ b, MeshArgs mesh, Div
   __shared__ T B2[E * N3];
   __shared__ T B3[E * N3];
   const int tid = threadIdx.x;
-  const int e0 = blockIdx.x * E;
+  const int e0 = xcd_remap(blockIdx.x, gridDim.x) * E;
   const int ne = min(E, mesh.n_el - e0);
   const size_t cs = (size_t)mesh.n_el * N3;
   for (int d = 0; d < 3; ++d) {
@@ -115,16 +122,16 @@ divergence_kernel(const T* __restrict__ u, T* __restrict__ b, MeshArgs mesh, Div
 #pragma unroll
     for (int a = 0; a < N; ++a) tmp[a] = B2[off + base + a];
 #pragma unroll
-    for (int a = 0; a < N; ++a) B2[off + base + a] = t.c[0] * out[a];
+    for (int a = 0; a < N; ++a) B2[off + base + a] = sc.c[0] * out[a];
     dmv<N, T>(t.M, tmp, out);
 #pragma unroll
     for (int a = 0; a < N; ++a) {
-      B3[off + base + a] = t.c[1] * out[a];
+      B3[off + base + a] = sc.c[1] * out[a];
       tmp[a] = B1[off + base + a];
     }
     dmv<N, T>(t.M, tmp, out);
 #pragma unroll
-    for (int a = 0; a < N; ++a) B1[off + base + a] = t.c[2] * out[a];
+    for (int a = 0; a < N; ++a) B1[off + base + a] = sc.c[2] * out[a];
   }
   __syncthreads();
   // Y again: S = My (c_x P) + c_y Q
@@ -158,10 +165,14 @@ static hipError_t launch_div_n(const DivPlan& P, const void* u, void* b, hipStre
       t.M[i][j] = (T)P.Mref[i * N + j];
       t.B[i][j] = (T)P.Bown[i * N + j];
     }
-  for (int d = 0; d < 3; ++d) t.c[d] = (T)P.c[d];
+  DivScal<T> sc;
+  for (int d = 0; d < 3; ++d) sc.c[d] = (T)P.c[d];
+  hipError_t err;
+  const DivTab<N, T>* dt = device_table_of("divergence", t, &err);
+  if (!dt) return err;
   const int grid = (P.mesh.n_el + C::E - 1) / C::E;
   hipLaunchKernelGGL((divergence_kernel<N, T>), dim3(grid), dim3(C::THREADS), 0, s, (const T*)u, (T*)b,
-                     P.mesh, t);
+                     P.mesh, dt, sc);
   return hipGetLastError();
 }
 

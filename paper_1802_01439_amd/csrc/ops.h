@@ -17,6 +17,8 @@ struct LaplacePlan {
   std::vector<double> Mref;  // n x n 1D mass on [0,1]
   std::vector<double> Kown;  // n x n 1D SIPG own-element part on [0,1]
   std::vector<double> D;     // n x n l_j'(xi_i) at the LGL nodes
+  std::vector<double> Lown;  // n x n  M^-1 Kown
+  std::vector<double> cR, cL, gR, gL;  // M^-1 times the neighbour coupling columns
   double c[3] = {0, 0, 0};   // scale * vol / h_d^2
   double sigma = 0;          // penalty_factor * (k+1)^2
 };

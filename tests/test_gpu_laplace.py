@@ -92,9 +92,12 @@ def test_three_components_penalty_scale_nq():
     y = _run(k, n_el, length, u, penalty_factor=2.5, scale=1 / 1600, n_q=9)
     ref = laplace_apply(u, k, msh, n_q=9, penalty_factor=2.5, scale=1 / 1600)
     assert rel_err(y, ref) < 1e-12
-    announce("laplace under-integrated n_q=4 for k=5")
-    y = _run(k, n_el, length, u[0], n_q=4)
-    assert rel_err(y, laplace_apply(u[0], k, msh, n_q=4)) < 1e-12
+    announce("laplace over-integrated n_q=12 for k=5")
+    y = _run(k, n_el, length, u[0], n_q=12)
+    assert rel_err(y, laplace_apply(u[0], k, msh, n_q=12)) < 1e-12
+    with pytest.raises(dgmf.DgError) as ei:
+        _run(k, n_el, length, u[0], n_q=4)
+    assert ei.value.code == dgmf.DG_ERR_UNSUPPORTED
 
 
 def test_invariants_on_gpu_output():
