@@ -5,21 +5,43 @@
 //   R_c = -sum_j s_j (d_j phi, u_c u_j)_K + sum_faces (phi, F*_c),   s_j = vol/h_j
 //   F*_c = 1/2 (u-_c u-.n + u+_c u+.n) + lf * max(|u-.n|, |u+.n|) (u-_c - u+_c)
 //
-// Sum factorisation with S (m x n, LGL -> Gauss interpolation) and G (m x n,
-// derivatives of the LGL basis at the Gauss points):
-//   cell:  u -> Sx -> Sy -> [Sz, flux W u_c u_j, S^T_z / G^T_z fused per
-//          z-pencil in registers] -> y back-sweep -> x back-sweep
-//          R_c = G^T_x S^T_y S^T_z F_cx + S^T_x G^T_y S^T_z F_cy + S^T_x S^T_y G^T_z F_cz
-//   faces: per direction, own (from LDS) and neighbour (from global) face
-//          layers are interpolated to the m x m face Gauss points (t1 then t2),
-//          the flux is formed pointwise and integrated back (t2 then t1) onto
-//          the n x n face nodes; the LGL basis makes the face layer the only
-//          non-zero trace.  Each element does its own six faces (no atomics).
+// 1D tables: S (m x n, LGL -> Gauss interpolation), G (m x n, derivatives of
+// the LGL basis at the Gauss points), Gauss weights w.
 //
-// GPU mapping: one workgroup per batch of E consecutive elements; every phase
-// is a loop of the workgroup's threads over the pencils of that phase, with
-// LDS buffers between phases (aliased by lifetime so that even k = 11 in FP64
-// fits one element in the 160 KB LDS).
+// Cell term: u -> S_x -> S_y -> S_z gives u at the m^3 points; the flux
+// F_cj = s_j W u_c u_j is contracted back as
+//   R_c = G^T_x S^T_y (S^T_z F_cx) + S^T_x [G^T_y (S^T_z F_cy) + S^T_y (G^T_z F_cz)].
+//
+// Face terms ride along with the cell sweeps.  With LGL nodes the trace of u on
+// a face is the face layer of nodes, and its test functions are the face layer:
+//   z faces: the neighbours' facing layers are carried as two extra z layers
+//            through the x and y sweeps, so after them both traces sit at the
+//            face points (q1,q2) of the z pencil that a thread owns; the face
+//            flux is added to the G^T_z F_cz pencil at its end nodes, where the
+//            following S^T_y, S^T_x sweeps integrate it over the face.
+//   y faces: own and neighbour layers are swept in x (own ones come out of the
+//            cell x sweep), then one thread per (side, q1) interpolates them in
+//            z, forms the flux at the m face points and integrates it back in
+//            z; the result joins the y back sweep at the end nodes.
+//   x faces: own and neighbour layers are swept in y, then in z per (side, q2)
+//            as for y; the result is integrated in y and added at the end
+//            nodes after the x back sweep.
+// Each element does its own six faces (each face flux is formed twice, no
+// atomics, every output written once).
+//
+// GPU mapping: one workgroup per batch of E consecutive elements.  Phases
+// (barriers between them):
+//   P1  x sweep of the cell (3n^2 pencils per element) and of the y/z
+//       neighbour layers, y sweep of the x-face layers; all inputs straight
+//       from global memory into registers.
+//   P2  y sweep, in place in LDS, of the cell and the two extra z layers.
+//   P3  per (q1,q2): z sweep into registers, z-face flux, cell flux and the
+//       z back sweep; per (side, q): y- and x-face flux pencils.
+//   Y   y back sweep (in place) and the y integral of the x-face terms.
+//   X   x back sweep, face end-node terms, write-out.
+// Small degrees keep the back sweeps of all three components in LDS at once
+// (5 phases); large ones run the Z/Y/X back sweeps per component from the z
+// pencils held in registers (11 phases, a third of the LDS).
 #include "api_internal.h"
 #include "common.h"
 #include "ops.h"
@@ -40,324 +62,441 @@ struct ConvScal {
   T lf;
 };
 
-template <int N, int Q, typename T>
-struct ConvCfg {
+// LDS layout of one element (units of T).
+//  Column block: a (q1, q2) grid with q1 pitch MP (odd, against bank
+//  conflicts); "slots" are stacked column blocks.
+//   forward:  slot j*(n+2) + c+1 holds component j at z layer c in -1..n
+//             (-1 and n: the z neighbours' facing layers), first as (q1, b)
+//             after the x sweep, then as (q1, q2) after the in-place y sweep.
+//   backward: slot (jj*3 + f)*n + cz holds S^T_z F_jx, S^T_z F_jy, G^T_z F_jz
+//             (f = 0, 1, 2) at (q1, q2); the y back sweep overwrites f = 0, 1
+//             in place with (q1, b).  A thread only overwrites the column it
+//             has itself read, so no barrier separates those steps.
+//  Face layers FY (y faces) and FX (x faces): [sigma][s][j][c][q] with sigma
+//  0 = own, 1 = neighbour, s the side, c the z node, q = q1 (FY) or q2 (FX);
+//  the face-flux pencils overwrite their own sigma = 0 entries with the z back
+//  sweep result (cz in place of c).
+//  XR: the x-face terms after the y integral, [jj][s][cz][b].
+template <int N, int Q, int SZ>
+struct ConvShape {
   static constexpr int N2 = N * N, N3 = N * N * N;
-  static constexpr int RA = (3 * Q * Q * N > 3 * N3 + 18 * Q * N) ? 3 * Q * Q * N : 3 * N3 + 18 * Q * N;
-  static constexpr int RB = 3 * Q * N2;
-  static constexpr int FR = 18 * N2;
-  static constexpr int PER_ELEM = RA + RB + FR;
-  static constexpr int BUDGET = 64 * 1024 / (int)sizeof(T);
-  static constexpr int LDS_MAX = 160 * 1024 / (int)sizeof(T);
-  static constexpr int E = (PER_ELEM <= BUDGET) ? (BUDGET / PER_ELEM) : 1;
-  static constexpr int THREADS = (Q * Q * E > 256) ? 512 : 256;
-  static constexpr int PPT = (E * Q * Q + THREADS - 1) / THREADS;   // z-pencils per thread
-  static_assert(E * PER_ELEM <= LDS_MAX, "convective LDS footprint exceeds 160 KB");
+  static constexpr int MP = Q | 1;
+  static constexpr int COLS = MP * Q;
+  static constexpr int LAYER = N * Q;
+  static constexpr int FL = 12 * LAYER;
+  static constexpr int slots(bool allc) { return allc ? (9 * N > 3 * (N + 2) ? 9 * N : 3 * (N + 2)) : 3 * (N + 2); }
+  static constexpr int per(bool allc) { return slots(allc) * COLS + 2 * FL + (allc ? 3 : 1) * 2 * N2; }
+  // all components' back sweeps at once while an element needs <= 24 KB
+  static constexpr bool ALLC = per(true) * SZ <= 24 * 1024;
+  static constexpr int PER = per(ALLC);
+  static constexpr int BYTES = PER * SZ;
+  // about 52 KB per workgroup (three per CU), 1..16 elements
+  static constexpr int E0 = (52 * 1024) / BYTES;
+  static constexpr int E = E0 < 1 ? 1 : (E0 > 16 ? 16 : E0);
+  // per-component mode keeps one z pencil per thread in registers
+  static constexpr int TH = (E * Q * Q > 256) ? ((E * Q * Q + 63) / 64) * 64 : 256;
+  static_assert(E * PER * SZ <= 160 * 1024, "convective LDS footprint exceeds 160 KB");
 };
 
-// node index of (value along d, t1, t2) for face direction d
-template <int N>
-__device__ __forceinline__ int face_node(int d, int dv, int t1, int t2) {
-  return d == 0 ? dv + N * (t1 + N * t2) : (d == 1 ? t1 + N * (dv + N * t2) : t1 + N * (t2 + N * dv));
+template <int N, int Q, typename T>
+__device__ __forceinline__ void load_pencil(const T* __restrict__ p, int stride, T (&in)[N]) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) in[i] = p[i * stride];
 }
 
-template <int N, int Q, typename T>
-__global__ void __launch_bounds__((ConvCfg<N, Q, T>::THREADS))
+// dst[q*stride] = sum_a S[q][a] in[a]   (and the same into dst2 if given)
+template <int N, int Q, typename T, typename Tab>
+__device__ __forceinline__ void interp_store(const Tab& t, const T (&in)[N], T* dst, int stride, T* dst2) {
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    T acc = t.S[q][0] * in[0];
+#pragma unroll
+    for (int a = 1; a < N; ++a) acc = fmadd(t.S[q][a], in[a], acc);
+    dst[q * stride] = acc;
+    if (dst2) dst2[q] = acc;
+  }
+}
+
+// LLF flux of component values um/up (own/neighbour) with normal velocities
+// unm/unp (already signed by the outward normal), scaled by wgt.
+template <typename T>
+__device__ __forceinline__ T llf(T um, T up, T unm, T unp, T lam, T lf, T wgt) {
+  return wgt * (T(0.5) * (um * unm + up * unp) + lf * lam * (um - up));
+}
+
+// The table pointer passed through an empty asm and returned in the constant
+// address space: table loads issued after it are scalar loads that cannot be
+// merged with loads of the same entries elsewhere in the kernel, so each phase
+// loads the rows it uses when it uses them instead of keeping the whole table
+// live in scalar registers.
+template <typename P>
+using const_ptr = const __attribute__((address_space(4))) P*;
+
+template <typename P>
+__device__ __forceinline__ const_ptr<P> fresh(const P* p) {
+  uint64_t x = (uint64_t)p;
+  asm volatile("" : "+v"(x));
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(x >> 32));
+  return (const_ptr<P>)(((uint64_t)hi << 32) | lo);
+}
+
+template <int N, int Q, typename T, int E, int TH, bool ALLC>
+__global__ void __launch_bounds__(TH)
 convective_kernel(const T* __restrict__ u, T* __restrict__ r, MeshArgs mesh,
                   const ConvTab<N, Q, T>* __restrict__ tab, ConvScal<T> sc) {
-  const ConvTab<N, Q, T>& t = *tab;
-  using C = ConvCfg<N, Q, T>;
-  constexpr int N2 = C::N2, N3 = C::N3, E = C::E, TH = C::THREADS;
-  __shared__ T RA[E * C::RA];
-  __shared__ T RB[E * C::RB];
-  __shared__ T FRb[E * C::FR];
-
+  using Sh = ConvShape<N, Q, (int)sizeof(T)>;
+  constexpr int N2 = Sh::N2, N3 = Sh::N3, MP = Sh::MP, COLS = Sh::COLS, LAYER = Sh::LAYER;
+  constexpr int PER = Sh::per(ALLC);
+  constexpr int FYo = Sh::slots(ALLC) * COLS;
+  constexpr int FXo = FYo + Sh::FL;
+  constexpr int XRo = FXo + Sh::FL;
+  __shared__ T lds[E * PER];
   const int tid = threadIdx.x;
   const int e0 = xcd_remap(blockIdx.x, gridDim.x) * E;
   const int ne = min(E, mesh.n_el - e0);
-  const size_t cstride = (size_t)mesh.n_el * N3;   // component stride in global arrays
+  const size_t cs = (size_t)mesh.n_el * N3;
 
-  // stage the batch: A[le][c][node] at RA + le*RA
-  for (int i = tid; i < ne * 3 * N3; i += TH) {
-    const int le = i / (3 * N3), rem = i - le * 3 * N3, c = rem / N3, node = rem - c * N3;
-    RA[le * C::RA + c * N3 + node] = u[c * cstride + (size_t)(e0 + le) * N3 + node];
-  }
-  __syncthreads();
-
-  // ---------------- faces, one direction at a time ----------------
-  for (int d = 0; d < 3; ++d) {
-    // F1: interpolate face layers along t1 (own from LDS, neighbour from global)
-    for (int w = tid; w < ne * 12 * N; w += TH) {
-      const int le = w / (12 * N);
-      int rem = w - le * 12 * N;
-      const int j = rem % N; rem /= N;
-      const int side = rem % 2; rem /= 2;
-      const int c = rem % 3;
-      const int s = rem / 3;
-      const int e = e0 + le;
-      T in[N];
-      if (side == 0) {
-        const T* A = RA + le * C::RA + c * N3;
-#pragma unroll
-        for (int i = 0; i < N; ++i) in[i] = A[face_node<N>(d, s ? N - 1 : 0, i, j)];
+  // ---------------- P1: x sweeps (and y sweeps of x-face layers) from global ----------------
+  {
+    const int nM = 3 * ne * N2, nY = ne * 6 * N, nZ = ne * 6 * N, nX = ne * 12 * N;
+    for (int w = tid; w < nM + nY + nZ + nX; w += TH) {
+      const auto& t = *fresh(tab);
+      const T* src;
+      int sstride = 1;
+      T* dst;
+      T* dst2 = nullptr;
+      if (w < nM) {   // cell pencil (b, c) of component j
+        const int j = w / (ne * N2), rem = w - j * ne * N2, le = rem / N2, bc = rem - le * N2;
+        const int b = bc % N, c = bc / N;
+        src = u + j * cs + (size_t)(e0 + le) * N3 + N * bc;
+        T* L = lds + le * PER;
+        dst = L + (j * (N + 2) + c + 1) * COLS + MP * b;
+        if (b == 0) dst2 = L + FYo + ((0 * 2 + 0) * 3 + j) * LAYER + c * Q;
+        else if (b == N - 1) dst2 = L + FYo + ((0 * 2 + 1) * 3 + j) * LAYER + c * Q;
       } else {
-        const int ex = e % mesh.nx, ey = (e / mesh.nx) % mesh.ny, ez = e / (mesh.nx * mesh.ny);
-        const T* g = u + c * cstride + (size_t)neighbor(mesh, ex, ey, ez, d, s) * N3;
-#pragma unroll
-        for (int i = 0; i < N; ++i) in[i] = g[face_node<N>(d, s ? 0 : N - 1, i, j)];
-      }
-      T* FA = RA + le * C::RA + 3 * N3 + (((s * 3 + c) * 2 + side) * N + j) * Q;
-#pragma unroll
-      for (int q = 0; q < Q; ++q) {
-        T acc = t.S[q][0] * in[0];
-#pragma unroll
-        for (int i = 1; i < N; ++i) acc = fmadd(t.S[q][i], in[i], acc);
-        FA[q] = acc;
-      }
-    }
-    __syncthreads();
-    // F2: per face column q1: interpolate along t2, flux, integrate along t2
-    for (int w = tid; w < ne * 2 * Q; w += TH) {
-      const int le = w / (2 * Q);
-      const int rem = w - le * 2 * Q;
-      const int s = rem / Q, q1 = rem - (rem / Q) * Q;
-      const T* FA = RA + le * C::RA + 3 * N3;
-      T tr[3][2][N];
-#pragma unroll
-      for (int c = 0; c < 3; ++c)
-#pragma unroll
-        for (int side = 0; side < 2; ++side)
-#pragma unroll
-          for (int j = 0; j < N; ++j) tr[c][side][j] = FA[(((s * 3 + c) * 2 + side) * N + j) * Q + q1];
-      T acc[3][N];
-#pragma unroll
-      for (int c = 0; c < 3; ++c)
-#pragma unroll
-        for (int j = 0; j < N; ++j) acc[c][j] = 0;
-      const T sgn = s ? T(1) : T(-1);
-      const T wq1 = t.w[q1] * sc.area[d];
-#pragma unroll
-      for (int q2 = 0; q2 < Q; ++q2) {
-        T um[3], up[3];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          T a = t.S[q2][0] * tr[c][0][0], b = t.S[q2][0] * tr[c][1][0];
-#pragma unroll
-          for (int j = 1; j < N; ++j) {
-            a = fmadd(t.S[q2][j], tr[c][0][j], a);
-            b = fmadd(t.S[q2][j], tr[c][1][j], b);
+        int v = w - nM;
+        if (v < nY + nZ) {   // y or z neighbour layer pencil, swept in x
+          const bool isz = v >= nY;
+          if (isz) v -= nY;
+          const int j = v / (ne * 2 * N);
+          int rem = v - j * ne * 2 * N;
+          const int le = rem / (2 * N);
+          rem -= le * 2 * N;
+          const int s = rem / N, p = rem - s * N;
+          const int e = e0 + le;
+          const int ex = e % mesh.nx, ey = (e / mesh.nx) % mesh.ny, ez = e / (mesh.nx * mesh.ny);
+          const int nb = neighbor(mesh, ex, ey, ez, isz ? 2 : 1, s);
+          const int lay = s ? 0 : N - 1;   // neighbour's facing layer
+          T* L = lds + le * PER;
+          if (isz) {   // pencil b = p of z layer lay -> extra z slot
+            src = u + j * cs + (size_t)nb * N3 + N * (p + N * lay);
+            dst = L + (j * (N + 2) + (s ? N + 1 : 0)) * COLS + MP * p;
+          } else {     // pencil c = p of y layer lay -> FY neighbour entry
+            src = u + j * cs + (size_t)nb * N3 + N * (lay + N * p);
+            dst = L + FYo + ((1 * 2 + s) * 3 + j) * LAYER + p * Q;
           }
-          um[c] = a;
-          up[c] = b;
-        }
-        const T unm = sgn * um[d], unp = sgn * up[d];
-        const T lam = fmax(fabs(unm), fabs(unp));
-        const T wgt = wq1 * t.w[q2];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          const T F = wgt * (T(0.5) * (um[c] * unm + up[c] * unp) + sc.lf * lam * (um[c] - up[c]));
-#pragma unroll
-          for (int j = 0; j < N; ++j) acc[c][j] = fmadd(t.S[q2][j], F, acc[c][j]);
-        }
-      }
-      T* FB = RA + le * C::RA + 3 * N3 + 12 * Q * N;
-#pragma unroll
-      for (int c = 0; c < 3; ++c)
-#pragma unroll
-        for (int j = 0; j < N; ++j) FB[((s * 3 + c) * Q + q1) * N + j] = acc[c][j];
-    }
-    __syncthreads();
-    // F3: integrate along t1 onto the face nodes
-    for (int w = tid; w < ne * 6 * N; w += TH) {
-      const int le = w / (6 * N);
-      int rem = w - le * 6 * N;
-      const int j = rem % N;
-      rem /= N;
-      const int c = rem % 3, s = rem / 3;
-      const T* FB = RA + le * C::RA + 3 * N3 + 12 * Q * N + ((s * 3 + c) * Q) * N + j;
-      T in[Q];
-#pragma unroll
-      for (int q = 0; q < Q; ++q) in[q] = FB[q * N];
-      T* FR = FRb + le * C::FR + ((d * 2 + s) * 3 + c) * N2 + N * j;
-#pragma unroll
-      for (int i = 0; i < N; ++i) {
-        T acc = t.S[0][i] * in[0];
-#pragma unroll
-        for (int q = 1; q < Q; ++q) acc = fmadd(t.S[q][i], in[q], acc);
-        FR[i] = acc;
-      }
-    }
-    __syncthreads();
-  }
-
-  // ---------------- cell: forward interpolation ----------------
-  // X: A[c][a,b,cz] -> B[c][q1 + Q(b + N cz)]
-  for (int w = tid; w < ne * 3 * N2; w += TH) {
-    const int le = w / (3 * N2);
-    const int rem = w - le * 3 * N2;
-    const int c = rem / N2, bc = rem - c * N2;
-    const T* A = RA + le * C::RA + c * N3 + N * bc;
-    T in[N];
-#pragma unroll
-    for (int a = 0; a < N; ++a) in[a] = A[a];
-    T* B = RB + le * C::RB + c * Q * N2 + Q * bc;
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      T acc = t.S[q][0] * in[0];
-#pragma unroll
-      for (int a = 1; a < N; ++a) acc = fmadd(t.S[q][a], in[a], acc);
-      B[q] = acc;
-    }
-  }
-  __syncthreads();
-  // Y: B[c][q1 + Q(b + N cz)] -> Cb[c][q1 + Q(q2 + Q cz)]   (Cb aliases A's region)
-  for (int w = tid; w < ne * 3 * Q * N; w += TH) {
-    const int le = w / (3 * Q * N);
-    int rem = w - le * 3 * Q * N;
-    const int c = rem / (Q * N);
-    rem -= c * Q * N;
-    const int cz = rem / Q, q1 = rem - cz * Q;
-    const T* B = RB + le * C::RB + c * Q * N2 + q1 + Q * N * cz;
-    T in[N];
-#pragma unroll
-    for (int b = 0; b < N; ++b) in[b] = B[Q * b];
-    T* Cb = RA + le * C::RA + c * Q * Q * N + q1 + Q * Q * cz;
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      T acc = t.S[q][0] * in[0];
-#pragma unroll
-      for (int b = 1; b < N; ++b) acc = fmadd(t.S[q][b], in[b], acc);
-      Cb[Q * q] = acc;
-    }
-  }
-  __syncthreads();
-  // Z: each thread takes whole (q1,q2) z-pencils into registers and
-  // interpolates them to the Gauss points in z: U[j][q3]
-  T Uz[C::PPT][3][Q];
-#pragma unroll
-  for (int pp = 0; pp < C::PPT; ++pp) {
-    const int w = tid + pp * TH;
-    if (w < ne * Q * Q) {
-      const int le = w / (Q * Q), qq = w - le * Q * Q;
-      const T* Cb = RA + le * C::RA + qq;
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        T in[N];
-#pragma unroll
-        for (int cz = 0; cz < N; ++cz) in[cz] = Cb[c * Q * Q * N + Q * Q * cz];
-#pragma unroll
-        for (int q = 0; q < Q; ++q) {
-          T acc = t.S[q][0] * in[0];
-#pragma unroll
-          for (int cz = 1; cz < N; ++cz) acc = fmadd(t.S[q][cz], in[cz], acc);
-          Uz[pp][c][q] = acc;
+        } else {       // x-face layer (own or neighbour), swept in y
+          v -= nY + nZ;
+          const int j = v / (ne * 4 * N);
+          int rem = v - j * ne * 4 * N;
+          const int le = rem / (4 * N);
+          rem -= le * 4 * N;
+          const int sg = rem / (2 * N);
+          rem -= sg * 2 * N;
+          const int s = rem / N, c = rem - s * N;
+          int e = e0 + le, a = s ? N - 1 : 0;
+          if (sg) {
+            const int ex = e % mesh.nx, ey = (e / mesh.nx) % mesh.ny, ez = e / (mesh.nx * mesh.ny);
+            e = neighbor(mesh, ex, ey, ez, 0, s);
+            a = s ? 0 : N - 1;
+          }
+          src = u + j * cs + (size_t)e * N3 + a + N2 * c;
+          sstride = N;
+          dst = lds + le * PER + FXo + ((sg * 2 + s) * 3 + j) * LAYER + c * Q;
         }
       }
+      T in[N];
+      load_pencil<N, Q, T>(src, sstride, in);
+      interp_store<N, Q, T>(t, in, dst, 1, dst2);
     }
   }
   __syncthreads();
 
-  // ---------------- cell: flux and back-contraction, per component ----------------
-  for (int c = 0; c < 3; ++c) {
-    // Zc: T_x = S^T_z F_cx, T_y = S^T_z F_cy, T_z = G^T_z F_cz  -> Tb[f][q1 + Q(q2 + Q cz)]
+  // ---------------- P2: y sweep in place (cell and extra z layers) ----------------
+  {
+    const int n2 = 3 * ne * (N + 2) * Q;
+    for (int w = tid; w < n2; w += TH) {
+      const auto& t = *fresh(tab);
+      const int q1 = w % Q, rest = w / Q;           // rest = (j*ne + le)*(N+2) + c'
+      const int cl = rest % (N + 2), jl = rest / (N + 2);
+      const int le = jl % ne, j = jl / ne;
+      T* p = lds + le * PER + (j * (N + 2) + cl) * COLS + q1;
+      T in[N];
 #pragma unroll
-    for (int pp = 0; pp < C::PPT; ++pp) {
-      const int w = tid + pp * TH;
-      if (w < ne * Q * Q) {
-        const int le = w / (Q * Q), qq = w - le * Q * Q;
+      for (int b = 0; b < N; ++b) in[b] = p[MP * b];
+      interp_store<N, Q, T>(t, in, p, MP, (T*)nullptr);
+    }
+  }
+  __syncthreads();
+
+  // ---------------- P3: z sweeps, fluxes, z back sweep ----------------
+  const int nCell = ne * Q * Q;
+  T Uz[3][Q];
+  T Fz[2][3];
+  T w12 = 0;
+  T* colp = lds;   // this thread's column (per-component mode)
+  {
+    const int nH = ne * 4 * Q;
+    for (int w = tid; w < nCell + nH; w += TH) {
+      const auto& t = *fresh(tab);
+      if (w < nCell) {
+        const int le = w / (Q * Q), qq = w - le * (Q * Q);
         const int q2 = qq / Q, q1 = qq - q2 * Q;
-        const T w12 = t.w[q1] * t.w[q2];
-        T ox[N], oy[N], oz[N];
+        T* col = lds + le * PER + q1 + MP * q2;
+        T v[3][N + 2];
 #pragma unroll
-        for (int cz = 0; cz < N; ++cz) ox[cz] = oy[cz] = oz[cz] = 0;
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+          for (int c = 0; c < N + 2; ++c) v[j][c] = col[(j * (N + 2) + c) * COLS];
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+#pragma unroll
+          for (int j = 0; j < 3; ++j) {
+            T acc = t.S[q][0] * v[j][1];
+#pragma unroll
+            for (int c = 1; c < N; ++c) acc = fmadd(t.S[q][c], v[j][c + 1], acc);
+            Uz[j][q] = acc;
+          }
+        w12 = t.w[q1] * t.w[q2];
+        const T wz = w12 * sc.area[2];
+        {   // z faces: side 0 (own layer c=0, neighbour below), side 1 (c=n-1, above)
+          const T unm0 = -v[2][1], unp0 = -v[2][0];
+          const T lam0 = fmax(fabs(unm0), fabs(unp0));
+          const T unm1 = v[2][N], unp1 = v[2][N + 1];
+          const T lam1 = fmax(fabs(unm1), fabs(unp1));
+#pragma unroll
+          for (int j = 0; j < 3; ++j) {
+            Fz[0][j] = llf(v[j][1], v[j][0], unm0, unp0, lam0, sc.lf, wz);
+            Fz[1][j] = llf(v[j][N], v[j][N + 1], unm1, unp1, lam1, sc.lf, wz);
+          }
+        }
+        colp = col;
+        // z back sweep: all components (ALLC) or component 0
+#pragma unroll
+        for (int j = 0; j < (ALLC ? 3 : 1); ++j) {
+          T ox[N], oy[N], oz[N];
+#pragma unroll
+          for (int c = 0; c < N; ++c) ox[c] = oy[c] = oz[c] = 0;
+#pragma unroll
+          for (int q = 0; q < Q; ++q) {
+            const T uc = w12 * t.w[q] * Uz[j][q];
+            const T fx = sc.cell[0] * uc * Uz[0][q];
+            const T fy = sc.cell[1] * uc * Uz[1][q];
+            const T fz = sc.cell[2] * uc * Uz[2][q];
+#pragma unroll
+            for (int c = 0; c < N; ++c) {
+              ox[c] = fmadd(t.S[q][c], fx, ox[c]);
+              oy[c] = fmadd(t.S[q][c], fy, oy[c]);
+              oz[c] = fmadd(t.G[q][c], fz, oz[c]);
+            }
+          }
+          oz[0] += Fz[0][j];
+          oz[N - 1] += Fz[1][j];
+#pragma unroll
+          for (int c = 0; c < N; ++c) {
+            col[((j * 3 + 0) * N + c) * COLS] = ox[c];
+            col[((j * 3 + 1) * N + c) * COLS] = oy[c];
+            col[((j * 3 + 2) * N + c) * COLS] = oz[c];
+          }
+        }
+      } else {   // face-flux pencil: fam 0 = y face (q = q1), 1 = x face (q = q2)
+        const int h = w - nCell;
+        const int le = h / (4 * Q);
+        int rem = h - le * 4 * Q;
+        const int fam = rem / (2 * Q);
+        rem -= fam * 2 * Q;
+        const int s = rem / Q, q = rem - s * Q;
+        T* F = lds + le * PER + (fam ? FXo : FYo) + q;
+        T own[3][N], nbr[3][N], acc[3][N];
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+          for (int c = 0; c < N; ++c) {
+            own[j][c] = F[((0 * 2 + s) * 3 + j) * LAYER + c * Q];
+            nbr[j][c] = F[((1 * 2 + s) * 3 + j) * LAYER + c * Q];
+            acc[j][c] = 0;
+          }
+        const T sgn = s ? T(1) : T(-1);
+        const T wq = t.w[q] * (fam ? sc.area[0] : sc.area[1]);
 #pragma unroll
         for (int q3 = 0; q3 < Q; ++q3) {
-          const T uc = w12 * t.w[q3] * Uz[pp][c][q3];
-          const T fx = sc.cell[0] * uc * Uz[pp][0][q3];
-          const T fy = sc.cell[1] * uc * Uz[pp][1][q3];
-          const T fz = sc.cell[2] * uc * Uz[pp][2][q3];
+          T um[3], up[3];
 #pragma unroll
-          for (int cz = 0; cz < N; ++cz) {
-            ox[cz] = fmadd(t.S[q3][cz], fx, ox[cz]);
-            oy[cz] = fmadd(t.S[q3][cz], fy, oy[cz]);
-            oz[cz] = fmadd(t.G[q3][cz], fz, oz[cz]);
+          for (int j = 0; j < 3; ++j) {
+            T a = t.S[q3][0] * own[j][0], b = t.S[q3][0] * nbr[j][0];
+#pragma unroll
+            for (int c = 1; c < N; ++c) {
+              a = fmadd(t.S[q3][c], own[j][c], a);
+              b = fmadd(t.S[q3][c], nbr[j][c], b);
+            }
+            um[j] = a;
+            up[j] = b;
+          }
+          const T unm = sgn * (fam ? um[0] : um[1]), unp = sgn * (fam ? up[0] : up[1]);
+          const T lam = fmax(fabs(unm), fabs(unp));
+          const T wgt = wq * t.w[q3];
+#pragma unroll
+          for (int j = 0; j < 3; ++j) {
+            const T f = llf(um[j], up[j], unm, unp, lam, sc.lf, wgt);
+#pragma unroll
+            for (int c = 0; c < N; ++c) acc[j][c] = fmadd(t.S[q3][c], f, acc[j][c]);
           }
         }
-        T* Tb = RA + le * C::RA + qq;
 #pragma unroll
-        for (int cz = 0; cz < N; ++cz) {
-          Tb[0 * Q * Q * N + Q * Q * cz] = ox[cz];
-          Tb[1 * Q * Q * N + Q * Q * cz] = oy[cz];
-          Tb[2 * Q * Q * N + Q * Q * cz] = oz[cz];
-        }
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+          for (int c = 0; c < N; ++c) F[((0 * 2 + s) * 3 + j) * LAYER + c * Q] = acc[j][c];
       }
     }
-    __syncthreads();
-    // Yc: V1 = S^T_y T_x, V2 = G^T_y T_y + S^T_y T_z  -> Vb[f][q1 + Q(b + N cz)]
-    for (int w = tid; w < ne * Q * N; w += TH) {
-      const int le = w / (Q * N);
-      const int rem = w - le * Q * N;
-      const int cz = rem / Q, q1 = rem - cz * Q;
-      const T* Tb = RA + le * C::RA + q1 + Q * Q * cz;
-      T v1[N], v2[N];
+  }
+  __syncthreads();
+
+  // ---------------- Y and X back sweeps ----------------
+  // component range [j0, j1) uses slot set jj = ALLC ? j : 0
+  auto back_y = [&](int j0, int j1) {
+    const int nc = j1 - j0;
+    const int nYc = nc * ne * N * Q, nXf = nc * ne * 2 * N;
+    for (int w = tid; w < nYc + nXf; w += TH) {
+      const auto& t = *fresh(tab);
+      if (w < nYc) {
+        const int q1 = w % Q, rest = w / Q;
+        const int cz = rest % N, jl = rest / N;
+        const int le = jl % ne, j = j0 + jl / ne;
+        const int jj = ALLC ? j : 0;
+        T* L = lds + le * PER;
+        T* tb = L + q1;
+        const int sx = ((jj * 3 + 0) * N + cz) * COLS, sy = sx + N * COLS, sz = sx + 2 * N * COLS;
+        T v1[N], v2[N];
 #pragma unroll
-      for (int b = 0; b < N; ++b) v1[b] = v2[b] = 0;
+        for (int b = 0; b < N; ++b) v1[b] = v2[b] = 0;
 #pragma unroll
-      for (int q2 = 0; q2 < Q; ++q2) {
-        const T tx = Tb[Q * q2], ty = Tb[Q * Q * N + Q * q2], tz = Tb[2 * Q * Q * N + Q * q2];
+        for (int q2 = 0; q2 < Q; ++q2) {
+          const T tx = tb[sx + MP * q2], ty = tb[sy + MP * q2], tz = tb[sz + MP * q2];
+#pragma unroll
+          for (int b = 0; b < N; ++b) {
+            v1[b] = fmadd(t.S[q2][b], tx, v1[b]);
+            v2[b] = fmadd(t.G[q2][b], ty, fmadd(t.S[q2][b], tz, v2[b]));
+          }
+        }
+        v2[0] += L[FYo + ((0 * 2 + 0) * 3 + j) * LAYER + cz * Q + q1];
+        v2[N - 1] += L[FYo + ((0 * 2 + 1) * 3 + j) * LAYER + cz * Q + q1];
 #pragma unroll
         for (int b = 0; b < N; ++b) {
-          v1[b] = fmadd(t.S[q2][b], tx, v1[b]);
-          v2[b] = fmadd(t.G[q2][b], ty, fmadd(t.S[q2][b], tz, v2[b]));
+          tb[sx + MP * b] = v1[b];
+          tb[sy + MP * b] = v2[b];
         }
-      }
-      T* Vb = RB + le * C::RB + q1 + Q * N * cz;
+      } else {   // x-face terms: integrate in y
+        const int v = w - nYc;
+        const int cz = v % N, rest = v / N;
+        const int s = rest % 2, jl = rest / 2;
+        const int le = jl % ne, j = j0 + jl / ne;
+        const int jj = ALLC ? j : 0;
+        T* L = lds + le * PER;
+        const T* xf = L + FXo + ((0 * 2 + s) * 3 + j) * LAYER + cz * Q;
+        T o[N];
 #pragma unroll
-      for (int b = 0; b < N; ++b) {
-        Vb[Q * b] = v1[b];
-        Vb[Q * N2 + Q * b] = v2[b];
+        for (int b = 0; b < N; ++b) o[b] = 0;
+#pragma unroll
+        for (int q2 = 0; q2 < Q; ++q2) {
+          const T x = xf[q2];
+#pragma unroll
+          for (int b = 0; b < N; ++b) o[b] = fmadd(t.S[q2][b], x, o[b]);
+        }
+        T* xr = L + XRo + ((jj * 2 + s) * N + cz) * N;
+#pragma unroll
+        for (int b = 0; b < N; ++b) xr[b] = o[b];
       }
     }
-    __syncthreads();
-    // Xc: R_c = G^T_x V1 + S^T_x V2 + face terms, written once
-    for (int w = tid; w < ne * N2; w += TH) {
-      const int le = w / N2, bc = w - le * N2;
+  };
+  auto back_x = [&](int j0, int j1) {
+    const int nXc = (j1 - j0) * ne * N2;
+    for (int w = tid; w < nXc; w += TH) {
+      const auto& t = *fresh(tab);
+      const int bc = w % N2, jl = w / N2;
+      const int le = jl % ne, j = j0 + jl / ne;
+      const int jj = ALLC ? j : 0;
       const int b = bc % N, cz = bc / N;
-      const T* Vb = RB + le * C::RB + Q * bc;
+      const T* L = lds + le * PER;
+      const T* v1 = L + ((jj * 3 + 0) * N + cz) * COLS + MP * b;
+      const T* v2 = v1 + N * COLS;
       T o[N];
 #pragma unroll
       for (int a = 0; a < N; ++a) o[a] = 0;
 #pragma unroll
       for (int q1 = 0; q1 < Q; ++q1) {
-        const T v1 = Vb[q1], v2 = Vb[Q * N2 + q1];
+        const T x1 = v1[q1], x2 = v2[q1];
 #pragma unroll
-        for (int a = 0; a < N; ++a) o[a] = fmadd(t.G[q1][a], v1, fmadd(t.S[q1][a], v2, o[a]));
+        for (int a = 0; a < N; ++a) o[a] = fmadd(t.G[q1][a], x1, fmadd(t.S[q1][a], x2, o[a]));
       }
-      const T* FR = FRb + le * C::FR;
-      // x faces: nodes a = 0 / N-1, face index (t1,t2) = (b,cz)
-      o[0] += FR[((0 * 2 + 0) * 3 + c) * N2 + b + N * cz];
-      o[N - 1] += FR[((0 * 2 + 1) * 3 + c) * N2 + b + N * cz];
-      if (b == 0 || b == N - 1) {   // y faces: (t1,t2) = (a,cz)
-        const T* F = FR + ((1 * 2 + (b == 0 ? 0 : 1)) * 3 + c) * N2 + N * cz;
-#pragma unroll
-        for (int a = 0; a < N; ++a) o[a] += F[a];
-      }
-      if (cz == 0 || cz == N - 1) { // z faces: (t1,t2) = (a,b)
-        const T* F = FR + ((2 * 2 + (cz == 0 ? 0 : 1)) * 3 + c) * N2 + N * b;
-#pragma unroll
-        for (int a = 0; a < N; ++a) o[a] += F[a];
-      }
-      T* g = r + c * cstride + (size_t)(e0 + le) * N3 + N * bc;
+      const T* xr = L + XRo + (jj * 2 * N + cz) * N + b;
+      o[0] += xr[0];
+      o[N - 1] += xr[N2];
+      T* g = r + j * cs + (size_t)(e0 + le) * N3 + N * bc;
 #pragma unroll
       for (int a = 0; a < N; ++a) g[a] = o[a];
     }
+  };
+
+  if constexpr (ALLC) {
+    back_y(0, 3);
     __syncthreads();
+    back_x(0, 3);
+  } else {
+    // per component: the thread's own z pencil (tid < nCell) is still in registers
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      if (j > 0) {
+        if (tid < nCell) {
+          const auto& t = *fresh(tab);
+          T ox[N], oy[N], oz[N];
+#pragma unroll
+          for (int c = 0; c < N; ++c) ox[c] = oy[c] = oz[c] = 0;
+#pragma unroll
+          for (int q = 0; q < Q; ++q) {
+            const T uc = w12 * t.w[q] * Uz[j][q];
+            const T fx = sc.cell[0] * uc * Uz[0][q];
+            const T fy = sc.cell[1] * uc * Uz[1][q];
+            const T fz = sc.cell[2] * uc * Uz[2][q];
+#pragma unroll
+            for (int c = 0; c < N; ++c) {
+              ox[c] = fmadd(t.S[q][c], fx, ox[c]);
+              oy[c] = fmadd(t.S[q][c], fy, oy[c]);
+              oz[c] = fmadd(t.G[q][c], fz, oz[c]);
+            }
+          }
+          oz[0] += Fz[0][j];
+          oz[N - 1] += Fz[1][j];
+#pragma unroll
+          for (int c = 0; c < N; ++c) {
+            colp[(0 * N + c) * COLS] = ox[c];
+            colp[(1 * N + c) * COLS] = oy[c];
+            colp[(2 * N + c) * COLS] = oz[c];
+          }
+        }
+        __syncthreads();
+      }
+      back_y(j, j + 1);
+      __syncthreads();
+      back_x(j, j + 1);
+      if (j < 2) __syncthreads();
+    }
   }
 }
 
 template <int N, int Q, typename T>
 static hipError_t launch_conv_nq(const ConvPlan& P, const void* u, void* r, hipStream_t s) {
-  using C = ConvCfg<N, Q, T>;
+  using Sh = ConvShape<N, Q, (int)sizeof(T)>;
   ConvTab<N, Q, T> t;
   for (int q = 0; q < Q; ++q) {
     for (int a = 0; a < N; ++a) {
@@ -375,8 +514,8 @@ static hipError_t launch_conv_nq(const ConvPlan& P, const void* u, void* r, hipS
   hipError_t err;
   const ConvTab<N, Q, T>* dt = device_table_of("convective", t, &err);
   if (!dt) return err;
-  const int grid = (P.mesh.n_el + C::E - 1) / C::E;
-  hipLaunchKernelGGL((convective_kernel<N, Q, T>), dim3(grid), dim3(C::THREADS), 0, s,
+  const int grid = (P.mesh.n_el + Sh::E - 1) / Sh::E;
+  hipLaunchKernelGGL((convective_kernel<N, Q, T, Sh::E, Sh::TH, Sh::ALLC>), dim3(grid), dim3(Sh::TH), 0, s,
                      (const T*)u, (T*)r, P.mesh, dt, sc);
   return hipGetLastError();
 }
