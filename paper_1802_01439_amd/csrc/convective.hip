@@ -42,7 +42,10 @@
 // Small degrees keep the back sweeps of all three components in LDS at once
 // (5 phases); large ones run the Z/Y/X back sweeps per component from the z
 // pencils held in registers (11 phases, a third of the LDS).
+#include <cmath>
+
 #include "api_internal.h"
+#include "basis_ct.h"
 #include "common.h"
 #include "ops.h"
 
@@ -54,6 +57,54 @@ struct ConvTab {
   T G[Q][N];   // l_a'(z_q)
   T w[Q];      // Gauss weights on [0,1]
 };
+
+// The tables of degree N-1 with Q Gauss points as compile-time constants.
+template <int N, int Q, typename T>
+constexpr ConvTab<N, Q, T> conv_tab_ct() {
+  constexpr ct::Tables<N, Q> d{};
+  ConvTab<N, Q, T> t{};
+  for (int q = 0; q < Q; ++q) {
+    for (int a = 0; a < N; ++a) {
+      t.S[q][a] = (T)d.S[q][a];
+      t.G[q][a] = (T)d.G[q][a];
+    }
+    t.w[q] = (T)d.w[q];
+  }
+  return t;
+}
+
+// Where the kernels read the tables from.  FP32: compile-time constants, which
+// become literal operands of the FMAs.  FP64: a table in device memory, read
+// with scalar loads through a pointer laundered by an empty asm (and returned
+// in the constant address space), so that loads issued after it cannot be
+// merged with loads of the same entries elsewhere in the kernel: each phase
+// loads the rows it uses when it uses them instead of keeping the table live
+// in scalar registers (64-bit constants would each take a scalar register pair
+// and spill at high degree).
+template <typename P>
+using const_ptr = const __attribute__((address_space(4))) P*;
+
+template <typename P>
+__device__ __forceinline__ const_ptr<P> fresh(const P* p) {
+  uint64_t x = (uint64_t)p;
+  asm volatile("" : "+v"(x));
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(x >> 32));
+  return (const_ptr<P>)(((uint64_t)hi << 32) | lo);
+}
+
+template <int N, int Q, typename T>
+__device__ __forceinline__ decltype(auto) conv_pick(const ConvTab<N, Q, T>& ct, const ConvTab<N, Q, T>* tab) {
+  if constexpr (sizeof(T) == 4) return (ct);
+  else return *fresh(tab);
+}
+
+// Declares `t`, the tables of the current phase.  The compile-time copy is a
+// constexpr local so that its entries fold into the instructions.
+#define CONV_TABLES(t)                                              \
+  constexpr ConvTab<N, Q, T> t##_ct =                               \
+      sizeof(T) == 4 ? conv_tab_ct<N, Q, T>() : ConvTab<N, Q, T>{}; \
+  const auto& t = conv_pick<N, Q, T>(t##_ct, tab)
 
 template <typename T>
 struct ConvScal {
@@ -124,23 +175,6 @@ __device__ __forceinline__ T llf(T um, T up, T unm, T unp, T lam, T lf, T wgt) {
   return wgt * (T(0.5) * (um * unm + up * unp) + lf * lam * (um - up));
 }
 
-// The table pointer passed through an empty asm and returned in the constant
-// address space: table loads issued after it are scalar loads that cannot be
-// merged with loads of the same entries elsewhere in the kernel, so each phase
-// loads the rows it uses when it uses them instead of keeping the whole table
-// live in scalar registers.
-template <typename P>
-using const_ptr = const __attribute__((address_space(4))) P*;
-
-template <typename P>
-__device__ __forceinline__ const_ptr<P> fresh(const P* p) {
-  uint64_t x = (uint64_t)p;
-  asm volatile("" : "+v"(x));
-  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
-  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(x >> 32));
-  return (const_ptr<P>)(((uint64_t)hi << 32) | lo);
-}
-
 template <int N, int Q, typename T, int E, int TH, bool ALLC>
 __global__ void __launch_bounds__(TH)
 convective_kernel(const T* __restrict__ u, T* __restrict__ r, MeshArgs mesh,
@@ -158,22 +192,23 @@ convective_kernel(const T* __restrict__ u, T* __restrict__ r, MeshArgs mesh,
   const size_t cs = (size_t)mesh.n_el * N3;
 
   // ---------------- P1: x sweeps (and y sweeps of x-face layers) from global ----------------
+  // All of a thread's pencils are loaded before any is swept, so the global
+  // load latency is paid once per thread rather than once per pencil.
   {
     const int nM = 3 * ne * N2, nY = ne * 6 * N, nZ = ne * 6 * N, nX = ne * 12 * N;
-    for (int w = tid; w < nM + nY + nZ + nX; w += TH) {
-      const auto& t = *fresh(tab);
-      const T* src;
-      int sstride = 1;
-      T* dst;
-      T* dst2 = nullptr;
+    const int total = nM + nY + nZ + nX;
+    // item w -> source pencil (src, stride) and LDS destination(s)
+    auto item = [&](int w, const T*& src, int& sstride, int& d1, int& d2) {
+      sstride = 1;
+      d2 = -1;
       if (w < nM) {   // cell pencil (b, c) of component j
         const int j = w / (ne * N2), rem = w - j * ne * N2, le = rem / N2, bc = rem - le * N2;
         const int b = bc % N, c = bc / N;
         src = u + j * cs + (size_t)(e0 + le) * N3 + N * bc;
-        T* L = lds + le * PER;
-        dst = L + (j * (N + 2) + c + 1) * COLS + MP * b;
-        if (b == 0) dst2 = L + FYo + ((0 * 2 + 0) * 3 + j) * LAYER + c * Q;
-        else if (b == N - 1) dst2 = L + FYo + ((0 * 2 + 1) * 3 + j) * LAYER + c * Q;
+        const int L = le * PER;
+        d1 = L + (j * (N + 2) + c + 1) * COLS + MP * b;
+        if (b == 0) d2 = L + FYo + ((0 * 2 + 0) * 3 + j) * LAYER + c * Q;
+        else if (b == N - 1) d2 = L + FYo + ((0 * 2 + 1) * 3 + j) * LAYER + c * Q;
       } else {
         int v = w - nM;
         if (v < nY + nZ) {   // y or z neighbour layer pencil, swept in x
@@ -188,13 +223,13 @@ convective_kernel(const T* __restrict__ u, T* __restrict__ r, MeshArgs mesh,
           const int ex = e % mesh.nx, ey = (e / mesh.nx) % mesh.ny, ez = e / (mesh.nx * mesh.ny);
           const int nb = neighbor(mesh, ex, ey, ez, isz ? 2 : 1, s);
           const int lay = s ? 0 : N - 1;   // neighbour's facing layer
-          T* L = lds + le * PER;
+          const int L = le * PER;
           if (isz) {   // pencil b = p of z layer lay -> extra z slot
             src = u + j * cs + (size_t)nb * N3 + N * (p + N * lay);
-            dst = L + (j * (N + 2) + (s ? N + 1 : 0)) * COLS + MP * p;
+            d1 = L + (j * (N + 2) + (s ? N + 1 : 0)) * COLS + MP * p;
           } else {     // pencil c = p of y layer lay -> FY neighbour entry
             src = u + j * cs + (size_t)nb * N3 + N * (lay + N * p);
-            dst = L + FYo + ((1 * 2 + s) * 3 + j) * LAYER + p * Q;
+            d1 = L + FYo + ((1 * 2 + s) * 3 + j) * LAYER + p * Q;
           }
         } else {       // x-face layer (own or neighbour), swept in y
           v -= nY + nZ;
@@ -213,12 +248,30 @@ convective_kernel(const T* __restrict__ u, T* __restrict__ r, MeshArgs mesh,
           }
           src = u + j * cs + (size_t)e * N3 + a + N2 * c;
           sstride = N;
-          dst = lds + le * PER + FXo + ((sg * 2 + s) * 3 + j) * LAYER + c * Q;
+          d1 = le * PER + FXo + ((sg * 2 + s) * 3 + j) * LAYER + c * Q;
         }
       }
-      T in[N];
-      load_pencil<N, Q, T>(src, sstride, in);
-      interp_store<N, Q, T>(t, in, dst, 1, dst2);
+    };
+    constexpr int NI1 = (E * (3 * N2 + 24 * N) + TH - 1) / TH;
+    T in[NI1][N];
+    int d1[NI1], d2[NI1];
+#pragma unroll
+    for (int i = 0; i < NI1; ++i) {
+      const int w = tid + i * TH;
+      d1[i] = -1;
+      if (w < total) {
+        const T* src;
+        int sstride;
+        item(w, src, sstride, d1[i], d2[i]);
+        load_pencil<N, Q, T>(src, sstride, in[i]);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NI1; ++i) {
+      if (d1[i] >= 0) {
+        CONV_TABLES(t);
+        interp_store<N, Q, T>(t, in[i], lds + d1[i], 1, d2[i] >= 0 ? lds + d2[i] : (T*)nullptr);
+      }
     }
   }
   __syncthreads();
@@ -227,7 +280,7 @@ convective_kernel(const T* __restrict__ u, T* __restrict__ r, MeshArgs mesh,
   {
     const int n2 = 3 * ne * (N + 2) * Q;
     for (int w = tid; w < n2; w += TH) {
-      const auto& t = *fresh(tab);
+      CONV_TABLES(t);
       const int q1 = w % Q, rest = w / Q;           // rest = (j*ne + le)*(N+2) + c'
       const int cl = rest % (N + 2), jl = rest / (N + 2);
       const int le = jl % ne, j = jl / ne;
@@ -249,7 +302,7 @@ convective_kernel(const T* __restrict__ u, T* __restrict__ r, MeshArgs mesh,
   {
     const int nH = ne * 4 * Q;
     for (int w = tid; w < nCell + nH; w += TH) {
-      const auto& t = *fresh(tab);
+      CONV_TABLES(t);
       if (w < nCell) {
         const int le = w / (Q * Q), qq = w - le * (Q * Q);
         const int q2 = qq / Q, q1 = qq - q2 * Q;
@@ -368,7 +421,7 @@ convective_kernel(const T* __restrict__ u, T* __restrict__ r, MeshArgs mesh,
     const int nc = j1 - j0;
     const int nYc = nc * ne * N * Q, nXf = nc * ne * 2 * N;
     for (int w = tid; w < nYc + nXf; w += TH) {
-      const auto& t = *fresh(tab);
+      CONV_TABLES(t);
       if (w < nYc) {
         const int q1 = w % Q, rest = w / Q;
         const int cz = rest % N, jl = rest / N;
@@ -422,7 +475,7 @@ convective_kernel(const T* __restrict__ u, T* __restrict__ r, MeshArgs mesh,
   auto back_x = [&](int j0, int j1) {
     const int nXc = (j1 - j0) * ne * N2;
     for (int w = tid; w < nXc; w += TH) {
-      const auto& t = *fresh(tab);
+      CONV_TABLES(t);
       const int bc = w % N2, jl = w / N2;
       const int le = jl % ne, j = j0 + jl / ne;
       const int jj = ALLC ? j : 0;
@@ -458,7 +511,7 @@ convective_kernel(const T* __restrict__ u, T* __restrict__ r, MeshArgs mesh,
     for (int j = 0; j < 3; ++j) {
       if (j > 0) {
         if (tid < nCell) {
-          const auto& t = *fresh(tab);
+          CONV_TABLES(t);
           T ox[N], oy[N], oz[N];
 #pragma unroll
           for (int c = 0; c < N; ++c) ox[c] = oy[c] = oz[c] = 0;
@@ -497,13 +550,13 @@ convective_kernel(const T* __restrict__ u, T* __restrict__ r, MeshArgs mesh,
 template <int N, int Q, typename T>
 static hipError_t launch_conv_nq(const ConvPlan& P, const void* u, void* r, hipStream_t s) {
   using Sh = ConvShape<N, Q, (int)sizeof(T)>;
-  ConvTab<N, Q, T> t;
+  // the kernel's compile-time tables must be the plan's tables
+  constexpr ct::Tables<N, Q> C{};
   for (int q = 0; q < Q; ++q) {
-    for (int a = 0; a < N; ++a) {
-      t.S[q][a] = (T)P.S[q * N + a];
-      t.G[q][a] = (T)P.G[q * N + a];
-    }
-    t.w[q] = (T)P.w[q];
+    if (std::fabs(C.w[q] - P.w[q]) > 1e-13) return hipErrorInvalidValue;
+    for (int a = 0; a < N; ++a)
+      if (std::fabs(C.S[q][a] - P.S[q * N + a]) > 1e-13 || std::fabs(C.G[q][a] - P.G[q * N + a]) > 1e-11)
+        return hipErrorInvalidValue;
   }
   ConvScal<T> sc;
   for (int d = 0; d < 3; ++d) {
@@ -511,9 +564,20 @@ static hipError_t launch_conv_nq(const ConvPlan& P, const void* u, void* r, hipS
     sc.area[d] = (T)P.area[d];
   }
   sc.lf = (T)P.lf;
-  hipError_t err;
-  const ConvTab<N, Q, T>* dt = device_table_of("convective", t, &err);
-  if (!dt) return err;
+  const ConvTab<N, Q, T>* dt = nullptr;   // FP32 kernels use the compile-time tables
+  if (sizeof(T) == 8) {
+    ConvTab<N, Q, T> t;
+    for (int q = 0; q < Q; ++q) {
+      for (int a = 0; a < N; ++a) {
+        t.S[q][a] = (T)P.S[q * N + a];
+        t.G[q][a] = (T)P.G[q * N + a];
+      }
+      t.w[q] = (T)P.w[q];
+    }
+    hipError_t err;
+    dt = device_table_of("convective", t, &err);
+    if (!dt) return err;
+  }
   const int grid = (P.mesh.n_el + Sh::E - 1) / Sh::E;
   hipLaunchKernelGGL((convective_kernel<N, Q, T, Sh::E, Sh::TH, Sh::ALLC>), dim3(grid), dim3(Sh::TH), 0, s,
                      (const T*)u, (T*)r, P.mesh, dt, sc);
