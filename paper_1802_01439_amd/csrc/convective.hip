@@ -188,73 +188,86 @@ convective_kernel(const T* __restrict__ u, T* __restrict__ r, MeshArgs mesh,
   __shared__ T lds[E * PER];
   const int tid = threadIdx.x;
   const int e0 = xcd_remap(blockIdx.x, gridDim.x) * E;
-  const int ne = min(E, mesh.n_el - e0);
+  const int ne = min(E, mesh.n_el - e0);   // elements of this batch; items of le >= ne are skipped
   const size_t cs = (size_t)mesh.n_el * N3;
+  // grid position of element e0 + le from that of e0 (uniform)
+  const int nxy = mesh.nx * mesh.ny;
+  const int ez0 = e0 / nxy, exy0 = e0 - ez0 * nxy, ey0 = exy0 / mesh.nx, ex0 = exy0 - ey0 * mesh.nx;
+  auto nbr = [&](int le, int d, int s) {
+    int ex = ex0 + le, ey = ey0, ez = ez0;
+    while (ex >= mesh.nx) {
+      ex -= mesh.nx;
+      if (++ey == mesh.ny) {
+        ey = 0;
+        ++ez;
+      }
+    }
+    return neighbor(mesh, ex, ey, ez, d, s);
+  };
 
   // ---------------- P1: x sweeps (and y sweeps of x-face layers) from global ----------------
-  // All of a thread's pencils are loaded before any is swept, so the global
-  // load latency is paid once per thread rather than once per pencil.
+  // An item is one pencil position taken for all three components, which
+  // share its index arithmetic; all of a thread's loads are issued before any
+  // sweep, so the global load latency is paid once per thread.
   {
-    const int nM = 3 * ne * N2, nY = ne * 6 * N, nZ = ne * 6 * N, nX = ne * 12 * N;
-    const int total = nM + nY + nZ + nX;
-    // item w -> source pencil (src, stride) and LDS destination(s)
-    auto item = [&](int w, const T*& src, int& sstride, int& d1, int& d2) {
+    constexpr int nM = E * N2, nL = E * 4 * N, nX = E * 4 * N;   // cell, y/z neighbour, x-face items
+    constexpr int total = nM + nL + nX;
+    constexpr int D1S = (N + 2) * COLS;   // component stride of the BC slots
+    // item w -> source pencil of component 0 (src, stride), LDS destination of
+    // component 0 (d1) with its component stride (dstr), second destination d2
+    auto item = [&](int w, const T*& src, int& sstride, int& d1, int& dstr, int& d2) {
       sstride = 1;
+      d1 = -1;
       d2 = -1;
-      if (w < nM) {   // cell pencil (b, c) of component j
-        const int j = w / (ne * N2), rem = w - j * ne * N2, le = rem / N2, bc = rem - le * N2;
+      dstr = D1S;
+      if (w < nM) {   // cell pencil (b, c)
+        const int le = w / N2, bc = w - le * N2;
+        if (le >= ne) return;
         const int b = bc % N, c = bc / N;
-        src = u + j * cs + (size_t)(e0 + le) * N3 + N * bc;
+        src = u + (size_t)(e0 + le) * N3 + N * bc;
         const int L = le * PER;
-        d1 = L + (j * (N + 2) + c + 1) * COLS + MP * b;
-        if (b == 0) d2 = L + FYo + ((0 * 2 + 0) * 3 + j) * LAYER + c * Q;
-        else if (b == N - 1) d2 = L + FYo + ((0 * 2 + 1) * 3 + j) * LAYER + c * Q;
-      } else {
-        int v = w - nM;
-        if (v < nY + nZ) {   // y or z neighbour layer pencil, swept in x
-          const bool isz = v >= nY;
-          if (isz) v -= nY;
-          const int j = v / (ne * 2 * N);
-          int rem = v - j * ne * 2 * N;
-          const int le = rem / (2 * N);
-          rem -= le * 2 * N;
-          const int s = rem / N, p = rem - s * N;
-          const int e = e0 + le;
-          const int ex = e % mesh.nx, ey = (e / mesh.nx) % mesh.ny, ez = e / (mesh.nx * mesh.ny);
-          const int nb = neighbor(mesh, ex, ey, ez, isz ? 2 : 1, s);
-          const int lay = s ? 0 : N - 1;   // neighbour's facing layer
-          const int L = le * PER;
-          if (isz) {   // pencil b = p of z layer lay -> extra z slot
-            src = u + j * cs + (size_t)nb * N3 + N * (p + N * lay);
-            d1 = L + (j * (N + 2) + (s ? N + 1 : 0)) * COLS + MP * p;
-          } else {     // pencil c = p of y layer lay -> FY neighbour entry
-            src = u + j * cs + (size_t)nb * N3 + N * (lay + N * p);
-            d1 = L + FYo + ((1 * 2 + s) * 3 + j) * LAYER + p * Q;
-          }
-        } else {       // x-face layer (own or neighbour), swept in y
-          v -= nY + nZ;
-          const int j = v / (ne * 4 * N);
-          int rem = v - j * ne * 4 * N;
-          const int le = rem / (4 * N);
-          rem -= le * 4 * N;
-          const int sg = rem / (2 * N);
-          rem -= sg * 2 * N;
-          const int s = rem / N, c = rem - s * N;
-          int e = e0 + le, a = s ? N - 1 : 0;
-          if (sg) {
-            const int ex = e % mesh.nx, ey = (e / mesh.nx) % mesh.ny, ez = e / (mesh.nx * mesh.ny);
-            e = neighbor(mesh, ex, ey, ez, 0, s);
-            a = s ? 0 : N - 1;
-          }
-          src = u + j * cs + (size_t)e * N3 + a + N2 * c;
-          sstride = N;
-          d1 = le * PER + FXo + ((sg * 2 + s) * 3 + j) * LAYER + c * Q;
+        d1 = L + (c + 1) * COLS + MP * b;
+        if (b == 0) d2 = L + FYo + (0 * 2 + 0) * 3 * LAYER + c * Q;
+        else if (b == N - 1) d2 = L + FYo + (0 * 2 + 1) * 3 * LAYER + c * Q;
+      } else if (w < nM + nL) {   // y or z neighbour layer pencil, swept in x
+        const int v = w - nM;
+        const int le = v / (4 * N);
+        if (le >= ne) return;
+        const int rem = v - le * 4 * N;
+        const int isz = rem / (2 * N), r2 = rem - isz * 2 * N;
+        const int s = r2 / N, p = r2 - s * N;
+        const int nb = nbr(le, isz ? 2 : 1, s);
+        const int lay = s ? 0 : N - 1;   // neighbour's facing layer
+        const int L = le * PER;
+        if (isz) {   // pencil b = p of z layer lay -> extra z slot
+          src = u + (size_t)nb * N3 + N * (p + N * lay);
+          d1 = L + (s ? N + 1 : 0) * COLS + MP * p;
+        } else {     // pencil c = p of y layer lay -> FY neighbour entry
+          src = u + (size_t)nb * N3 + N * (lay + N * p);
+          d1 = L + FYo + (1 * 2 + s) * 3 * LAYER + p * Q;
+          dstr = LAYER;
         }
+      } else {        // x-face layer (own or neighbour), swept in y
+        const int v = w - nM - nL;
+        const int le = v / (4 * N);
+        if (le >= ne) return;
+        const int rem = v - le * 4 * N;
+        const int sg = rem / (2 * N), r2 = rem - sg * 2 * N;
+        const int s = r2 / N, c = r2 - s * N;
+        int e = e0 + le, a = s ? N - 1 : 0;
+        if (sg) {
+          e = nbr(le, 0, s);
+          a = s ? 0 : N - 1;
+        }
+        src = u + (size_t)e * N3 + a + N2 * c;
+        sstride = N;
+        d1 = le * PER + FXo + (sg * 2 + s) * 3 * LAYER + c * Q;
+        dstr = LAYER;
       }
     };
-    constexpr int NI1 = (E * (3 * N2 + 24 * N) + TH - 1) / TH;
-    T in[NI1][N];
-    int d1[NI1], d2[NI1];
+    constexpr int NI1 = (total + TH - 1) / TH;
+    T in[NI1][3][N];
+    int d1[NI1], ds[NI1], d2[NI1];
 #pragma unroll
     for (int i = 0; i < NI1; ++i) {
       const int w = tid + i * TH;
@@ -262,15 +275,22 @@ convective_kernel(const T* __restrict__ u, T* __restrict__ r, MeshArgs mesh,
       if (w < total) {
         const T* src;
         int sstride;
-        item(w, src, sstride, d1[i], d2[i]);
-        load_pencil<N, Q, T>(src, sstride, in[i]);
+        item(w, src, sstride, d1[i], ds[i], d2[i]);
+        if (d1[i] >= 0) {
+#pragma unroll
+          for (int j = 0; j < 3; ++j) load_pencil<N, Q, T>(src + j * cs, sstride, in[i][j]);
+        }
       }
     }
 #pragma unroll
     for (int i = 0; i < NI1; ++i) {
       if (d1[i] >= 0) {
-        CONV_TABLES(t);
-        interp_store<N, Q, T>(t, in[i], lds + d1[i], 1, d2[i] >= 0 ? lds + d2[i] : (T*)nullptr);
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+          CONV_TABLES(t);
+          interp_store<N, Q, T>(t, in[i][j], lds + d1[i] + j * ds[i], 1,
+                                d2[i] >= 0 ? lds + d2[i] + j * LAYER : (T*)nullptr);
+        }
       }
     }
   }
@@ -278,12 +298,13 @@ convective_kernel(const T* __restrict__ u, T* __restrict__ r, MeshArgs mesh,
 
   // ---------------- P2: y sweep in place (cell and extra z layers) ----------------
   {
-    const int n2 = 3 * ne * (N + 2) * Q;
+    constexpr int n2 = 3 * E * (N + 2) * Q;
     for (int w = tid; w < n2; w += TH) {
-      CONV_TABLES(t);
-      const int q1 = w % Q, rest = w / Q;           // rest = (j*ne + le)*(N+2) + c'
+      const int q1 = w % Q, rest = w / Q;           // rest = (j*E + le)*(N+2) + c'
       const int cl = rest % (N + 2), jl = rest / (N + 2);
-      const int le = jl % ne, j = jl / ne;
+      const int le = jl % E, j = jl / E;
+      if (le >= ne) continue;
+      CONV_TABLES(t);
       T* p = lds + le * PER + (j * (N + 2) + cl) * COLS + q1;
       T in[N];
 #pragma unroll
@@ -294,17 +315,20 @@ convective_kernel(const T* __restrict__ u, T* __restrict__ r, MeshArgs mesh,
   __syncthreads();
 
   // ---------------- P3: z sweeps, fluxes, z back sweep ----------------
-  const int nCell = ne * Q * Q;
+  constexpr int nCell = E * Q * Q;
+  bool own_cell = false;   // this thread holds the z pencil of cell item tid
   T Uz[3][Q];
   T Fz[2][3];
   T w12 = 0;
   T* colp = lds;   // this thread's column (per-component mode)
   {
-    const int nH = ne * 4 * Q;
+    constexpr int nH = E * 4 * Q;
     for (int w = tid; w < nCell + nH; w += TH) {
       CONV_TABLES(t);
       if (w < nCell) {
         const int le = w / (Q * Q), qq = w - le * (Q * Q);
+        if (le >= ne) continue;
+        own_cell = true;
         const int q2 = qq / Q, q1 = qq - q2 * Q;
         T* col = lds + le * PER + q1 + MP * q2;
         T v[3][N + 2];
@@ -343,15 +367,22 @@ convective_kernel(const T* __restrict__ u, T* __restrict__ r, MeshArgs mesh,
           for (int c = 0; c < N; ++c) ox[c] = oy[c] = oz[c] = 0;
 #pragma unroll
           for (int q = 0; q < Q; ++q) {
-            const T uc = w12 * t.w[q] * Uz[j][q];
-            const T fx = sc.cell[0] * uc * Uz[0][q];
-            const T fy = sc.cell[1] * uc * Uz[1][q];
-            const T fz = sc.cell[2] * uc * Uz[2][q];
+            const T uc = t.w[q] * Uz[j][q];
+            const T fx = uc * Uz[0][q], fy = uc * Uz[1][q], fz = uc * Uz[2][q];
 #pragma unroll
             for (int c = 0; c < N; ++c) {
               ox[c] = fmadd(t.S[q][c], fx, ox[c]);
               oy[c] = fmadd(t.S[q][c], fy, oy[c]);
               oz[c] = fmadd(t.G[q][c], fz, oz[c]);
+            }
+          }
+          {   // cell scalings s_d w_q1 w_q2 applied once per output
+            const T s0 = sc.cell[0] * w12, s1 = sc.cell[1] * w12, s2 = sc.cell[2] * w12;
+#pragma unroll
+            for (int c = 0; c < N; ++c) {
+              ox[c] *= s0;
+              oy[c] *= s1;
+              oz[c] *= s2;
             }
           }
           oz[0] += Fz[0][j];
@@ -366,6 +397,7 @@ convective_kernel(const T* __restrict__ u, T* __restrict__ r, MeshArgs mesh,
       } else {   // face-flux pencil: fam 0 = y face (q = q1), 1 = x face (q = q2)
         const int h = w - nCell;
         const int le = h / (4 * Q);
+        if (le >= ne) continue;
         int rem = h - le * 4 * Q;
         const int fam = rem / (2 * Q);
         rem -= fam * 2 * Q;
@@ -419,13 +451,14 @@ convective_kernel(const T* __restrict__ u, T* __restrict__ r, MeshArgs mesh,
   // component range [j0, j1) uses slot set jj = ALLC ? j : 0
   auto back_y = [&](int j0, int j1) {
     const int nc = j1 - j0;
-    const int nYc = nc * ne * N * Q, nXf = nc * ne * 2 * N;
+    const int nYc = nc * E * N * Q, nXf = nc * E * 2 * N;
     for (int w = tid; w < nYc + nXf; w += TH) {
       CONV_TABLES(t);
       if (w < nYc) {
         const int q1 = w % Q, rest = w / Q;
         const int cz = rest % N, jl = rest / N;
-        const int le = jl % ne, j = j0 + jl / ne;
+        const int le = jl % E, j = j0 + jl / E;
+        if (le >= ne) continue;
         const int jj = ALLC ? j : 0;
         T* L = lds + le * PER;
         T* tb = L + q1;
@@ -453,7 +486,8 @@ convective_kernel(const T* __restrict__ u, T* __restrict__ r, MeshArgs mesh,
         const int v = w - nYc;
         const int cz = v % N, rest = v / N;
         const int s = rest % 2, jl = rest / 2;
-        const int le = jl % ne, j = j0 + jl / ne;
+        const int le = jl % E, j = j0 + jl / E;
+        if (le >= ne) continue;
         const int jj = ALLC ? j : 0;
         T* L = lds + le * PER;
         const T* xf = L + FXo + ((0 * 2 + s) * 3 + j) * LAYER + cz * Q;
@@ -473,11 +507,12 @@ convective_kernel(const T* __restrict__ u, T* __restrict__ r, MeshArgs mesh,
     }
   };
   auto back_x = [&](int j0, int j1) {
-    const int nXc = (j1 - j0) * ne * N2;
+    const int nXc = (j1 - j0) * E * N2;
     for (int w = tid; w < nXc; w += TH) {
       CONV_TABLES(t);
       const int bc = w % N2, jl = w / N2;
-      const int le = jl % ne, j = j0 + jl / ne;
+      const int le = jl % E, j = j0 + jl / E;
+      if (le >= ne) continue;
       const int jj = ALLC ? j : 0;
       const int b = bc % N, cz = bc / N;
       const T* L = lds + le * PER;
@@ -510,22 +545,29 @@ convective_kernel(const T* __restrict__ u, T* __restrict__ r, MeshArgs mesh,
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
       if (j > 0) {
-        if (tid < nCell) {
+        if (own_cell) {
           CONV_TABLES(t);
           T ox[N], oy[N], oz[N];
 #pragma unroll
           for (int c = 0; c < N; ++c) ox[c] = oy[c] = oz[c] = 0;
 #pragma unroll
           for (int q = 0; q < Q; ++q) {
-            const T uc = w12 * t.w[q] * Uz[j][q];
-            const T fx = sc.cell[0] * uc * Uz[0][q];
-            const T fy = sc.cell[1] * uc * Uz[1][q];
-            const T fz = sc.cell[2] * uc * Uz[2][q];
+            const T uc = t.w[q] * Uz[j][q];
+            const T fx = uc * Uz[0][q], fy = uc * Uz[1][q], fz = uc * Uz[2][q];
 #pragma unroll
             for (int c = 0; c < N; ++c) {
               ox[c] = fmadd(t.S[q][c], fx, ox[c]);
               oy[c] = fmadd(t.S[q][c], fy, oy[c]);
               oz[c] = fmadd(t.G[q][c], fz, oz[c]);
+            }
+          }
+          {   // cell scalings s_d w_q1 w_q2 applied once per output
+            const T s0 = sc.cell[0] * w12, s1 = sc.cell[1] * w12, s2 = sc.cell[2] * w12;
+#pragma unroll
+            for (int c = 0; c < N; ++c) {
+              ox[c] *= s0;
+              oy[c] *= s1;
+              oz[c] *= s2;
             }
           }
           oz[0] += Fz[0][j];
