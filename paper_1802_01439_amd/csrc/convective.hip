@@ -6,7 +6,8 @@
 //   F*_c = 1/2 (u-_c u-.n + u+_c u+.n) + lf * max(|u-.n|, |u+.n|) (u-_c - u+_c)
 //
 // 1D tables: S (m x n, LGL -> Gauss interpolation), G (m x n, derivatives of
-// the LGL basis at the Gauss points), Gauss weights w.
+// the LGL basis at the Gauss points), Gauss weights w.  Every 1D sweep runs in
+// even-odd form (see ConvTab), which halves its multiply-adds.
 //
 // Cell term: u -> S_x -> S_y -> S_z gives u at the m^3 points; the flux
 // F_cj = s_j W u_c u_j is contracted back as
@@ -31,9 +32,9 @@
 //
 // GPU mapping: one workgroup per batch of E consecutive elements.  Phases
 // (barriers between them):
-//   P1  x sweep of the cell (3n^2 pencils per element) and of the y/z
-//       neighbour layers, y sweep of the x-face layers; all inputs straight
-//       from global memory into registers.
+//   P1  x sweep of the cell (n^2 pencil positions per element, three
+//       components each) and of the y/z neighbour layers, y sweep of the
+//       x-face layers; all inputs straight from global memory into registers.
 //   P2  y sweep, in place in LDS, of the cell and the two extra z layers.
 //   P3  per (q1,q2): z sweep into registers, z-face flux, cell flux and the
 //       z back sweep; per (side, q): y- and x-face flux pencils.
@@ -51,26 +52,68 @@
 
 namespace dgmf {
 
+// 1D tables in even-odd form.  The LGL nodes and the Gauss points are
+// symmetric about 1/2, so S[m-1-q][n-1-a] = S[q][a] and
+// G[m-1-q][n-1-a] = -G[q][a].  With x_e[a] = x[a] + x[n-1-a] and
+// x_o[a] = x[a] - x[n-1-a] (a < n/2):
+//   y = S x:      y[q] = E_q + O_q,  y[m-1-q] = E_q - O_q   (q < ceil(m/2))
+//                 E_q = sum_a Sp[q][a] x_e[a] + Sc[q] x[n/2] (n odd),
+//                 O_q = sum_a Sm[q][a] x_o[a],
+//                 Sp/Sm = half sum/difference of S[q][a] and S[q][n-1-a];
+//   y = A^T x     (A = S, sign +1; A = G, sign -1), inputs taken in mirrored
+//                 pairs (x[q], x[m-1-q]), q < m/2, and the middle x[m/2]:
+//                 y[a] = E_a + O_a,  y[n-1-a] = sign (E_a - O_a)  (a < ceil(n/2)),
+//                 E_a = sum_q Tp[q][a] (x[q] + x[m-1-q]) + Tc[a] x[m/2] (m odd),
+//                 O_a = sum_q Tm[q][a] (x[q] - x[m-1-q]),
+//                 Tp/Tm = half sum/difference of A[q][a] and A[m-1-q][a].
+// Each sweep thus takes about half the multiply-adds of the plain product.
 template <int N, int Q, typename T>
 struct ConvTab {
-  T S[Q][N];   // l_a(z_q)
-  T G[Q][N];   // l_a'(z_q)
-  T w[Q];      // Gauss weights on [0,1]
+  static constexpr int NH = N / 2, NC = (N + 1) / 2, QH = Q / 2, QC = (Q + 1) / 2;
+  T Sp[QC][NH], Sm[QC][NH], Sc[QC];   // S, rows q < ceil(m/2)
+  T Tp[QH][NC], Tm[QH][NC], Tc[NC];   // S^T, by input pair q < m/2
+  T Hp[QH][NC], Hm[QH][NC], Hc[NC];   // G^T, by input pair q < m/2
+  T w[Q];                             // Gauss weights on [0,1]
 };
+
+// Even-odd tables from plain row-major S, G (m x n) and w.
+template <int N, int Q, typename T>
+constexpr ConvTab<N, Q, T> make_conv_tab(const double* S, const double* G, const double* w) {
+  using Tb = ConvTab<N, Q, T>;
+  Tb t{};
+  for (int q = 0; q < Tb::QC; ++q) {
+    for (int a = 0; a < Tb::NH; ++a) {
+      t.Sp[q][a] = (T)(0.5 * (S[q * N + a] + S[q * N + N - 1 - a]));
+      t.Sm[q][a] = (T)(0.5 * (S[q * N + a] - S[q * N + N - 1 - a]));
+    }
+    t.Sc[q] = (N % 2) ? (T)S[q * N + Tb::NH] : T(0);
+  }
+  for (int q = 0; q < Tb::QH; ++q)
+    for (int a = 0; a < Tb::NC; ++a) {
+      t.Tp[q][a] = (T)(0.5 * (S[q * N + a] + S[(Q - 1 - q) * N + a]));
+      t.Tm[q][a] = (T)(0.5 * (S[q * N + a] - S[(Q - 1 - q) * N + a]));
+      t.Hp[q][a] = (T)(0.5 * (G[q * N + a] + G[(Q - 1 - q) * N + a]));
+      t.Hm[q][a] = (T)(0.5 * (G[q * N + a] - G[(Q - 1 - q) * N + a]));
+    }
+  for (int a = 0; a < Tb::NC; ++a) {
+    t.Tc[a] = (Q % 2) ? (T)S[Tb::QH * N + a] : T(0);
+    t.Hc[a] = (Q % 2) ? (T)G[Tb::QH * N + a] : T(0);
+  }
+  for (int q = 0; q < Q; ++q) t.w[q] = (T)w[q];
+  return t;
+}
 
 // The tables of degree N-1 with Q Gauss points as compile-time constants.
 template <int N, int Q, typename T>
 constexpr ConvTab<N, Q, T> conv_tab_ct() {
   constexpr ct::Tables<N, Q> d{};
-  ConvTab<N, Q, T> t{};
-  for (int q = 0; q < Q; ++q) {
+  double S[Q * N] = {}, G[Q * N] = {};
+  for (int q = 0; q < Q; ++q)
     for (int a = 0; a < N; ++a) {
-      t.S[q][a] = (T)d.S[q][a];
-      t.G[q][a] = (T)d.G[q][a];
+      S[q * N + a] = d.S[q][a];
+      G[q * N + a] = d.G[q][a];
     }
-    t.w[q] = (T)d.w[q];
-  }
-  return t;
+  return make_conv_tab<N, Q, T>(S, G, d.w);
 }
 
 // Where the kernels read the tables from.  FP32: compile-time constants, which
@@ -144,8 +187,11 @@ struct ConvShape {
   // about 52 KB per workgroup (three per CU), 1..16 elements
   static constexpr int E0 = (52 * 1024) / BYTES;
   static constexpr int E = E0 < 1 ? 1 : (E0 > 16 ? 16 : E0);
-  // per-component mode keeps one z pencil per thread in registers
-  static constexpr int TH = (E * Q * Q > 256) ? ((E * Q * Q + 63) / 64) * 64 : 256;
+  // per-component mode keeps one z pencil per thread in registers; at the
+  // highest degrees (one element, one workgroup per CU) 512 threads hide
+  // more latency, below that a larger group only lowers the register limit
+  static constexpr int TH0 = (E * Q * Q > 256) ? ((E * Q * Q + 63) / 64) * 64 : 256;
+  static constexpr int TH = (E == 1 && Q >= 16) ? 512 : TH0;
   static_assert(E * PER * SZ <= 160 * 1024, "convective LDS footprint exceeds 160 KB");
 };
 
@@ -155,18 +201,61 @@ __device__ __forceinline__ void load_pencil(const T* __restrict__ p, int stride,
   for (int i = 0; i < N; ++i) in[i] = p[i * stride];
 }
 
-// dst[q*stride] = sum_a S[q][a] in[a]   (and the same into dst2 if given)
-template <int N, int Q, typename T, typename Tab>
-__device__ __forceinline__ void interp_store(const Tab& t, const T (&in)[N], T* dst, int stride, T* dst2) {
+// y = S x in even-odd form; st(q, y[q]) receives every output.
+template <int N, int Q, typename T, typename Tab, typename St>
+__device__ __forceinline__ void eo_interp(const Tab& t, const T (&x)[N], St&& st) {
+  constexpr int NH = N / 2, QH = Q / 2, QC = (Q + 1) / 2;
+  T xe[NH], xo[NH];
 #pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    T acc = t.S[q][0] * in[0];
+  for (int a = 0; a < NH; ++a) {
+    xe[a] = x[a] + x[N - 1 - a];
+    xo[a] = x[a] - x[N - 1 - a];
+  }
 #pragma unroll
-    for (int a = 1; a < N; ++a) acc = fmadd(t.S[q][a], in[a], acc);
-    dst[q * stride] = acc;
-    if (dst2) dst2[q] = acc;
+  for (int q = 0; q < QC; ++q) {
+    T e = t.Sp[q][0] * xe[0], o = t.Sm[q][0] * xo[0];
+#pragma unroll
+    for (int a = 1; a < NH; ++a) {
+      e = fmadd(t.Sp[q][a], xe[a], e);
+      o = fmadd(t.Sm[q][a], xo[a], o);
+    }
+    if constexpr (N % 2 == 1) e = fmadd(t.Sc[q], x[NH], e);
+    st(q, e + o);
+    if (q < QH) st(Q - 1 - q, e - o);
   }
 }
+
+// y = A^T x in even-odd form (A = S: SIGN = +1, A = G: SIGN = -1), fed with
+// mirrored input pairs and, for odd m, the middle input.
+template <int N, typename T, int SIGN>
+struct EoT {
+  static constexpr int NH = N / 2, NC = (N + 1) / 2;
+  T e[NC], o[NC];
+  __device__ __forceinline__ void zero() {
+#pragma unroll
+    for (int a = 0; a < NC; ++a) e[a] = o[a] = T(0);
+  }
+  template <typename Row>
+  __device__ __forceinline__ void pair(const Row& p, const Row& m, T xq, T xr) {
+    const T xe = xq + xr, xo = xq - xr;
+#pragma unroll
+    for (int a = 0; a < NC; ++a) {
+      e[a] = fmadd(p[a], xe, e[a]);
+      o[a] = fmadd(m[a], xo, o[a]);
+    }
+  }
+  template <typename Row>
+  __device__ __forceinline__ void mid(const Row& c, T x) {
+#pragma unroll
+    for (int a = 0; a < NC; ++a) e[a] = fmadd(c[a], x, e[a]);
+  }
+  // output a (a compile-time index after unrolling)
+  __device__ __forceinline__ T out(int a) const {
+    if (a < NC) return e[a] + o[a];
+    const int b = N - 1 - a;
+    return SIGN > 0 ? e[b] - o[b] : o[b] - e[b];
+  }
+};
 
 // LLF flux of component values um/up (own/neighbour) with normal velocities
 // unm/unp (already signed by the outward normal), scaled by wgt.
@@ -181,6 +270,7 @@ convective_kernel(const T* __restrict__ u, T* __restrict__ r, MeshArgs mesh,
                   const ConvTab<N, Q, T>* __restrict__ tab, ConvScal<T> sc) {
   using Sh = ConvShape<N, Q, (int)sizeof(T)>;
   constexpr int N2 = Sh::N2, N3 = Sh::N3, MP = Sh::MP, COLS = Sh::COLS, LAYER = Sh::LAYER;
+  constexpr int NH = N / 2, QH = Q / 2;
   constexpr int PER = Sh::per(ALLC);
   constexpr int FYo = Sh::slots(ALLC) * COLS;
   constexpr int FXo = FYo + Sh::FL;
@@ -288,8 +378,16 @@ convective_kernel(const T* __restrict__ u, T* __restrict__ r, MeshArgs mesh,
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
           CONV_TABLES(t);
-          interp_store<N, Q, T>(t, in[i][j], lds + d1[i] + j * ds[i], 1,
-                                d2[i] >= 0 ? lds + d2[i] + j * LAYER : (T*)nullptr);
+          T* dst = lds + d1[i] + j * ds[i];
+          if (d2[i] >= 0) {
+            T* dst2 = lds + d2[i] + j * LAYER;
+            eo_interp<N, Q, T>(t, in[i][j], [&](int q, T v) {
+              dst[q] = v;
+              dst2[q] = v;
+            });
+          } else {
+            eo_interp<N, Q, T>(t, in[i][j], [&](int q, T v) { dst[q] = v; });
+          }
         }
       }
     }
@@ -309,7 +407,7 @@ convective_kernel(const T* __restrict__ u, T* __restrict__ r, MeshArgs mesh,
       T in[N];
 #pragma unroll
       for (int b = 0; b < N; ++b) in[b] = p[MP * b];
-      interp_store<N, Q, T>(t, in, p, MP, (T*)nullptr);
+      eo_interp<N, Q, T>(t, in, [&](int q, T v) { p[MP * q] = v; });
     }
   }
   __syncthreads();
@@ -321,10 +419,44 @@ convective_kernel(const T* __restrict__ u, T* __restrict__ r, MeshArgs mesh,
   T Fz[2][3];
   T w12 = 0;
   T* colp = lds;   // this thread's column (per-component mode)
+  // z back sweep of component j of the thread's pencil into slot set jj:
+  // S^T_z F_jx, S^T_z F_jy, G^T_z F_jz (+ z-face terms at the end nodes)
+  auto zback = [&](int j, int jj, T* col) {
+    CONV_TABLES(t);
+    EoT<N, T, 1> ax, ay;
+    EoT<N, T, -1> az;
+    ax.zero();
+    ay.zero();
+    az.zero();
+#pragma unroll
+    for (int q = 0; q < QH; ++q) {
+      const int rq = Q - 1 - q;
+      const T uq = t.w[q] * Uz[j][q], ur = t.w[q] * Uz[j][rq];   // w[m-1-q] = w[q]
+      ax.pair(t.Tp[q], t.Tm[q], uq * Uz[0][q], ur * Uz[0][rq]);
+      ay.pair(t.Tp[q], t.Tm[q], uq * Uz[1][q], ur * Uz[1][rq]);
+      az.pair(t.Hp[q], t.Hm[q], uq * Uz[2][q], ur * Uz[2][rq]);
+    }
+    if constexpr (Q % 2 == 1) {
+      const T um = t.w[QH] * Uz[j][QH];
+      ax.mid(t.Tc, um * Uz[0][QH]);
+      ay.mid(t.Tc, um * Uz[1][QH]);
+      az.mid(t.Hc, um * Uz[2][QH]);
+    }
+    // cell scalings s_d w_q1 w_q2 applied once per output
+    const T s0 = sc.cell[0] * w12, s1 = sc.cell[1] * w12, s2 = sc.cell[2] * w12;
+#pragma unroll
+    for (int c = 0; c < N; ++c) {
+      T oz = s2 * az.out(c);
+      if (c == 0) oz += Fz[0][j];
+      if (c == N - 1) oz += Fz[1][j];
+      col[((jj * 3 + 0) * N + c) * COLS] = s0 * ax.out(c);
+      col[((jj * 3 + 1) * N + c) * COLS] = s1 * ay.out(c);
+      col[((jj * 3 + 2) * N + c) * COLS] = oz;
+    }
+  };
   {
     constexpr int nH = E * 4 * Q;
     for (int w = tid; w < nCell + nH; w += TH) {
-      CONV_TABLES(t);
       if (w < nCell) {
         const int le = w / (Q * Q), qq = w - le * (Q * Q);
         if (le >= ne) continue;
@@ -336,16 +468,17 @@ convective_kernel(const T* __restrict__ u, T* __restrict__ r, MeshArgs mesh,
         for (int j = 0; j < 3; ++j)
 #pragma unroll
           for (int c = 0; c < N + 2; ++c) v[j][c] = col[(j * (N + 2) + c) * COLS];
-#pragma unroll
-        for (int q = 0; q < Q; ++q)
+        {
+          CONV_TABLES(t);
 #pragma unroll
           for (int j = 0; j < 3; ++j) {
-            T acc = t.S[q][0] * v[j][1];
+            T x[N];
 #pragma unroll
-            for (int c = 1; c < N; ++c) acc = fmadd(t.S[q][c], v[j][c + 1], acc);
-            Uz[j][q] = acc;
+            for (int c = 0; c < N; ++c) x[c] = v[j][c + 1];
+            eo_interp<N, Q, T>(t, x, [&](int q, T val) { Uz[j][q] = val; });
           }
-        w12 = t.w[q1] * t.w[q2];
+          w12 = t.w[q1] * t.w[q2];
+        }
         const T wz = w12 * sc.area[2];
         {   // z faces: side 0 (own layer c=0, neighbour below), side 1 (c=n-1, above)
           const T unm0 = -v[2][1], unp0 = -v[2][0];
@@ -361,87 +494,86 @@ convective_kernel(const T* __restrict__ u, T* __restrict__ r, MeshArgs mesh,
         colp = col;
         // z back sweep: all components (ALLC) or component 0
 #pragma unroll
-        for (int j = 0; j < (ALLC ? 3 : 1); ++j) {
-          T ox[N], oy[N], oz[N];
-#pragma unroll
-          for (int c = 0; c < N; ++c) ox[c] = oy[c] = oz[c] = 0;
-#pragma unroll
-          for (int q = 0; q < Q; ++q) {
-            const T uc = t.w[q] * Uz[j][q];
-            const T fx = uc * Uz[0][q], fy = uc * Uz[1][q], fz = uc * Uz[2][q];
-#pragma unroll
-            for (int c = 0; c < N; ++c) {
-              ox[c] = fmadd(t.S[q][c], fx, ox[c]);
-              oy[c] = fmadd(t.S[q][c], fy, oy[c]);
-              oz[c] = fmadd(t.G[q][c], fz, oz[c]);
-            }
-          }
-          {   // cell scalings s_d w_q1 w_q2 applied once per output
-            const T s0 = sc.cell[0] * w12, s1 = sc.cell[1] * w12, s2 = sc.cell[2] * w12;
-#pragma unroll
-            for (int c = 0; c < N; ++c) {
-              ox[c] *= s0;
-              oy[c] *= s1;
-              oz[c] *= s2;
-            }
-          }
-          oz[0] += Fz[0][j];
-          oz[N - 1] += Fz[1][j];
-#pragma unroll
-          for (int c = 0; c < N; ++c) {
-            col[((j * 3 + 0) * N + c) * COLS] = ox[c];
-            col[((j * 3 + 1) * N + c) * COLS] = oy[c];
-            col[((j * 3 + 2) * N + c) * COLS] = oz[c];
-          }
-        }
+        for (int j = 0; j < (ALLC ? 3 : 1); ++j) zback(j, j, col);
       } else {   // face-flux pencil: fam 0 = y face (q = q1), 1 = x face (q = q2)
         const int h = w - nCell;
         const int le = h / (4 * Q);
         if (le >= ne) continue;
+        CONV_TABLES(t);
         int rem = h - le * 4 * Q;
         const int fam = rem / (2 * Q);
         rem -= fam * 2 * Q;
         const int s = rem / Q, q = rem - s * Q;
         T* F = lds + le * PER + (fam ? FXo : FYo) + q;
-        T own[3][N], nbr[3][N], acc[3][N];
+        // even-odd parts of the own (0) and neighbour (1) pencils of each component
+        T xe[2][3][NH], xo[2][3][NH], xm[2][3];
 #pragma unroll
-        for (int j = 0; j < 3; ++j)
+        for (int sg = 0; sg < 2; ++sg)
 #pragma unroll
-          for (int c = 0; c < N; ++c) {
-            own[j][c] = F[((0 * 2 + s) * 3 + j) * LAYER + c * Q];
-            nbr[j][c] = F[((1 * 2 + s) * 3 + j) * LAYER + c * Q];
-            acc[j][c] = 0;
+          for (int j = 0; j < 3; ++j) {
+            T x[N];
+#pragma unroll
+            for (int c = 0; c < N; ++c) x[c] = F[((sg * 2 + s) * 3 + j) * LAYER + c * Q];
+#pragma unroll
+            for (int a = 0; a < NH; ++a) {
+              xe[sg][j][a] = x[a] + x[N - 1 - a];
+              xo[sg][j][a] = x[a] - x[N - 1 - a];
+            }
+            xm[sg][j] = (N % 2) ? x[NH] : T(0);
           }
+        EoT<N, T, 1> acc[3];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) acc[j].zero();
         const T sgn = s ? T(1) : T(-1);
         const T wq = t.w[q] * (fam ? sc.area[0] : sc.area[1]);
-#pragma unroll
-        for (int q3 = 0; q3 < Q; ++q3) {
-          T um[3], up[3];
-#pragma unroll
-          for (int j = 0; j < 3; ++j) {
-            T a = t.S[q3][0] * own[j][0], b = t.S[q3][0] * nbr[j][0];
-#pragma unroll
-            for (int c = 1; c < N; ++c) {
-              a = fmadd(t.S[q3][c], own[j][c], a);
-              b = fmadd(t.S[q3][c], nbr[j][c], b);
-            }
-            um[j] = a;
-            up[j] = b;
-          }
+        // fluxes f[j] at a face point with traces um (own), up (neighbour)
+        auto flux = [&](const T (&um)[3], const T (&up)[3], T wgt, T (&f)[3]) {
           const T unm = sgn * (fam ? um[0] : um[1]), unp = sgn * (fam ? up[0] : up[1]);
           const T lam = fmax(fabs(unm), fabs(unp));
-          const T wgt = wq * t.w[q3];
+#pragma unroll
+          for (int j = 0; j < 3; ++j) f[j] = llf(um[j], up[j], unm, unp, lam, sc.lf, wgt);
+        };
+#pragma unroll
+        for (int q3 = 0; q3 < (Q + 1) / 2; ++q3) {
+          // traces at q3 and at its mirror m-1-q3
+          T umq[3], upq[3], umr[3], upr[3];
 #pragma unroll
           for (int j = 0; j < 3; ++j) {
-            const T f = llf(um[j], up[j], unm, unp, lam, sc.lf, wgt);
+            T e0v = t.Sp[q3][0] * xe[0][j][0], o0v = t.Sm[q3][0] * xo[0][j][0];
+            T e1v = t.Sp[q3][0] * xe[1][j][0], o1v = t.Sm[q3][0] * xo[1][j][0];
 #pragma unroll
-            for (int c = 0; c < N; ++c) acc[j][c] = fmadd(t.S[q3][c], f, acc[j][c]);
+            for (int a = 1; a < NH; ++a) {
+              e0v = fmadd(t.Sp[q3][a], xe[0][j][a], e0v);
+              o0v = fmadd(t.Sm[q3][a], xo[0][j][a], o0v);
+              e1v = fmadd(t.Sp[q3][a], xe[1][j][a], e1v);
+              o1v = fmadd(t.Sm[q3][a], xo[1][j][a], o1v);
+            }
+            if constexpr (N % 2 == 1) {
+              e0v = fmadd(t.Sc[q3], xm[0][j], e0v);
+              e1v = fmadd(t.Sc[q3], xm[1][j], e1v);
+            }
+            umq[j] = e0v + o0v;
+            upq[j] = e1v + o1v;
+            umr[j] = e0v - o0v;
+            upr[j] = e1v - o1v;
+          }
+          const T wgt = wq * t.w[q3];
+          T fq[3];
+          flux(umq, upq, wgt, fq);
+          if (q3 < QH) {
+            T fr[3];
+            flux(umr, upr, wgt, fr);
+#pragma unroll
+            for (int j = 0; j < 3; ++j) acc[j].pair(t.Tp[q3], t.Tm[q3], fq[j], fr[j]);
+          } else {
+#pragma unroll
+            for (int j = 0; j < 3; ++j) acc[j].mid(t.Tc, fq[j]);
           }
         }
 #pragma unroll
         for (int j = 0; j < 3; ++j)
 #pragma unroll
-          for (int c = 0; c < N; ++c) F[((0 * 2 + s) * 3 + j) * LAYER + c * Q] = acc[j][c];
+          for (int c = 0; c < N; ++c) F[((0 * 2 + s) * 3 + j) * LAYER + c * Q] = acc[j].out(c);
       }
     }
   }
@@ -463,24 +595,33 @@ convective_kernel(const T* __restrict__ u, T* __restrict__ r, MeshArgs mesh,
         T* L = lds + le * PER;
         T* tb = L + q1;
         const int sx = ((jj * 3 + 0) * N + cz) * COLS, sy = sx + N * COLS, sz = sx + 2 * N * COLS;
-        T v1[N], v2[N];
+        // v1 = S^T_y T_x, v2 = G^T_y T_y + S^T_y T_z
+        EoT<N, T, 1> v1, v2s;
+        EoT<N, T, -1> v2g;
+        v1.zero();
+        v2s.zero();
+        v2g.zero();
 #pragma unroll
-        for (int b = 0; b < N; ++b) v1[b] = v2[b] = 0;
-#pragma unroll
-        for (int q2 = 0; q2 < Q; ++q2) {
-          const T tx = tb[sx + MP * q2], ty = tb[sy + MP * q2], tz = tb[sz + MP * q2];
-#pragma unroll
-          for (int b = 0; b < N; ++b) {
-            v1[b] = fmadd(t.S[q2][b], tx, v1[b]);
-            v2[b] = fmadd(t.G[q2][b], ty, fmadd(t.S[q2][b], tz, v2[b]));
-          }
+        for (int q2 = 0; q2 < QH; ++q2) {
+          const int r2 = Q - 1 - q2;
+          v1.pair(t.Tp[q2], t.Tm[q2], tb[sx + MP * q2], tb[sx + MP * r2]);
+          v2g.pair(t.Hp[q2], t.Hm[q2], tb[sy + MP * q2], tb[sy + MP * r2]);
+          v2s.pair(t.Tp[q2], t.Tm[q2], tb[sz + MP * q2], tb[sz + MP * r2]);
         }
-        v2[0] += L[FYo + ((0 * 2 + 0) * 3 + j) * LAYER + cz * Q + q1];
-        v2[N - 1] += L[FYo + ((0 * 2 + 1) * 3 + j) * LAYER + cz * Q + q1];
+        if constexpr (Q % 2 == 1) {
+          v1.mid(t.Tc, tb[sx + MP * QH]);
+          v2g.mid(t.Hc, tb[sy + MP * QH]);
+          v2s.mid(t.Tc, tb[sz + MP * QH]);
+        }
+        const T f0 = L[FYo + ((0 * 2 + 0) * 3 + j) * LAYER + cz * Q + q1];
+        const T f1 = L[FYo + ((0 * 2 + 1) * 3 + j) * LAYER + cz * Q + q1];
 #pragma unroll
         for (int b = 0; b < N; ++b) {
-          tb[sx + MP * b] = v1[b];
-          tb[sy + MP * b] = v2[b];
+          T o2 = v2g.out(b) + v2s.out(b);
+          if (b == 0) o2 += f0;
+          if (b == N - 1) o2 += f1;
+          tb[sx + MP * b] = v1.out(b);
+          tb[sy + MP * b] = o2;
         }
       } else {   // x-face terms: integrate in y
         const int v = w - nYc;
@@ -491,18 +632,14 @@ convective_kernel(const T* __restrict__ u, T* __restrict__ r, MeshArgs mesh,
         const int jj = ALLC ? j : 0;
         T* L = lds + le * PER;
         const T* xf = L + FXo + ((0 * 2 + s) * 3 + j) * LAYER + cz * Q;
-        T o[N];
+        EoT<N, T, 1> o;
+        o.zero();
 #pragma unroll
-        for (int b = 0; b < N; ++b) o[b] = 0;
-#pragma unroll
-        for (int q2 = 0; q2 < Q; ++q2) {
-          const T x = xf[q2];
-#pragma unroll
-          for (int b = 0; b < N; ++b) o[b] = fmadd(t.S[q2][b], x, o[b]);
-        }
+        for (int q2 = 0; q2 < QH; ++q2) o.pair(t.Tp[q2], t.Tm[q2], xf[q2], xf[Q - 1 - q2]);
+        if constexpr (Q % 2 == 1) o.mid(t.Tc, xf[QH]);
         T* xr = L + XRo + ((jj * 2 + s) * N + cz) * N;
 #pragma unroll
-        for (int b = 0; b < N; ++b) xr[b] = o[b];
+        for (int b = 0; b < N; ++b) xr[b] = o.out(b);
       }
     }
   };
@@ -518,21 +655,30 @@ convective_kernel(const T* __restrict__ u, T* __restrict__ r, MeshArgs mesh,
       const T* L = lds + le * PER;
       const T* v1 = L + ((jj * 3 + 0) * N + cz) * COLS + MP * b;
       const T* v2 = v1 + N * COLS;
-      T o[N];
+      // o = G^T_x v1 + S^T_x v2
+      EoT<N, T, -1> og;
+      EoT<N, T, 1> os;
+      og.zero();
+      os.zero();
 #pragma unroll
-      for (int a = 0; a < N; ++a) o[a] = 0;
-#pragma unroll
-      for (int q1 = 0; q1 < Q; ++q1) {
-        const T x1 = v1[q1], x2 = v2[q1];
-#pragma unroll
-        for (int a = 0; a < N; ++a) o[a] = fmadd(t.G[q1][a], x1, fmadd(t.S[q1][a], x2, o[a]));
+      for (int q1 = 0; q1 < QH; ++q1) {
+        og.pair(t.Hp[q1], t.Hm[q1], v1[q1], v1[Q - 1 - q1]);
+        os.pair(t.Tp[q1], t.Tm[q1], v2[q1], v2[Q - 1 - q1]);
+      }
+      if constexpr (Q % 2 == 1) {
+        og.mid(t.Hc, v1[QH]);
+        os.mid(t.Tc, v2[QH]);
       }
       const T* xr = L + XRo + (jj * 2 * N + cz) * N + b;
-      o[0] += xr[0];
-      o[N - 1] += xr[N2];
+      const T x0 = xr[0], x1 = xr[N2];
       T* g = r + j * cs + (size_t)(e0 + le) * N3 + N * bc;
 #pragma unroll
-      for (int a = 0; a < N; ++a) g[a] = o[a];
+      for (int a = 0; a < N; ++a) {
+        T o = og.out(a) + os.out(a);
+        if (a == 0) o += x0;
+        if (a == N - 1) o += x1;
+        g[a] = o;
+      }
     }
   };
 
@@ -545,40 +691,7 @@ convective_kernel(const T* __restrict__ u, T* __restrict__ r, MeshArgs mesh,
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
       if (j > 0) {
-        if (own_cell) {
-          CONV_TABLES(t);
-          T ox[N], oy[N], oz[N];
-#pragma unroll
-          for (int c = 0; c < N; ++c) ox[c] = oy[c] = oz[c] = 0;
-#pragma unroll
-          for (int q = 0; q < Q; ++q) {
-            const T uc = t.w[q] * Uz[j][q];
-            const T fx = uc * Uz[0][q], fy = uc * Uz[1][q], fz = uc * Uz[2][q];
-#pragma unroll
-            for (int c = 0; c < N; ++c) {
-              ox[c] = fmadd(t.S[q][c], fx, ox[c]);
-              oy[c] = fmadd(t.S[q][c], fy, oy[c]);
-              oz[c] = fmadd(t.G[q][c], fz, oz[c]);
-            }
-          }
-          {   // cell scalings s_d w_q1 w_q2 applied once per output
-            const T s0 = sc.cell[0] * w12, s1 = sc.cell[1] * w12, s2 = sc.cell[2] * w12;
-#pragma unroll
-            for (int c = 0; c < N; ++c) {
-              ox[c] *= s0;
-              oy[c] *= s1;
-              oz[c] *= s2;
-            }
-          }
-          oz[0] += Fz[0][j];
-          oz[N - 1] += Fz[1][j];
-#pragma unroll
-          for (int c = 0; c < N; ++c) {
-            colp[(0 * N + c) * COLS] = ox[c];
-            colp[(1 * N + c) * COLS] = oy[c];
-            colp[(2 * N + c) * COLS] = oz[c];
-          }
-        }
+        if (own_cell) zback(j, 0, colp);
         __syncthreads();
       }
       back_y(j, j + 1);
@@ -608,14 +721,7 @@ static hipError_t launch_conv_nq(const ConvPlan& P, const void* u, void* r, hipS
   sc.lf = (T)P.lf;
   const ConvTab<N, Q, T>* dt = nullptr;   // FP32 kernels use the compile-time tables
   if (sizeof(T) == 8) {
-    ConvTab<N, Q, T> t;
-    for (int q = 0; q < Q; ++q) {
-      for (int a = 0; a < N; ++a) {
-        t.S[q][a] = (T)P.S[q * N + a];
-        t.G[q][a] = (T)P.G[q * N + a];
-      }
-      t.w[q] = (T)P.w[q];
-    }
+    const ConvTab<N, Q, T> t = make_conv_tab<N, Q, T>(P.S.data(), P.G.data(), P.w.data());
     hipError_t err;
     dt = device_table_of("convective", t, &err);
     if (!dt) return err;
