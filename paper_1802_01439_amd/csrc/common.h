@@ -34,32 +34,22 @@ __device__ __forceinline__ int xcd_remap(int b, int G) {
   return x * q + (x < r ? x : r) + (b >> 3);
 }
 
-// Traversal of the element batches.  A batch is a run of E consecutive
-// elements inside one z-plane (plane-linear index j*E .. j*E+E-1, so only the
-// last batch of a plane can be short); planes are numbered pz = comp*Nz + ez.
-// Batches are grouped into strips of S consecutive runs (a few element rows)
-// and a strip is walked plane by plane: logical id L -> (strip, pz, run in
-// strip).  Consecutive ids are x-neighbours, ids S apart are z-neighbours and
-// y-neighbours sit within the same strip, so the neighbour data an element
-// needs was loaded a few dozen workgroups earlier and is still in L2.
-struct Traversal {
-  int PB;   // batches per plane
-  int PZ;   // planes (n_comp * Nz)
-  int S;    // runs per strip
-};
+// A table pointer passed through an empty asm and returned in the constant
+// address space (loads through it are scalar loads).  Loads issued after it
+// cannot be merged with loads of the same entries elsewhere in the kernel, so
+// a kernel that calls it at the start of each phase or loop step loads the
+// table rows it uses when it uses them, instead of having the compiler hoist
+// the whole (loop-invariant) table into scalar registers and spill it.
+template <typename P>
+using const_ptr = const __attribute__((address_space(4))) P*;
 
-__device__ __forceinline__ void strip_order(int L, const Traversal& t, int& j, int& pz) {
-  const int F = t.PB / t.S, R = t.PB - F * t.S;
-  const int full = F * t.S * t.PZ;
-  if (L < full) {
-    const int s = L / (t.S * t.PZ), rem = L - s * t.S * t.PZ;
-    pz = rem / t.S;
-    j = s * t.S + (rem - pz * t.S);
-  } else {
-    const int rem = L - full;
-    pz = rem / R;
-    j = F * t.S + (rem - pz * R);
-  }
+template <typename P>
+__device__ __forceinline__ const_ptr<P> fresh(const P* p) {
+  uint64_t x = (uint64_t)p;
+  asm volatile("" : "+v"(x));
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(x >> 32));
+  return (const_ptr<P>)(((uint64_t)hi << 32) | lo);
 }
 
 // Host-side launch status: 0 or a hipError_t from the launch.

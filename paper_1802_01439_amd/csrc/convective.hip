@@ -117,25 +117,9 @@ constexpr ConvTab<N, Q, T> conv_tab_ct() {
 }
 
 // Where the kernels read the tables from.  FP32: compile-time constants, which
-// become literal operands of the FMAs.  FP64: a table in device memory, read
-// with scalar loads through a pointer laundered by an empty asm (and returned
-// in the constant address space), so that loads issued after it cannot be
-// merged with loads of the same entries elsewhere in the kernel: each phase
-// loads the rows it uses when it uses them instead of keeping the table live
-// in scalar registers (64-bit constants would each take a scalar register pair
-// and spill at high degree).
-template <typename P>
-using const_ptr = const __attribute__((address_space(4))) P*;
-
-template <typename P>
-__device__ __forceinline__ const_ptr<P> fresh(const P* p) {
-  uint64_t x = (uint64_t)p;
-  asm volatile("" : "+v"(x));
-  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
-  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(x >> 32));
-  return (const_ptr<P>)(((uint64_t)hi << 32) | lo);
-}
-
+// become literal operands of the FMAs.  FP64: a table in device memory read
+// through fresh() (common.h) in every phase (64-bit constants would each take
+// a scalar register pair and spill at high degree).
 template <int N, int Q, typename T>
 __device__ __forceinline__ decltype(auto) conv_pick(const ConvTab<N, Q, T>& ct, const ConvTab<N, Q, T>* tab) {
   if constexpr (sizeof(T) == 4) return (ct);
