@@ -3,7 +3,7 @@
 //
 // Linearising R_c = -sum_j s_j (d_j phi, u_c u_j) + faces (Sec. 3.2, weak
 // form of c_h) and transposing against the coefficient vector w gives
-//   cell:  g_k = (phi, P_k),  P_k = sum_j c_j u_j d_j w_k + c_k sum_c u_c d_k w_c,
+//   cell:  g_k = (phi, W P_k),  P_k = sum_j c_j u_j d_j w_k + c_k sum_c u_c d_k w_c,
 //          c_j = -vol/h_j (reference derivatives), W the Gauss weights,
 //   faces: g_k += area * (phi, sum_i (w-_i - w+_i) dF*_i/du-_k), with
 //          dF*_i/du-_k = 1/2 (delta_ik u-.n + u-_i n_k)
@@ -12,387 +12,568 @@
 // Each element differentiates only through its own traces u-, so every
 // element writes its own coefficients (no atomics).
 //
-// Sum factorisation: u -> Sx Sy (3 fields), w -> (Sx,Gx) then (Sy,Gy) giving
-// the partial fields of d_x w, d_y w and the Sx Sy w field that G_z turns into
-// d_z w (9 fields); per (x,y) Gauss pencil the z-direction interpolation, P_k
-// and the S^T_z back-contraction run in registers; then S^T_y and S^T_x.
-// Faces as in the forward operator: per direction, own/neighbour traces of u
-// and w are interpolated to the face Gauss points, combined pointwise and
-// integrated back onto the face nodes.
+// Same organisation as the convective kernel (conv_common.h holds the
+// even-odd tables and sweeps):
+//   P1  x sweeps from global memory: u -> S_x u; w -> S_x w and G_x w; the
+//       y/z neighbour layers of u and w -> S_x; the x-face layers -> S_y.
+//   P2  y sweeps in place: S_y S_x u, S_y S_x w (and G_y S_x w beside it),
+//       S_y G_x w; the two extra z layers of u and w come along.
+//   P3  per (q1,q2) z pencil: u, d_x w, d_y w, d_z w at the m Gauss points
+//       (S_z, S_z, S_z, G_z), P_k, and the back sweep S^T_z W P_k, with the
+//       z-face terms added at the end nodes; per (side, q) face pencil of the
+//       y and x faces: traces of u and w, the transposed flux derivative at
+//       the m face points, and S^T_z.
+//   Y   S^T_y (in place) plus the y-face terms; S^T_y of the x-face terms.
+//   X   S^T_x plus the x-face terms, write-out.
+// The back sweeps use S^T only, so all three components fit at once.
+#include <cmath>
+
 #include "api_internal.h"
 #include "common.h"
+#include "conv_common.h"
 #include "ops.h"
 
 namespace dgmf {
 
-template <int N, int Q, typename T>
-struct VjpTab {
-  T S[Q][N];
-  T G[Q][N];
-  T w[Q];
-};
-
-template <typename T>
-struct VjpScal {
-  T cell[3];   // -vol/h_j
-  T area[3];   // vol/h_d
-  T lf;
-};
-
-template <int N, int Q, typename T>
-struct VjpCfg {
+// LDS layout of one element (units of T); column blocks (q1, q2) with q1
+// pitch MP as in the convective kernel.
+//   slots [0, 3(n+2)):         U_j, S_y S_x u_j at z layer c in -1..n
+//   slots [3(n+2), 6(n+2)):    WS_j, S_y S_x w_j at z layer c in -1..n
+//   then 3n slots:             WGY_j, G_y S_x w_j
+//   then 3n slots:             WGX_j, S_y G_x w_j
+//   back sweep:                slot k*n + cz holds S^T_z W P_k (+ z faces),
+//                              then S^T_y of it in place (own columns only)
+//   face layers FY, FX:        [sigma][s][f][j][c][q], f = 0 (u), 1 (w); the
+//                              face pencils overwrite (0, s, 0, k) with their
+//                              S^T_z result for component k
+//   XR:                        x-face terms after S^T_y, [k][s][cz][b]
+template <int N, int Q, int SZ>
+struct VjpShape {
   static constexpr int N2 = N * N, N3 = N * N * N;
-  static constexpr int RA0 = 6 * N3 + 30 * N * Q;
-  static constexpr int RA1 = 12 * Q * Q * N;
-  static constexpr int RA2 = 3 * Q * N2;
-  static constexpr int RA = RA0 > RA1 ? (RA0 > RA2 ? RA0 : RA2) : (RA1 > RA2 ? RA1 : RA2);
-  static constexpr int RB = (9 * Q * N2 > 3 * Q * Q * N) ? 9 * Q * N2 : 3 * Q * Q * N;
-  static constexpr int FR = 18 * N2;
-  static constexpr int PER_ELEM = RA + RB + FR;
-  static constexpr int BUDGET = 80 * 1024 / (int)sizeof(T);
-  static constexpr int LDS_MAX = 160 * 1024 / (int)sizeof(T);
-  static constexpr int E = (PER_ELEM <= BUDGET) ? (BUDGET / PER_ELEM) : 1;
-  static constexpr int THREADS = 256;
-  static constexpr bool FITS = E * PER_ELEM <= LDS_MAX;
+  static constexpr int MP = Q | 1;
+  static constexpr int COLS = MP * Q;
+  static constexpr int LAYER = N * Q;
+  static constexpr int SU = 0, SWS = 3 * (N + 2), SWGY = 6 * (N + 2), SWGX = 6 * (N + 2) + 3 * N;
+  static constexpr int SLOTS = 6 * (N + 2) + 6 * N;
+  static constexpr int FL = 24 * LAYER;
+  static constexpr int PER = SLOTS * COLS + 2 * FL + 6 * N2;
+  static constexpr int BYTES = PER * SZ;
+  static constexpr int E0 = (52 * 1024) / BYTES;
+  static constexpr int E = E0 < 1 ? 1 : (E0 > 16 ? 16 : E0);
+  static constexpr int TH = (E * Q * Q >= 96) ? 256 : 128;
+  static constexpr bool FITS = E * PER * SZ <= 160 * 1024;
 };
 
-template <int N>
-__device__ __forceinline__ int vface_node(int d, int dv, int t1, int t2) {
-  return d == 0 ? dv + N * (t1 + N * t2) : (d == 1 ? t1 + N * (dv + N * t2) : t1 + N * (t2 + N * dv));
-}
-
-template <int N, int Q, typename T>
-__global__ void __launch_bounds__(256)
-convective_vjp_kernel(const T* __restrict__ u, const T* __restrict__ wv, T* __restrict__ g,
-                      MeshArgs mesh, const VjpTab<N, Q, T>* __restrict__ tab, VjpScal<T> sc) {
-  const VjpTab<N, Q, T>& t = *tab;
-  using C = VjpCfg<N, Q, T>;
-  constexpr int N2 = C::N2, N3 = C::N3, E = C::E, TH = C::THREADS;
-  __shared__ T RA[E * C::RA];
-  __shared__ T RB[E * C::RB];
-  __shared__ T FRb[E * C::FR];
-
+template <int N, int Q, typename T, int E, int TH>
+__global__ void __launch_bounds__(TH)
+convective_vjp_kernel(const T* __restrict__ u, const T* __restrict__ wv, T* __restrict__ g, MeshArgs mesh,
+                      const ConvTab<N, Q, T>* __restrict__ tab, ConvScal<T> sc) {
+  using Sh = VjpShape<N, Q, (int)sizeof(T)>;
+  constexpr int N2 = Sh::N2, N3 = Sh::N3, MP = Sh::MP, COLS = Sh::COLS, LAYER = Sh::LAYER, PER = Sh::PER;
+  constexpr int NH = N / 2, QH = Q / 2;
+  constexpr int FYo = Sh::SLOTS * COLS, FXo = FYo + Sh::FL, XRo = FXo + Sh::FL;
+  __shared__ T lds[E * PER];
   const int tid = threadIdx.x;
   const int e0 = xcd_remap(blockIdx.x, gridDim.x) * E;
-  const int ne = min(E, mesh.n_el - e0);
+  const int ne = min(E, mesh.n_el - e0);   // items of le >= ne are skipped
   const size_t cs = (size_t)mesh.n_el * N3;
+  const int nxy = mesh.nx * mesh.ny;
+  const int ez0 = e0 / nxy, exy0 = e0 - ez0 * nxy, ey0 = exy0 / mesh.nx, ex0 = exy0 - ey0 * mesh.nx;
+  auto nbr = [&](int le, int d, int s) {
+    int ex = ex0 + le, ey = ey0, ez = ez0;
+    while (ex >= mesh.nx) {
+      ex -= mesh.nx;
+      if (++ey == mesh.ny) {
+        ey = 0;
+        ++ez;
+      }
+    }
+    return neighbor(mesh, ex, ey, ez, d, s);
+  };
+  // offset of face-layer entry (sigma, s, f, j)
+  auto fl = [](int sg, int s, int f, int j) { return (((sg * 2 + s) * 2 + f) * 3 + j) * LAYER; };
 
-  // stage u (fields 0..2) and w (fields 3..5)
-  for (int i = tid; i < ne * 6 * N3; i += TH) {
-    const int le = i / (6 * N3), rem = i - le * 6 * N3, f = rem / N3, node = rem - f * N3;
-    const T* src = f < 3 ? u : wv;
-    RA[le * C::RA + f * N3 + node] = src[(f % 3) * cs + (size_t)(e0 + le) * N3 + node];
-  }
-  __syncthreads();
-
-  // ---------------- faces ----------------
-  for (int d = 0; d < 3; ++d) {
-    // F1: field f = (kind*2 + side)*3 + c, kind 0 = u, 1 = w; side 0 own, 1 neighbour
-    for (int it = tid; it < ne * 24 * N; it += TH) {
-      const int le = it / (24 * N);
-      int rem = it - le * 24 * N;
-      const int j = rem % N;
-      rem /= N;
-      const int f = rem % 12, s = rem / 12;
-      const int c = f % 3, side = (f / 3) % 2, kind = f / 6;
-      T in[N];
-      if (side == 0) {
-        const T* A = RA + le * C::RA + (kind * 3 + c) * N3;
+  // ---------------- P1: x sweeps from global (all loads first) ----------------
+  {
+    constexpr int nM = E * N2, nL = E * 4 * N, nX = E * 4 * N;
+    constexpr int total = nM + nL + nX;
+    constexpr int NI1 = (total + TH - 1) / TH;
+    // kind 0: cell pencil, 1: y/z neighbour layer, 2: x-face layer
+    T in[NI1][2][3][N];
+    int kind[NI1], le_[NI1], a1[NI1], a2[NI1], a3[NI1];
 #pragma unroll
-        for (int i = 0; i < N; ++i) in[i] = A[vface_node<N>(d, s ? N - 1 : 0, i, j)];
+    for (int i = 0; i < NI1; ++i) {
+      const int w = tid + i * TH;
+      kind[i] = -1;
+      if (w >= total) continue;
+      size_t off;
+      int sstride = 1;
+      if (w < nM) {
+        const int le = w / N2, bc = w - le * N2;
+        if (le >= ne) continue;
+        kind[i] = 0;
+        le_[i] = le;
+        a1[i] = bc;
+        off = (size_t)(e0 + le) * N3 + N * bc;
+      } else if (w < nM + nL) {
+        const int v = w - nM;
+        const int le = v / (4 * N);
+        if (le >= ne) continue;
+        const int rem = v - le * 4 * N;
+        const int isz = rem / (2 * N), r2 = rem - isz * 2 * N;
+        const int s = r2 / N, p = r2 - s * N;
+        kind[i] = 1;
+        le_[i] = le;
+        a1[i] = isz;
+        a2[i] = s;
+        a3[i] = p;
+        const int nb = nbr(le, isz ? 2 : 1, s);
+        const int lay = s ? 0 : N - 1;   // neighbour's facing layer
+        off = (size_t)nb * N3 + (isz ? N * (p + N * lay) : N * (lay + N * p));
       } else {
-        const int e = e0 + le;
-        const int ex = e % mesh.nx, ey = (e / mesh.nx) % mesh.ny, ez = e / (mesh.nx * mesh.ny);
-        const T* src = (kind == 0 ? u : wv) + c * cs + (size_t)neighbor(mesh, ex, ey, ez, d, s) * N3;
-#pragma unroll
-        for (int i = 0; i < N; ++i) in[i] = src[vface_node<N>(d, s ? 0 : N - 1, i, j)];
+        const int v = w - nM - nL;
+        const int le = v / (4 * N);
+        if (le >= ne) continue;
+        const int rem = v - le * 4 * N;
+        const int sg = rem / (2 * N), r2 = rem - sg * 2 * N;
+        const int s = r2 / N, c = r2 - s * N;
+        kind[i] = 2;
+        le_[i] = le;
+        a1[i] = sg;
+        a2[i] = s;
+        a3[i] = c;
+        int e = e0 + le, a = s ? N - 1 : 0;
+        if (sg) {
+          e = nbr(le, 0, s);
+          a = s ? 0 : N - 1;
+        }
+        sstride = N;
+        off = (size_t)e * N3 + a + N2 * c;
       }
-      T* FA = RA + le * C::RA + 6 * N3 + ((s * 12 + f) * N + j) * Q;
 #pragma unroll
-      for (int q = 0; q < Q; ++q) {
-        T acc = t.S[q][0] * in[0];
-#pragma unroll
-        for (int i = 1; i < N; ++i) acc = fmadd(t.S[q][i], in[i], acc);
-        FA[q] = acc;
+      for (int j = 0; j < 3; ++j) {
+        load_pencil<N, Q, T>(u + j * cs + off, sstride, in[i][0][j]);
+        load_pencil<N, Q, T>(wv + j * cs + off, sstride, in[i][1][j]);
       }
     }
-    __syncthreads();
-    // F2: per face column q1: along t2, pointwise adjoint flux, back along t2
-    for (int it = tid; it < ne * 2 * Q; it += TH) {
-      const int le = it / (2 * Q);
-      const int rem = it - le * 2 * Q;
-      const int s = rem / Q, q1 = rem % Q;
-      const T* FA = RA + le * C::RA + 6 * N3 + (s * 12) * N * Q + q1;
-      T acc[3][N];
 #pragma unroll
-      for (int k = 0; k < 3; ++k)
+    for (int i = 0; i < NI1; ++i) {
+      if (kind[i] < 0) continue;
+      T* L = lds + le_[i] * PER;
 #pragma unroll
-        for (int j = 0; j < N; ++j) acc[k][j] = 0;
-      const T sgn = s ? T(1) : T(-1);
-      const T wq1 = t.w[q1] * sc.area[d];
-#pragma unroll 1
-      for (int q2 = 0; q2 < Q; ++q2) {
-        T v[12];
-#pragma unroll
-        for (int f = 0; f < 12; ++f) {
-          T a = 0;
-#pragma unroll
-          for (int j = 0; j < N; ++j) a = fmadd(t.S[q2][j], FA[(f * N + j) * Q], a);
-          v[f] = a;
-        }
-        // v[0..2] u-, v[3..5] u+, v[6..8] w-, v[9..11] w+
-        const T unm = sgn * v[d], unp = sgn * v[3 + d];
-        const T am = fabs(unm), ap = fabs(unp);
-        const T lam = fmax(am, ap);
-        const T sm = am > ap ? T(1) : (am == ap ? T(0.5) : T(0));
-        const T sg = unm > 0 ? T(1) : (unm < 0 ? T(-1) : T(0));
-        T dw[3], sdu = 0, sdj = 0;
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-          dw[i] = v[6 + i] - v[9 + i];
-          sdu = fmadd(dw[i], v[i], sdu);
-          sdj = fmadd(dw[i], v[i] - v[3 + i], sdj);
-        }
-        const T wgt = wq1 * t.w[q2];
-        const T diag = T(0.5) * unm + sc.lf * lam;
-        const T extra = sgn * (T(0.5) * sdu + sc.lf * sm * sg * sdj);
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          const T Gk = wgt * (dw[k] * diag + (k == d ? extra : T(0)));
-#pragma unroll
-          for (int j = 0; j < N; ++j) acc[k][j] = fmadd(t.S[q2][j], Gk, acc[k][j]);
+      for (int j = 0; j < 3; ++j) {
+        CONV_TABLES(t);
+        if (kind[i] == 0) {
+          const int bc = a1[i], b = bc % N, c = bc / N;
+          T* du = L + (Sh::SU + j * (N + 2) + c + 1) * COLS + MP * b;
+          T* dw = L + (Sh::SWS + j * (N + 2) + c + 1) * COLS + MP * b;
+          T* dg = L + (Sh::SWGX + j * N + c) * COLS + MP * b;
+          const int side = b == 0 ? 0 : (b == N - 1 ? 1 : -1);
+          if (side >= 0) {   // own y-face layer: also into FY
+            T* fu = L + FYo + fl(0, side, 0, j) + c * Q;
+            T* fw = L + FYo + fl(0, side, 1, j) + c * Q;
+            eo_interp<N, Q, T>(t, in[i][0][j], [&](int q, T val) {
+              du[q] = val;
+              fu[q] = val;
+            });
+            eo_interp<N, Q, T>(t, in[i][1][j], [&](int q, T val) {
+              dw[q] = val;
+              fw[q] = val;
+            });
+          } else {
+            eo_interp<N, Q, T>(t, in[i][0][j], [&](int q, T val) { du[q] = val; });
+            eo_interp<N, Q, T>(t, in[i][1][j], [&](int q, T val) { dw[q] = val; });
+          }
+          eo_interp_g<N, Q, T>(t, in[i][1][j], [&](int q, T val) { dg[q] = val; });
+        } else if (kind[i] == 1) {
+          const int isz = a1[i], s = a2[i], p = a3[i];
+          T *du, *dw;
+          if (isz) {   // pencil b = p of the neighbour's z layer -> extra z slot
+            du = L + (Sh::SU + j * (N + 2) + (s ? N + 1 : 0)) * COLS + MP * p;
+            dw = L + (Sh::SWS + j * (N + 2) + (s ? N + 1 : 0)) * COLS + MP * p;
+          } else {     // pencil c = p of the neighbour's y layer -> FY
+            du = L + FYo + fl(1, s, 0, j) + p * Q;
+            dw = L + FYo + fl(1, s, 1, j) + p * Q;
+          }
+          eo_interp<N, Q, T>(t, in[i][0][j], [&](int q, T val) { du[q] = val; });
+          eo_interp<N, Q, T>(t, in[i][1][j], [&](int q, T val) { dw[q] = val; });
+        } else {
+          const int sg = a1[i], s = a2[i], c = a3[i];
+          T* du = L + FXo + fl(sg, s, 0, j) + c * Q;
+          T* dw = L + FXo + fl(sg, s, 1, j) + c * Q;
+          eo_interp<N, Q, T>(t, in[i][0][j], [&](int q, T val) { du[q] = val; });
+          eo_interp<N, Q, T>(t, in[i][1][j], [&](int q, T val) { dw[q] = val; });
         }
       }
-      T* FB = RA + le * C::RA + 6 * N3 + 24 * N * Q;
-#pragma unroll
-      for (int k = 0; k < 3; ++k)
-#pragma unroll
-        for (int j = 0; j < N; ++j) FB[((s * 3 + k) * Q + q1) * N + j] = acc[k][j];
     }
-    __syncthreads();
-    // F3: back along t1 onto the face nodes
-    for (int it = tid; it < ne * 6 * N; it += TH) {
-      const int le = it / (6 * N);
-      int rem = it - le * 6 * N;
-      const int j = rem % N;
-      rem /= N;
-      const int k = rem % 3, s = rem / 3;
-      const T* FB = RA + le * C::RA + 6 * N3 + 24 * N * Q + ((s * 3 + k) * Q) * N + j;
-      T in[Q];
-#pragma unroll
-      for (int q = 0; q < Q; ++q) in[q] = FB[q * N];
-      T* FR = FRb + le * C::FR + ((d * 2 + s) * 3 + k) * N2 + N * j;
-#pragma unroll
-      for (int i = 0; i < N; ++i) {
-        T acc = t.S[0][i] * in[0];
-#pragma unroll
-        for (int q = 1; q < Q; ++q) acc = fmadd(t.S[q][i], in[q], acc);
-        FR[i] = acc;
-      }
-    }
-    __syncthreads();
   }
+  __syncthreads();
 
-  // ---------------- cell forward ----------------
-  // X: fields XB[0..2] = Sx u_c, XB[3..5] = Sx w_c, XB[6..8] = Gx w_c, layout q1 + Q(b + N cz)
-  for (int it = tid; it < ne * 6 * N2; it += TH) {
-    const int le = it / (6 * N2);
-    const int rem = it - le * 6 * N2;
-    const int f = rem / N2, bc = rem - f * N2;
-    const T* A = RA + le * C::RA + f * N3 + N * bc;
-    T in[N];
+  // ---------------- P2: y sweeps in place ----------------
+  {
+    constexpr int nUW = 2 * 3 * E * (N + 2) * Q, nG = 3 * E * N * Q;
+    for (int w = tid; w < nUW + nG; w += TH) {
+      CONV_TABLES(t);
+      if (w < nUW) {   // U or WS column block (q1, layer c')
+        const int q1 = w % Q, rest = w / Q;
+        const int cl = rest % (N + 2), r2 = rest / (N + 2);
+        const int le = r2 % E, jw = r2 / E;   // jw = which*3 + j
+        if (le >= ne) continue;
+        const int which = jw / 3, j = jw - which * 3;
+        T* L = lds + le * PER;
+        T* p = L + ((which ? Sh::SWS : Sh::SU) + j * (N + 2) + cl) * COLS + q1;
+        T x[N];
 #pragma unroll
-    for (int a = 0; a < N; ++a) in[a] = A[a];
-    T* XB = RB + le * C::RB + Q * bc;
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      T sv = t.S[q][0] * in[0], gv = t.G[q][0] * in[0];
-#pragma unroll
-      for (int a = 1; a < N; ++a) {
-        sv = fmadd(t.S[q][a], in[a], sv);
-        gv = fmadd(t.G[q][a], in[a], gv);
-      }
-      XB[f * Q * N2 + q] = sv;
-      if (f >= 3) XB[(f + 3) * Q * N2 + q] = gv;
-    }
-  }
-  __syncthreads();
-  // Y: YC fields (layout q1 + Q(q2 + Q cz)):
-  //   0..2 Sy Sx u_c; 3..5 Sy Sx w_c (-> d_z w); 6..8 Gy Sx w_c (d_y w); 9..11 Sy Gx w_c (d_x w)
-  for (int it = tid; it < ne * 9 * Q * N; it += TH) {
-    const int le = it / (9 * Q * N);
-    int rem = it - le * 9 * Q * N;
-    const int f = rem / (Q * N);
-    rem -= f * Q * N;
-    const int cz = rem / Q, q1 = rem - cz * Q;
-    const T* XB = RB + le * C::RB + f * Q * N2 + q1 + Q * N * cz;
-    T in[N];
-#pragma unroll
-    for (int b = 0; b < N; ++b) in[b] = XB[Q * b];
-    T* YC = RA + le * C::RA + q1 + Q * Q * cz;
-    // f 0..2 -> out 0..2 (S); f 3..5 -> out 3..5 (S) and 6..8 (G); f 6..8 -> out 9..11 (S)
-    const int fo = f < 3 ? f : (f < 6 ? f : f + 3);
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      T sv = t.S[q][0] * in[0], gv = t.G[q][0] * in[0];
-#pragma unroll
-      for (int b = 1; b < N; ++b) {
-        sv = fmadd(t.S[q][b], in[b], sv);
-        gv = fmadd(t.G[q][b], in[b], gv);
-      }
-      YC[fo * Q * Q * N + Q * q] = sv;
-      if (f >= 3 && f < 6) YC[(f + 3) * Q * Q * N + Q * q] = gv;
-    }
-  }
-  __syncthreads();
-  // Z (fused): per (q1,q2) pencil: values at z Gauss points, P_k, S^T_z -> ZT[k] in RB
-  for (int it = tid; it < ne * Q * Q; it += TH) {
-    const int le = it / (Q * Q), qq = it - le * Q * Q;
-    const int q2 = qq / Q, q1 = qq - q2 * Q;
-    const T* YC = RA + le * C::RA + qq;
-    T o[3][N];
-#pragma unroll
-    for (int k = 0; k < 3; ++k)
-#pragma unroll
-      for (int cz = 0; cz < N; ++cz) o[k][cz] = 0;
-    const T w12 = t.w[q1] * t.w[q2];
-#pragma unroll 1
-    for (int q3 = 0; q3 < Q; ++q3) {
-      T uu[3], dx[3], dy[3], dz[3];
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        T a0 = 0, a1 = 0, a2 = 0, a3 = 0;
-#pragma unroll
-        for (int cz = 0; cz < N; ++cz) {
-          const T sq = t.S[q3][cz];
-          a0 = fmadd(sq, YC[(0 + c) * Q * Q * N + Q * Q * cz], a0);
-          a1 = fmadd(sq, YC[(9 + c) * Q * Q * N + Q * Q * cz], a1);
-          a2 = fmadd(sq, YC[(6 + c) * Q * Q * N + Q * Q * cz], a2);
-          a3 = fmadd(t.G[q3][cz], YC[(3 + c) * Q * Q * N + Q * Q * cz], a3);
+        for (int b = 0; b < N; ++b) x[b] = p[MP * b];
+        if (which && cl >= 1 && cl <= N) {   // w: also G_y into WGY (interior layers)
+          T* pg = L + (Sh::SWGY + j * N + cl - 1) * COLS + q1;
+          eo_interp_g<N, Q, T>(t, x, [&](int q, T val) { pg[MP * q] = val; });
         }
-        uu[c] = a0;
-        dx[c] = a1;
-        dy[c] = a2;
-        dz[c] = a3;
+        eo_interp<N, Q, T>(t, x, [&](int q, T val) { p[MP * q] = val; });
+      } else {          // WGX column block: S_y in place
+        const int v = w - nUW;
+        const int q1 = v % Q, rest = v / Q;
+        const int c = rest % N, r2 = rest / N;
+        const int le = r2 % E, j = r2 / E;
+        if (le >= ne) continue;
+        T* p = lds + le * PER + (Sh::SWGX + j * N + c) * COLS + q1;
+        T x[N];
+#pragma unroll
+        for (int b = 0; b < N; ++b) x[b] = p[MP * b];
+        eo_interp<N, Q, T>(t, x, [&](int q, T val) { p[MP * q] = val; });
       }
-      const T wq = w12 * t.w[q3];
-      const T cu[3] = {sc.cell[0] * uu[0], sc.cell[1] * uu[1], sc.cell[2] * uu[2]};
-      // sum_c u_c d_k w_c for k = x, y, z
-      const T ux = uu[0] * dx[0] + uu[1] * dx[1] + uu[2] * dx[2];
-      const T uy = uu[0] * dy[0] + uu[1] * dy[1] + uu[2] * dy[2];
-      const T uz = uu[0] * dz[0] + uu[1] * dz[1] + uu[2] * dz[2];
-      T P[3];
-#pragma unroll
-      for (int k = 0; k < 3; ++k) P[k] = cu[0] * dx[k] + cu[1] * dy[k] + cu[2] * dz[k];
-      P[0] += sc.cell[0] * ux;
-      P[1] += sc.cell[1] * uy;
-      P[2] += sc.cell[2] * uz;
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        const T pk = wq * P[k];
-#pragma unroll
-        for (int cz = 0; cz < N; ++cz) o[k][cz] = fmadd(t.S[q3][cz], pk, o[k][cz]);
-      }
-    }
-    T* ZT = RB + le * C::RB + qq;
-#pragma unroll
-    for (int k = 0; k < 3; ++k)
-#pragma unroll
-      for (int cz = 0; cz < N; ++cz) ZT[k * Q * Q * N + Q * Q * cz] = o[k][cz];
-  }
-  __syncthreads();
-  // back Y: V[k][q1 + Q(b + N cz)] = S^T_y ZT[k]
-  for (int it = tid; it < ne * 3 * Q * N; it += TH) {
-    const int le = it / (3 * Q * N);
-    int rem = it - le * 3 * Q * N;
-    const int k = rem / (Q * N);
-    rem -= k * Q * N;
-    const int cz = rem / Q, q1 = rem - cz * Q;
-    const T* ZT = RB + le * C::RB + k * Q * Q * N + q1 + Q * Q * cz;
-    T in[Q];
-#pragma unroll
-    for (int q = 0; q < Q; ++q) in[q] = ZT[Q * q];
-    T* V = RA + le * C::RA + k * Q * N2 + q1 + Q * N * cz;
-#pragma unroll
-    for (int b = 0; b < N; ++b) {
-      T acc = t.S[0][b] * in[0];
-#pragma unroll
-      for (int q = 1; q < Q; ++q) acc = fmadd(t.S[q][b], in[q], acc);
-      V[Q * b] = acc;
     }
   }
   __syncthreads();
-  // back X + faces: g_k = S^T_x V[k] + face terms, written once
-  for (int it = tid; it < ne * 3 * N2; it += TH) {
-    const int le = it / (3 * N2);
-    const int rem = it - le * 3 * N2;
-    const int k = rem / N2, bc = rem - k * N2;
-    const int b = bc % N, cz = bc / N;
-    const T* V = RA + le * C::RA + k * Q * N2 + Q * bc;
-    T in[Q];
+
+  // transposed flux derivative at one face point from the own/neighbour
+  // traces of u and w; normal index d, outward sign sgn; G_k weighted by wgt
+  auto face_adj = [&](const T (&um)[3], const T (&up)[3], const T (&wm)[3], const T (&wp)[3], int d, T sgn,
+                      T wgt, T (&G)[3]) {
+    const T unm = sgn * (d == 0 ? um[0] : (d == 1 ? um[1] : um[2]));
+    const T unp = sgn * (d == 0 ? up[0] : (d == 1 ? up[1] : up[2]));
+    const T am = fabs(unm), ap = fabs(unp);
+    const T lam = fmax(am, ap);
+    const T sm = am > ap ? T(1) : (am == ap ? T(0.5) : T(0));
+    const T sgu = unm > T(0) ? T(1) : (unm < T(0) ? T(-1) : T(0));
+    T dw[3], sdu = 0, sdj = 0;
 #pragma unroll
-    for (int q = 0; q < Q; ++q) in[q] = V[q];
-    T o[N];
-#pragma unroll
-    for (int a = 0; a < N; ++a) {
-      T acc = t.S[0][a] * in[0];
-#pragma unroll
-      for (int q = 1; q < Q; ++q) acc = fmadd(t.S[q][a], in[q], acc);
-      o[a] = acc;
+    for (int i = 0; i < 3; ++i) {
+      dw[i] = wm[i] - wp[i];
+      sdu = fmadd(dw[i], um[i], sdu);
+      sdj = fmadd(dw[i], um[i] - up[i], sdj);
     }
-    const T* FR = FRb + le * C::FR;
-    o[0] += FR[((0 * 2 + 0) * 3 + k) * N2 + b + N * cz];
-    o[N - 1] += FR[((0 * 2 + 1) * 3 + k) * N2 + b + N * cz];
-    if (b == 0 || b == N - 1) {
-      const T* F = FR + ((1 * 2 + (b == 0 ? 0 : 1)) * 3 + k) * N2 + N * cz;
+    const T diag = T(0.5) * unm + sc.lf * lam;
+    const T extra = sgn * (T(0.5) * sdu + sc.lf * sm * sgu * sdj);
 #pragma unroll
-      for (int a = 0; a < N; ++a) o[a] += F[a];
+    for (int k = 0; k < 3; ++k) G[k] = wgt * (dw[k] * diag + (k == d ? extra : T(0)));
+  };
+
+  // ---------------- P3: z pencils and face pencils ----------------
+  {
+    constexpr int nCell = E * Q * Q, nH = E * 4 * Q;
+    for (int w = tid; w < nCell + nH; w += TH) {
+      CONV_TABLES(t);
+      if (w < nCell) {
+        const int le = w / (Q * Q), qq = w - le * (Q * Q);
+        if (le >= ne) continue;
+        const int q2 = qq / Q, q1 = qq - q2 * Q;
+        T* col = lds + le * PER + q1 + MP * q2;
+        const T w12 = t.w[q1] * t.w[q2];
+        // z faces from the layers -1, 0, n-1, n of U and WS
+        T Gz[2][3];
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+          T um[3], up[3], wm[3], wp[3];
+          const int own = s ? N : 1, nb = s ? N + 1 : 0;
+#pragma unroll
+          for (int j = 0; j < 3; ++j) {
+            um[j] = col[(Sh::SU + j * (N + 2) + own) * COLS];
+            up[j] = col[(Sh::SU + j * (N + 2) + nb) * COLS];
+            wm[j] = col[(Sh::SWS + j * (N + 2) + own) * COLS];
+            wp[j] = col[(Sh::SWS + j * (N + 2) + nb) * COLS];
+          }
+          face_adj(um, up, wm, wp, 2, s ? T(1) : T(-1), w12 * sc.area[2], Gz[s]);
+        }
+        // even-odd parts of the interior columns: f = 0 U (S_z: u), 1 WGX
+        // (S_z: d_x w), 2 WGY (S_z: d_y w), 3 WS (G_z: d_z w)
+        T xe[4][3][NH], xo[4][3][NH], xm[4][3];
+#pragma unroll
+        for (int f = 0; f < 4; ++f)
+#pragma unroll
+          for (int j = 0; j < 3; ++j) {
+            T x[N];
+#pragma unroll
+            for (int c = 0; c < N; ++c) {
+              const int slot = f == 0   ? Sh::SU + j * (N + 2) + c + 1
+                               : f == 1 ? Sh::SWGX + j * N + c
+                               : f == 2 ? Sh::SWGY + j * N + c
+                                        : Sh::SWS + j * (N + 2) + c + 1;
+              x[c] = col[slot * COLS];
+            }
+#pragma unroll
+            for (int a = 0; a < NH; ++a) {
+              xe[f][j][a] = x[a] + x[N - 1 - a];
+              xo[f][j][a] = x[a] - x[N - 1 - a];
+            }
+            xm[f][j] = (N % 2) ? x[NH] : T(0);
+          }
+        EoT<N, T, 1> acc[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) acc[k].zero();
+        // W_q3 P_k at one point from u and d_x w, d_y w, d_z w
+        auto pk = [&](const T (&uu)[3], const T (&dx)[3], const T (&dy)[3], const T (&dz)[3], T wq, T (&P)[3]) {
+          const T cu0 = sc.cell[0] * uu[0], cu1 = sc.cell[1] * uu[1], cu2 = sc.cell[2] * uu[2];
+          const T ux = uu[0] * dx[0] + uu[1] * dx[1] + uu[2] * dx[2];
+          const T uy = uu[0] * dy[0] + uu[1] * dy[1] + uu[2] * dy[2];
+          const T uz = uu[0] * dz[0] + uu[1] * dz[1] + uu[2] * dz[2];
+#pragma unroll
+          for (int k = 0; k < 3; ++k) P[k] = cu0 * dx[k] + cu1 * dy[k] + cu2 * dz[k];
+          P[0] = wq * fmadd(sc.cell[0], ux, P[0]);
+          P[1] = wq * fmadd(sc.cell[1], uy, P[1]);
+          P[2] = wq * fmadd(sc.cell[2], uz, P[2]);
+        };
+#pragma unroll
+        for (int q = 0; q < (Q + 1) / 2; ++q) {
+          // the four fields at q and at its mirror m-1-q
+          T vq[4][3], vr[4][3];
+#pragma unroll
+          for (int f = 0; f < 4; ++f)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+              T e, o;
+              if (f == 3) {
+                e = t.Gp[q][0] * xe[f][j][0];
+                o = t.Gm[q][0] * xo[f][j][0];
+#pragma unroll
+                for (int a = 1; a < NH; ++a) {
+                  e = fmadd(t.Gp[q][a], xe[f][j][a], e);
+                  o = fmadd(t.Gm[q][a], xo[f][j][a], o);
+                }
+                if constexpr (N % 2 == 1) e = fmadd(t.Gc[q], xm[f][j], e);
+                vq[f][j] = e + o;
+                vr[f][j] = o - e;
+              } else {
+                e = t.Sp[q][0] * xe[f][j][0];
+                o = t.Sm[q][0] * xo[f][j][0];
+#pragma unroll
+                for (int a = 1; a < NH; ++a) {
+                  e = fmadd(t.Sp[q][a], xe[f][j][a], e);
+                  o = fmadd(t.Sm[q][a], xo[f][j][a], o);
+                }
+                if constexpr (N % 2 == 1) e = fmadd(t.Sc[q], xm[f][j], e);
+                vq[f][j] = e + o;
+                vr[f][j] = e - o;
+              }
+            }
+          T Pq[3];
+          pk(vq[0], vq[1], vq[2], vq[3], t.w[q], Pq);
+          if (q < QH) {
+            T Pr[3];
+            pk(vr[0], vr[1], vr[2], vr[3], t.w[q], Pr);   // w[m-1-q] = w[q]
+#pragma unroll
+            for (int k = 0; k < 3; ++k) acc[k].pair(t.Tp[q], t.Tm[q], Pq[k], Pr[k]);
+          } else {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) acc[k].mid(t.Tc, Pq[k]);
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+          for (int c = 0; c < N; ++c) {
+            T o = w12 * acc[k].out(c);
+            if (c == 0) o += Gz[0][k];
+            if (c == N - 1) o += Gz[1][k];
+            col[(k * N + c) * COLS] = o;
+          }
+      } else {   // face pencil: fam 0 = y face (q = q1), 1 = x face (q = q2)
+        const int h = w - nCell;
+        const int le = h / (4 * Q);
+        if (le >= ne) continue;
+        int rem = h - le * 4 * Q;
+        const int fam = rem / (2 * Q);
+        rem -= fam * 2 * Q;
+        const int s = rem / Q, q = rem - s * Q;
+        T* F = lds + le * PER + (fam ? FXo : FYo) + q;
+        // even-odd parts of the (sigma, f, j) pencils
+        T xe[2][2][3][NH], xo[2][2][3][NH], xm[2][2][3];
+#pragma unroll
+        for (int sg = 0; sg < 2; ++sg)
+#pragma unroll
+          for (int f = 0; f < 2; ++f)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+              T x[N];
+#pragma unroll
+              for (int c = 0; c < N; ++c) x[c] = F[fl(sg, s, f, j) + c * Q];
+#pragma unroll
+              for (int a = 0; a < NH; ++a) {
+                xe[sg][f][j][a] = x[a] + x[N - 1 - a];
+                xo[sg][f][j][a] = x[a] - x[N - 1 - a];
+              }
+              xm[sg][f][j] = (N % 2) ? x[NH] : T(0);
+            }
+        EoT<N, T, 1> acc[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) acc[k].zero();
+        const T sgn = s ? T(1) : T(-1);
+        const int d = fam ? 0 : 1;
+        const T wq = t.w[q] * (fam ? sc.area[0] : sc.area[1]);
+#pragma unroll
+        for (int q3 = 0; q3 < (Q + 1) / 2; ++q3) {
+          T vq[2][2][3], vr[2][2][3];
+#pragma unroll
+          for (int sg = 0; sg < 2; ++sg)
+#pragma unroll
+            for (int f = 0; f < 2; ++f)
+#pragma unroll
+              for (int j = 0; j < 3; ++j) {
+                T e = t.Sp[q3][0] * xe[sg][f][j][0], o = t.Sm[q3][0] * xo[sg][f][j][0];
+#pragma unroll
+                for (int a = 1; a < NH; ++a) {
+                  e = fmadd(t.Sp[q3][a], xe[sg][f][j][a], e);
+                  o = fmadd(t.Sm[q3][a], xo[sg][f][j][a], o);
+                }
+                if constexpr (N % 2 == 1) e = fmadd(t.Sc[q3], xm[sg][f][j], e);
+                vq[sg][f][j] = e + o;
+                vr[sg][f][j] = e - o;
+              }
+          const T wgt = wq * t.w[q3];
+          T Gq[3];
+          face_adj(vq[0][0], vq[1][0], vq[0][1], vq[1][1], d, sgn, wgt, Gq);
+          if (q3 < QH) {
+            T Gr[3];
+            face_adj(vr[0][0], vr[1][0], vr[0][1], vr[1][1], d, sgn, wgt, Gr);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) acc[k].pair(t.Tp[q3], t.Tm[q3], Gq[k], Gr[k]);
+          } else {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) acc[k].mid(t.Tc, Gq[k]);
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+          for (int c = 0; c < N; ++c) F[fl(0, s, 0, k) + c * Q] = acc[k].out(c);
+      }
     }
-    if (cz == 0 || cz == N - 1) {
-      const T* F = FR + ((2 * 2 + (cz == 0 ? 0 : 1)) * 3 + k) * N2 + N * b;
+  }
+  __syncthreads();
+
+  // ---------------- Y: S^T_y in place, y-face terms; S^T_y of the x-face terms ----------------
+  {
+    constexpr int nY = 3 * E * N * Q, nXf = 3 * E * 2 * N;
+    for (int w = tid; w < nY + nXf; w += TH) {
+      CONV_TABLES(t);
+      if (w < nY) {
+        const int q1 = w % Q, rest = w / Q;
+        const int cz = rest % N, r2 = rest / N;
+        const int le = r2 % E, k = r2 / E;
+        if (le >= ne) continue;
+        T* L = lds + le * PER;
+        T* tb = L + (k * N + cz) * COLS + q1;
+        EoT<N, T, 1> v;
+        v.zero();
 #pragma unroll
-      for (int a = 0; a < N; ++a) o[a] += F[a];
+        for (int q2 = 0; q2 < QH; ++q2) v.pair(t.Tp[q2], t.Tm[q2], tb[MP * q2], tb[MP * (Q - 1 - q2)]);
+        if constexpr (Q % 2 == 1) v.mid(t.Tc, tb[MP * QH]);
+        const T f0 = L[FYo + fl(0, 0, 0, k) + cz * Q + q1];
+        const T f1 = L[FYo + fl(0, 1, 0, k) + cz * Q + q1];
+#pragma unroll
+        for (int b = 0; b < N; ++b) {
+          T o = v.out(b);
+          if (b == 0) o += f0;
+          if (b == N - 1) o += f1;
+          tb[MP * b] = o;
+        }
+      } else {
+        const int vv = w - nY;
+        const int cz = vv % N, rest = vv / N;
+        const int s = rest % 2, r2 = rest / 2;
+        const int le = r2 % E, k = r2 / E;
+        if (le >= ne) continue;
+        T* L = lds + le * PER;
+        const T* xf = L + FXo + fl(0, s, 0, k) + cz * Q;
+        EoT<N, T, 1> o;
+        o.zero();
+#pragma unroll
+        for (int q2 = 0; q2 < QH; ++q2) o.pair(t.Tp[q2], t.Tm[q2], xf[q2], xf[Q - 1 - q2]);
+        if constexpr (Q % 2 == 1) o.mid(t.Tc, xf[QH]);
+        T* xr = L + XRo + ((k * 2 + s) * N + cz) * N;
+#pragma unroll
+        for (int b = 0; b < N; ++b) xr[b] = o.out(b);
+      }
     }
-    T* out = g + k * cs + (size_t)(e0 + le) * N3 + N * bc;
+  }
+  __syncthreads();
+
+  // ---------------- X: S^T_x, x-face terms, write-out ----------------
+  {
+    constexpr int nX = 3 * E * N2;
+    for (int w = tid; w < nX; w += TH) {
+      CONV_TABLES(t);
+      const int bc = w % N2, r2 = w / N2;
+      const int le = r2 % E, k = r2 / E;
+      if (le >= ne) continue;
+      const int b = bc % N, cz = bc / N;
+      const T* L = lds + le * PER;
+      const T* v = L + (k * N + cz) * COLS + MP * b;
+      EoT<N, T, 1> o;
+      o.zero();
 #pragma unroll
-    for (int a = 0; a < N; ++a) out[a] = o[a];
+      for (int q1 = 0; q1 < QH; ++q1) o.pair(t.Tp[q1], t.Tm[q1], v[q1], v[Q - 1 - q1]);
+      if constexpr (Q % 2 == 1) o.mid(t.Tc, v[QH]);
+      const T* xr = L + XRo + (k * 2 * N + cz) * N + b;
+      const T x0 = xr[0], x1 = xr[N2];
+      T* out = g + k * cs + (size_t)(e0 + le) * N3 + N * bc;
+#pragma unroll
+      for (int a = 0; a < N; ++a) {
+        T val = o.out(a);
+        if (a == 0) val += x0;
+        if (a == N - 1) val += x1;
+        out[a] = val;
+      }
+    }
   }
 }
 
 template <int N, int Q, typename T>
-static hipError_t launch_vjp_nq(const ConvPlan& P, const void* u, const void* w, void* g,
-                                hipStream_t s) {
-  using C = VjpCfg<N, Q, T>;
-  if constexpr (!C::FITS) {
+static hipError_t launch_vjp_nq(const ConvPlan& P, const void* u, const void* w, void* g, hipStream_t s) {
+  using Sh = VjpShape<N, Q, (int)sizeof(T)>;
+  if constexpr (!Sh::FITS) {
     return hipErrorInvalidConfiguration;
   } else {
-    VjpTab<N, Q, T> t;
+    // the kernel's compile-time tables must be the plan's tables
+    constexpr ct::Tables<N, Q> C{};
     for (int q = 0; q < Q; ++q) {
-      for (int a = 0; a < N; ++a) {
-        t.S[q][a] = (T)P.S[q * N + a];
-        t.G[q][a] = (T)P.G[q * N + a];
-      }
-      t.w[q] = (T)P.w[q];
+      if (std::fabs(C.w[q] - P.w[q]) > 1e-13) return hipErrorInvalidValue;
+      for (int a = 0; a < N; ++a)
+        if (std::fabs(C.S[q][a] - P.S[q * N + a]) > 1e-13 || std::fabs(C.G[q][a] - P.G[q * N + a]) > 1e-11)
+          return hipErrorInvalidValue;
     }
-    VjpScal<T> sc;
+    ConvScal<T> sc;
     for (int d = 0; d < 3; ++d) {
       sc.cell[d] = (T)P.cell[d];
       sc.area[d] = (T)P.area[d];
     }
     sc.lf = (T)P.lf;
-    hipError_t err;
-    const VjpTab<N, Q, T>* dt = device_table_of("convective_vjp", t, &err);
-    if (!dt) return err;
-    const int grid = (P.mesh.n_el + C::E - 1) / C::E;
-    hipLaunchKernelGGL((convective_vjp_kernel<N, Q, T>), dim3(grid), dim3(C::THREADS), 0, s,
+    const ConvTab<N, Q, T>* dt = nullptr;   // FP32 kernels use the compile-time tables
+    if (sizeof(T) == 8) {
+      const ConvTab<N, Q, T> t = make_conv_tab<N, Q, T>(P.S.data(), P.G.data(), P.w.data());
+      hipError_t err;
+      dt = device_table_of("convective", t, &err);
+      if (!dt) return err;
+    }
+    const int grid = (P.mesh.n_el + Sh::E - 1) / Sh::E;
+    hipLaunchKernelGGL((convective_vjp_kernel<N, Q, T, Sh::E, Sh::TH>), dim3(grid), dim3(Sh::TH), 0, s,
                        (const T*)u, (const T*)w, (T*)g, P.mesh, dt, sc);
     return hipGetLastError();
   }
 }
 
 template <typename T>
-static hipError_t launch_vjp_t(const ConvPlan& P, const void* u, const void* w, void* g,
-                               hipStream_t s) {
+static hipError_t launch_vjp_t(const ConvPlan& P, const void* u, const void* w, void* g, hipStream_t s) {
   switch (P.k) {
     case 1: return launch_vjp_nq<2, 2, T>(P, u, w, g, s);
     case 2: return launch_vjp_nq<3, 4, T>(P, u, w, g, s);
@@ -409,8 +590,8 @@ static hipError_t launch_vjp_t(const ConvPlan& P, const void* u, const void* w, 
 
 int vjp_max_degree(bool f32) { return f32 ? 9 : 7; }
 
-hipError_t launch_convective_vjp(const ConvPlan& P, bool f32, const void* u, const void* w,
-                                 void* g, hipStream_t s) {
+hipError_t launch_convective_vjp(const ConvPlan& P, bool f32, const void* u, const void* w, void* g,
+                                 hipStream_t s) {
   return f32 ? launch_vjp_t<float>(P, u, w, g, s) : launch_vjp_t<double>(P, u, w, g, s);
 }
 

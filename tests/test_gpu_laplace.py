@@ -142,3 +142,39 @@ def test_alias_error_on_gpu():
     with pytest.raises(dgmf.DgError) as ei:
         dgmf.apply_laplace(d, u, out=u)
     assert ei.value.code == dgmf.DG_ERR_ALIAS
+
+
+@pytest.mark.parametrize("k,dtype", [(3, torch.float64), (2, torch.float32), (4, torch.float64)])
+def test_partial_tiles_and_short_last_z_segment(k, dtype):
+    """47 x 46 x 47 elements: the low-degree kernel's x-y tiles do not divide
+    the mesh and its last z segment is shorter than the others; sampled
+    elements at tile and segment borders, corners and wrap-around."""
+    n_el = (47, 46, 47)
+    msh = M.Mesh(n_el, (2 * np.pi,) * 3)
+    n3 = (k + 1) ** 3
+    u = inputs.uniform((msh.N, n3), seed=400 + k)
+    if dtype == torch.float32:
+        u = round_f32(u)
+    announce(f"laplace partial tiles k={k} {dtype}")
+    y = _run(k, n_el, msh.length, u, dtype=dtype)
+    nx, ny, nz = n_el
+    rng = np.random.default_rng(11)
+    ex = np.concatenate([[0, 1, 3, 4, 7, 8, nx - 2, nx - 1], rng.integers(0, nx, 12)])
+    ey = np.concatenate([[0, 3, 4, 7, 8, ny - 2, ny - 1], rng.integers(0, ny, 12)])
+    ez = np.concatenate([[0, 1, 2, 3, 4, nz - 4, nz - 3, nz - 2, nz - 1], rng.integers(0, nz, 12)])
+    sample = np.unique((ex[:, None, None] + nx * (ey[None, :, None] + ny * ez[None, None, :])).ravel())
+    sample = sample[rng.permutation(len(sample))[:400]]
+    ref = laplace_apply(u, k, msh, elems=np.sort(sample))
+    tol = 1e-12 if dtype == torch.float64 else 1e-5
+    assert rel_err(y[np.sort(sample)], ref) < tol
+
+
+def test_three_components_low_degree():
+    """n_comp = 3 through the low-degree (marching) kernel, full oracle check."""
+    k, n_el = 3, (6, 5, 7)
+    msh = M.Mesh(n_el, (1.0, 2.0, 3.0))
+    u = inputs.uniform((3, msh.N, 64), seed=21)
+    announce("laplace n_comp=3 k=3")
+    y = _run(k, n_el, msh.length, u, penalty_factor=1.5, scale=0.25)
+    ref = laplace_apply(u, k, msh, penalty_factor=1.5, scale=0.25)
+    assert rel_err(y, ref) < 1e-12
