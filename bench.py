@@ -39,7 +39,7 @@ ALU_PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}
 BYTES_PER_DOF = {("laplace", "f64"): 16, ("laplace", "f32"): 8,
                  ("convective", "f64"): 16, ("convective", "f32"): 8,
                  ("vjp", "f64"): 24, ("vjp", "f32"): 12}
-KERNEL_NAME = {"laplace": "laplace_kernel", "convective": "convective_kernel", "vjp": "convective_vjp_kernel"}
+KERNEL_NAME = {"laplace": "laplace_march_kernel|laplace_batch_kernel", "convective": "convective_kernel", "vjp": "convective_vjp_kernel"}
 SOURCES = {"laplace": "laplace.hip", "convective": "convective.hip", "vjp": "convective_vjp.hip"}
 
 
