@@ -133,8 +133,11 @@ typedef struct {
 
 typedef struct {
   int32_t iterations;    /* CG iterations done                                       */
-  int32_t matvec_f64;    /* double-precision operator applications                   */
-  int32_t matvec_f32;    /* single-precision operator applications (preconditioner)  */
+  int32_t matvec_f64;    /* double-precision operator applications launched          */
+  int32_t matvec_f32;    /* single-precision operator applications launched          */
+                         /* (iterations run in batches between host checks of the    */
+                         /*  residual; a batch may end with a few no-op iterations   */
+                         /*  after convergence, counted here and in seconds_solve)   */
   double  rel_res;       /* recursive ||r||/||b|| at exit                             */
   double  true_rel_res;  /* ||b - A x||/||b|| recomputed in double at exit           */
   double  lambda_max;    /* estimate of the largest eigenvalue of D^-1 A (Chebyshev) */

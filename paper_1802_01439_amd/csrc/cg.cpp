@@ -21,6 +21,7 @@
 // on a hashed random zero-mean vector); lmin = lmax / range.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <map>
@@ -43,6 +44,8 @@ struct Workspace {
   double* partial = nullptr;   // 8 * kCgBlocks
   double* res = nullptr;       // 8 results (device)
   double* host = nullptr;      // 8 results (pinned host)
+  double* st = nullptr;        // main-loop state (device), kStateSize
+  double* host_st = nullptr;   // its pinned host copy
   double* dinv = nullptr;      // n3
   float* dinv32 = nullptr;     // n3
 };
@@ -55,6 +58,8 @@ hipError_t ensure(Workspace& w, long long n) {
   if (!w.partial && (e = hipMalloc((void**)&w.partial, 8 * kCgBlocks * sizeof(double))) != hipSuccess) return e;
   if (!w.res && (e = hipMalloc((void**)&w.res, 8 * sizeof(double))) != hipSuccess) return e;
   if (!w.host && (e = hipHostMalloc((void**)&w.host, 8 * sizeof(double), 0)) != hipSuccess) return e;
+  if (!w.st && (e = hipMalloc((void**)&w.st, kStateSize * sizeof(double))) != hipSuccess) return e;
+  if (!w.host_st && (e = hipHostMalloc((void**)&w.host_st, kStateSize * sizeof(double), 0)) != hipSuccess) return e;
   if (!w.dinv && (e = hipMalloc((void**)&w.dinv, 1728 * sizeof(double))) != hipSuccess) return e;
   if (!w.dinv32 && (e = hipMalloc((void**)&w.dinv32, 1728 * sizeof(float))) != hipSuccess) return e;
   if (w.n >= n) return hipSuccess;
@@ -248,14 +253,38 @@ extern "C" int dg_cg_solve(const dg_op_desc* desc, const dg_cg_opts* opts, const
   if (!S.ok(hipStreamSynchronize(S.s))) return hip_fail(S.err, "setup");
   const double t_setup = now();
 
-  // ---- preconditioner: z = M^-1 r (r projected in place), returns partials
-  // sum z, r.z, r.zold, r.r in H[0..3] ----
-  auto precondition = [&](double mu_r) -> bool {
+  // ---- main loop ----
+  // The iteration scalars (alpha, beta, means, |r|, convergence) are computed
+  // on the device and stay there; the host enqueues a batch of iterations and
+  // reads the state once per batch.  Iterations queued after convergence are
+  // no-ops (alpha = 0), so the result does not depend on the batch size.
+  // Jacobi (a fixed symmetric preconditioner) uses the standard PCG beta,
+  // Chebyshev in FP32 the flexible one.
+  int status = DG_OK;
+  int it = 0;
+  double rel = 0, bnorm = 0;
+  S.apply64(x, W.q);
+  S.ok(cg_residual(b, W.q, W.r, n, W.partial, S.s));
+  if (!S.fetch(4)) return hip_fail(S.err, "initial residual");
+  const double sum_b = H[2], sum_bb = H[3];
+  bnorm = std::sqrt(std::fmax(0.0, S.project ? sum_bb - sum_b * sum_b / dn : sum_bb));
+  const double tol = std::fmax(opts->rtol * bnorm, opts->atol);
+  double sum_d = 0;
+  for (long long i = 0; i < n3; ++i) sum_d += dinv[i];
+  sum_d *= (double)num_elements(desc);
+  S.ok(cg_state_init(W.st, tol * tol, opts->max_iter, sum_d, n, S.project, S.s));
+  S.ok(cg_fill(W.p, 0.0, n, S.s));
+  S.ok(cg_fill(W.zold, 0.0, n, S.s));
+  // z = M^-1 r' and the scalars of the current residual (sums of r from the
+  // x/r update); then p = z + beta p
+  auto precondition_and_p = [&](bool start) {
     if (!cheb) {
-      S.ok(cg_jacobi(W.r, W.z, W.zold, W.dinv, S.n3, mu_r, n, W.partial, S.s));
-      return S.fetch(4);
+      S.ok(cg_fin_jacobi(W.partial, W.st, start, S.s));
+      S.ok(cg_update_p_jacobi(W.r, W.p, W.dinv, S.n3, W.st, n, S.s));
+      return;
     }
-    S.ok(cg_cheb_init(W.r, W.r32, W.x32, W.d32, W.dinv32, S.n3, mu_r, (float)(1.0 / theta), n, S.s));
+    S.ok(cg_fin_resid(W.partial, W.st, start, S.s));
+    S.ok(cg_cheb_init_st(W.r, W.r32, W.x32, W.d32, W.dinv32, S.n3, W.st, (float)(1.0 / theta), n, S.s));
     double rho_prev = delta / theta;
     for (int k = 1; k < opts->cheb_degree; ++k) {
       const double rho = 1.0 / (2.0 * theta / delta - rho_prev);
@@ -264,50 +293,47 @@ extern "C" int dg_cg_solve(const dg_op_desc* desc, const dg_cg_opts* opts, const
                         (float)(2.0 * rho / delta), n, S.s));
       rho_prev = rho;
     }
-    S.ok(cg_cheb_final(W.r, W.z, W.zold, W.x32, n, W.partial, S.s));
-    return S.fetch(4);
+    S.ok(cg_cheb_sums(W.r, W.x32, W.zold, W.st, n, W.partial, S.s));
+    S.ok(cg_fin_cheb(W.partial, W.st, start, S.s));
+    S.ok(cg_update_p_cheb(W.x32, W.p, W.zold, W.st, n, S.s));
   };
-
-  // ---- CG ----
-  int status = DG_OK;
-  int it = 0;
-  double rel = 0, bnorm = 0;
-  S.apply64(x, W.q);
-  S.ok(cg_residual(b, W.q, W.r, n, W.partial, S.s));
-  if (!S.fetch(4)) return hip_fail(S.err, "initial residual");
-  const double sum_r = H[0], sum_b = H[2], sum_bb = H[3];
-  bnorm = std::sqrt(std::fmax(0.0, S.project ? sum_bb - sum_b * sum_b / dn : sum_bb));
-  const double tol = std::fmax(opts->rtol * bnorm, opts->atol);
-  S.ok(cg_fill(W.zold, 0.0, n, S.s));
-  if (!precondition(S.project ? sum_r / dn : 0.0)) return hip_fail(S.err, "preconditioner");
-  double muz = S.project ? H[0] / dn : 0.0;
-  double rz = H[1];
-  double rnorm = std::sqrt(H[3]);
-  S.ok(cg_update_p(W.z, W.p, W.zold, muz, 0.0, n, S.s));
-  rel = bnorm > 0 ? rnorm / bnorm : rnorm;
+  // start: alpha is 0 in the fresh state, so this only forms the sums of r0
+  S.ok(cg_update_xr_st(x, W.r, W.p, W.q, W.dinv, S.n3, W.st, !cheb, n, W.partial, S.s));
+  precondition_and_p(true);
+  // batch size: up to max_batch, fewer when the observed contraction rate
+  // says the tolerance is that close (keeps queued no-op iterations rare)
+  const int max_batch = cheb ? 4 : 8;
+  int batch = max_batch;
+  long long queued = 0;
+  double* HS = W.host_st;
+  double rn2_prev = -1, it_prev = 0;
   for (;;) {
-    if (!std::isfinite(rnorm) || !std::isfinite(rz)) { status = DG_ERR_BREAKDOWN; break; }
-    if (rnorm <= tol) break;
-    if (it >= opts->max_iter) { status = DG_NOT_CONVERGED; break; }
-    S.apply64(W.p, W.q);
-    S.ok(cg_dot(W.p, W.q, n, W.partial, S.s));
-    if (!S.fetch(1)) return hip_fail(S.err, "p.Ap");
-    const double pq = H[0];
-    if (!(pq > 0) || !std::isfinite(pq)) { status = DG_ERR_BREAKDOWN; break; }
-    const double alpha = rz / pq;
-    S.ok(cg_update_xr(x, W.r, W.p, W.q, alpha, n, W.partial, S.s));
-    if (!S.fetch(1)) return hip_fail(S.err, "update");
-    const double mur = S.project ? H[0] / dn : 0.0;
-    if (!precondition(mur)) return hip_fail(S.err, "preconditioner");
-    muz = S.project ? H[0] / dn : 0.0;
-    const double rz_new = H[1], rzold = H[2];
-    rnorm = std::sqrt(H[3]);
-    const double beta = (rz_new - rzold) / rz;
-    S.ok(cg_update_p(W.z, W.p, W.zold, muz, beta, n, S.s));
-    rz = rz_new;
-    ++it;
-    rel = bnorm > 0 ? rnorm / bnorm : rnorm;
+    if (!S.ok(hipMemcpyAsync(HS, W.st, kStateSize * sizeof(double), hipMemcpyDeviceToHost, S.s)) ||
+        !S.ok(hipStreamSynchronize(S.s)))
+      return hip_fail(S.err, "CG state");
+    if (HS[kDone] != 0.0 || queued > (long long)opts->max_iter + max_batch) break;
+    batch = max_batch;
+    if (rn2_prev > 0 && HS[kRN2] > 0 && HS[kRN2] < rn2_prev && HS[kIter] > it_prev) {
+      const double rate = std::log(HS[kRN2] / rn2_prev) / (HS[kIter] - it_prev);   // per iteration, < 0
+      const double left = std::log(HS[kTol2] / HS[kRN2]) / rate;
+      if (std::isfinite(left)) batch = (int)std::max(1.0, std::min((double)max_batch, std::ceil(left)));
+    }
+    rn2_prev = HS[kRN2];
+    it_prev = HS[kIter];
+    for (int b2 = 0; b2 < batch; ++b2) {
+      S.apply64(W.p, W.q);
+      S.ok(cg_dot(W.p, W.q, n, W.partial, S.s));
+      S.ok(cg_fin_alpha(W.partial, W.st, S.s));
+      S.ok(cg_update_xr_st(x, W.r, W.p, W.q, W.dinv, S.n3, W.st, !cheb, n, W.partial, S.s));
+      precondition_and_p(false);
+    }
+    queued += batch;
+    if (S.err != hipSuccess) return hip_fail(S.err, "CG iteration");
   }
+  it = (int)HS[kIter];
+  rel = std::sqrt(std::fmax(0.0, HS[kRN2])) / (bnorm > 0 ? bnorm : 1.0);
+  if (HS[kStatus] == 2.0) status = DG_ERR_BREAKDOWN;
+  else if (HS[kStatus] == 1.0 || HS[kDone] == 0.0) status = DG_NOT_CONVERGED;
   if (!S.ok(hipStreamSynchronize(S.s))) return hip_fail(S.err, "solve");
   const double t_solve = now();
   // true residual in FP64

@@ -9,6 +9,27 @@ namespace dgmf {
 constexpr int kCgThreads = 256;
 constexpr int kCgBlocks = 1024;
 
+// Device-side state of the main CG loop (doubles).
+enum : int {
+  kRZ = 0,      // r'.z' of the current residual
+  kAlpha,       // step length of the current iteration
+  kBeta,        // direction update coefficient
+  kMuR,         // mean of r (0 without projection)
+  kMuZ,         // mean of D^-1 r' or of the Chebyshev output
+  kRN2,         // |r'|^2
+  kDone,        // 1: converged, broken down or out of iterations
+  kStatus,      // 0 ok, 1 max_iter reached, 2 breakdown
+  kIter,        // iterations done
+  kTol2,        // stopping threshold on |r'|^2
+  kMaxIt,       // iteration limit
+  kSumD,        // sum of D^-1 over all DoFs
+  kN,           // number of DoFs
+  kProj,        // 1: project on zero coefficient mean
+  kPQ,          // p.Ap of the current iteration
+  kSumRp,       // sum r' (0 with projection)
+  kStateSize
+};
+
 hipError_t cg_finalize(const double* partial, int nq, double* out, hipStream_t s);
 hipError_t cg_residual(const double* b, const double* q, double* r, long long n, double* partial, hipStream_t s);
 hipError_t cg_dot(const double* x, const double* y, long long n, double* partial, hipStream_t s);
@@ -26,5 +47,21 @@ hipError_t cg_cheb_final(const double* r, double* z, const double* zold, const f
 hipError_t cg_hash_fill(double* v, unsigned long long seed, long long n, double* partial, hipStream_t s);
 hipError_t cg_axpb(double* y, const double* x, double a, double c, long long n, hipStream_t s);
 hipError_t cg_fill(double* y, double c, long long n, hipStream_t s);
+
+// main loop with device-side scalars
+hipError_t cg_state_init(double* st, double tol2, int max_it, double sum_d, long long n, bool proj, hipStream_t s);
+hipError_t cg_fin_alpha(const double* partial, double* st, hipStream_t s);
+hipError_t cg_update_xr_st(double* x, double* r, const double* p, const double* q, const double* dinv, int n3,
+                           const double* st, bool jacobi, long long n, double* partial, hipStream_t s);
+hipError_t cg_fin_jacobi(const double* partial, double* st, bool start, hipStream_t s);
+hipError_t cg_update_p_jacobi(const double* r, double* p, const double* dinv, int n3, const double* st, long long n,
+                              hipStream_t s);
+hipError_t cg_fin_resid(const double* partial, double* st, bool start, hipStream_t s);
+hipError_t cg_cheb_init_st(const double* r, float* r32, float* x32, float* d32, const float* dinv32, int n3,
+                           const double* st, float inv_theta, long long n, hipStream_t s);
+hipError_t cg_cheb_sums(const double* r, const float* x32, const double* zold, const double* st, long long n,
+                        double* partial, hipStream_t s);
+hipError_t cg_fin_cheb(const double* partial, double* st, bool start, hipStream_t s);
+hipError_t cg_update_p_cheb(const float* x32, double* p, double* zold, const double* st, long long n, hipStream_t s);
 
 }  // namespace dgmf

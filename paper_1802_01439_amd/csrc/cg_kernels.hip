@@ -189,6 +189,223 @@ __global__ void __launch_bounds__(kThreads) k_fill(double* __restrict__ y, doubl
     y[i] = c;
 }
 
+// ---------------------------------------------------------------------------
+// Main-loop kernels with the iteration scalars kept on the device (state
+// array st, indices in cg_kernels.h): the host enqueues several iterations at
+// a time and reads the state once per batch.  Once st[kDone] is set every
+// update below becomes a no-op, so iterations queued past convergence change
+// nothing.
+//
+// Mean projection on periodic meshes, folded into the sums: with r' = r - mu
+// (mu = mean r), z' = D^-1 r' - mu_z (mu_z = mean of D^-1 r') and d = D^-1 1,
+//   |r'|^2    = S_rr - 2 mu S_r + n mu^2
+//   r'.D^-1r' = S_rdr - 2 mu S_dr + mu^2 S_d
+//   mu_z      = (S_dr - mu S_d) / n
+//   r'.z'     = r'.D^-1r' - mu_z (S_r - n mu)
+// from one pass computing S_r = sum r, S_rr = sum r^2, S_dr = sum d r,
+// S_rdr = sum d r^2 (S_d = sum d is a setup constant).  r itself is stored
+// unprojected; every use subtracts mu.
+
+// Sum of partial[q * nblocks + i] over i, fixed order; valid in thread 0.
+__device__ double block_sum(const double* __restrict__ partial, int nblocks, int q, double* sh) {
+  double s = 0;
+  for (int i = threadIdx.x; i < nblocks; i += kThreads) s += partial[q * nblocks + i];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int st = kThreads / 2; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+    __syncthreads();
+  }
+  const double v = sh[0];
+  __syncthreads();
+  return v;
+}
+
+// alpha = rz / p.q  (p.q from one partial), breakdown if p.q <= 0 or not finite
+__global__ void __launch_bounds__(kThreads) k_fin_alpha(const double* __restrict__ partial, int nblocks,
+                                                        double* __restrict__ st) {
+  __shared__ double sh[kThreads];
+  const double pq = block_sum(partial, nblocks, 0, sh);
+  if (threadIdx.x != 0) return;
+  if (st[kDone] != 0.0) {
+    st[kAlpha] = 0.0;
+    return;
+  }
+  st[kPQ] = pq;
+  if (!(pq > 0.0) || !isfinite(pq)) {
+    st[kAlpha] = 0.0;
+    st[kDone] = 1.0;
+    st[kStatus] = 2.0;
+    return;
+  }
+  st[kAlpha] = st[kRZ] / pq;
+}
+
+// x += alpha p; r -= alpha q; partials S_r, S_rr and (JAC) S_dr, S_rdr
+template <bool JAC>
+__global__ void __launch_bounds__(kThreads) k_update_xr_st(double* __restrict__ x, double* __restrict__ r,
+                                                           const double* __restrict__ p, const double* __restrict__ q,
+                                                           const double* __restrict__ dinv, int n3,
+                                                           const double* __restrict__ st, long long n,
+                                                           double* partial) {
+  const double alpha = st[kAlpha];
+  double v[JAC ? 4 : 2] = {};
+  for (long long i = blockIdx.x * (long long)kThreads + threadIdx.x; i < n; i += (long long)gridDim.x * kThreads) {
+    double ri = r[i];
+    if (alpha != 0.0) {
+      x[i] += alpha * p[i];
+      ri -= alpha * q[i];
+      r[i] = ri;
+    }
+    v[0] += ri;
+    v[1] += ri * ri;
+    if constexpr (JAC) {
+      const double d = dinv[i % n3];
+      v[2] += d * ri;
+      v[3] += d * ri * ri;
+    }
+  }
+  block_partials<JAC ? 4 : 2>(v, partial);
+}
+
+// count the iteration (not for the start) and test convergence / limits
+__device__ void account(double* st, double rn2, double rz, bool start) {
+  if (!start) st[kIter] += 1.0;
+  if (!isfinite(rn2) || !isfinite(rz)) {
+    st[kDone] = 1.0;
+    st[kStatus] = 2.0;
+  } else if (rn2 <= st[kTol2]) {
+    st[kDone] = 1.0;
+  } else if (st[kIter] >= st[kMaxIt]) {
+    st[kDone] = 1.0;
+    st[kStatus] = 1.0;
+  }
+}
+
+// Jacobi: scalars of the new residual (sums from k_update_xr_st<true>);
+// beta = rz_new / rz (a fixed symmetric preconditioner: standard PCG)
+__global__ void __launch_bounds__(kThreads) k_fin_jacobi(const double* __restrict__ partial, int nblocks,
+                                                         double* __restrict__ st, int start) {
+  __shared__ double sh[kThreads];
+  const double Sr = block_sum(partial, nblocks, 0, sh), Srr = block_sum(partial, nblocks, 1, sh);
+  const double Sdr = block_sum(partial, nblocks, 2, sh), Srdr = block_sum(partial, nblocks, 3, sh);
+  if (threadIdx.x != 0) return;
+  if (!start && st[kDone] != 0.0) return;
+  const double n = st[kN], Sd = st[kSumD];
+  const bool proj = st[kProj] != 0.0;
+  const double mu = proj ? Sr / n : 0.0;
+  const double rn2 = Srr - 2.0 * mu * Sr + n * mu * mu;
+  const double muz = proj ? (Sdr - mu * Sd) / n : 0.0;
+  const double rz = (Srdr - 2.0 * mu * Sdr + mu * mu * Sd) - muz * (Sr - n * mu);
+  st[kBeta] = start ? 0.0 : rz / st[kRZ];
+  st[kRZ] = rz;
+  st[kMuR] = mu;
+  st[kMuZ] = muz;
+  st[kRN2] = rn2;
+  account(st, rn2, rz, start != 0);
+}
+
+// p = D^-1 (r - mu) - mu_z + beta p
+__global__ void __launch_bounds__(kThreads) k_update_p_jacobi(const double* __restrict__ r, double* __restrict__ p,
+                                                              const double* __restrict__ dinv, int n3,
+                                                              const double* __restrict__ st, long long n) {
+  const double mu = st[kMuR], muz = st[kMuZ], beta = st[kBeta];
+  for (long long i = blockIdx.x * (long long)kThreads + threadIdx.x; i < n; i += (long long)gridDim.x * kThreads)
+    p[i] = fma(dinv[i % n3], r[i] - mu, -muz) + beta * p[i];
+}
+
+// Chebyshev: mean and norm of the new residual (sums from k_update_xr_st<false>)
+__global__ void __launch_bounds__(kThreads) k_fin_resid(const double* __restrict__ partial, int nblocks,
+                                                        double* __restrict__ st, int start) {
+  __shared__ double sh[kThreads];
+  const double Sr = block_sum(partial, nblocks, 0, sh), Srr = block_sum(partial, nblocks, 1, sh);
+  if (threadIdx.x != 0) return;
+  if (!start && st[kDone] != 0.0) return;
+  const double n = st[kN];
+  const double mu = st[kProj] != 0.0 ? Sr / n : 0.0;
+  const double rn2 = Srr - 2.0 * mu * Sr + n * mu * mu;
+  st[kMuR] = mu;
+  st[kRN2] = rn2;
+  st[kSumRp] = Sr - n * mu;
+  account(st, rn2, 1.0, start != 0);
+}
+
+// Chebyshev start (FP32): r32 = r - mu; x32 = d32 = dinv32 * r32 / theta
+__global__ void __launch_bounds__(kThreads) k_cheb_init_st(const double* __restrict__ r, float* __restrict__ r32,
+                                                           float* __restrict__ x32, float* __restrict__ d32,
+                                                           const float* __restrict__ dinv32, int n3,
+                                                           const double* __restrict__ st, float inv_theta,
+                                                           long long n) {
+  const double mu = st[kMuR];
+  for (long long i = blockIdx.x * (long long)kThreads + threadIdx.x; i < n; i += (long long)gridDim.x * kThreads) {
+    const float rf = (float)(r[i] - mu);
+    r32[i] = rf;
+    const float di = dinv32[i % n3] * rf * inv_theta;
+    x32[i] = di;
+    d32[i] = di;
+  }
+}
+
+// partials of z = x32: sum z, r'.z, r'.zold
+__global__ void __launch_bounds__(kThreads) k_cheb_sums(const double* __restrict__ r, const float* __restrict__ x32,
+                                                        const double* __restrict__ zold,
+                                                        const double* __restrict__ st, long long n, double* partial) {
+  const double mu = st[kMuR];
+  double v[3] = {0, 0, 0};
+  for (long long i = blockIdx.x * (long long)kThreads + threadIdx.x; i < n; i += (long long)gridDim.x * kThreads) {
+    const double ri = r[i] - mu, zi = (double)x32[i];
+    v[0] += zi;
+    v[1] += ri * zi;
+    v[2] += ri * zold[i];
+  }
+  block_partials<3>(v, partial);
+}
+
+// flexible beta = r'.(z' - zold) / rz with z' = z - mu_z
+__global__ void __launch_bounds__(kThreads) k_fin_cheb(const double* __restrict__ partial, int nblocks,
+                                                       double* __restrict__ st, int start) {
+  __shared__ double sh[kThreads];
+  const double Sz = block_sum(partial, nblocks, 0, sh), Srz = block_sum(partial, nblocks, 1, sh);
+  const double Srzo = block_sum(partial, nblocks, 2, sh);
+  if (threadIdx.x != 0) return;
+  if (!start && st[kDone] != 0.0) return;
+  const double muz = st[kProj] != 0.0 ? Sz / st[kN] : 0.0;
+  const double rz = Srz - muz * st[kSumRp];
+  st[kBeta] = start ? 0.0 : (rz - Srzo) / st[kRZ];
+  st[kRZ] = rz;
+  st[kMuZ] = muz;
+  if (!isfinite(rz)) {
+    st[kDone] = 1.0;
+    st[kStatus] = 2.0;
+  }
+}
+
+// z = x32 - mu_z; zold = z; p = z + beta p
+__global__ void __launch_bounds__(kThreads) k_update_p_cheb(const float* __restrict__ x32, double* __restrict__ p,
+                                                            double* __restrict__ zold, const double* __restrict__ st,
+                                                            long long n) {
+  const double muz = st[kMuZ], beta = st[kBeta];
+  for (long long i = blockIdx.x * (long long)kThreads + threadIdx.x; i < n; i += (long long)gridDim.x * kThreads) {
+    const double zi = (double)x32[i] - muz;
+    zold[i] = zi;
+    p[i] = zi + beta * p[i];
+  }
+}
+
+// state set-up: zero, then the constants
+__global__ void k_state_init(double* __restrict__ st, double tol2, double max_it, double sum_d, double n,
+                             double proj) {
+  if (threadIdx.x < kStateSize) st[threadIdx.x] = 0.0;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    st[kTol2] = tol2;
+    st[kMaxIt] = max_it;
+    st[kSumD] = sum_d;
+    st[kN] = n;
+    st[kProj] = proj;
+  }
+}
+
 }  // namespace
 
 #define DG_LAUNCH(kern, ...)                                                                  \
@@ -237,5 +454,47 @@ hipError_t cg_axpb(double* y, const double* x, double a, double c, long long n, 
   DG_LAUNCH(k_axpb, y, x, a, c, n);
 }
 hipError_t cg_fill(double* y, double c, long long n, hipStream_t s) { DG_LAUNCH(k_fill, y, c, n); }
+
+hipError_t cg_state_init(double* st, double tol2, int max_it, double sum_d, long long n, bool proj, hipStream_t s) {
+  hipLaunchKernelGGL(k_state_init, dim3(1), dim3(64), 0, s, st, tol2, (double)max_it, sum_d, (double)n,
+                     proj ? 1.0 : 0.0);
+  return hipGetLastError();
+}
+hipError_t cg_fin_alpha(const double* partial, double* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_fin_alpha, dim3(1), dim3(kThreads), 0, s, partial, kCgBlocks, st);
+  return hipGetLastError();
+}
+hipError_t cg_update_xr_st(double* x, double* r, const double* p, const double* q, const double* dinv, int n3,
+                           const double* st, bool jacobi, long long n, double* partial, hipStream_t s) {
+  if (jacobi) DG_LAUNCH(k_update_xr_st<true>, x, r, p, q, dinv, n3, st, n, partial);
+  DG_LAUNCH(k_update_xr_st<false>, x, r, p, q, dinv, n3, st, n, partial);
+}
+hipError_t cg_fin_jacobi(const double* partial, double* st, bool start, hipStream_t s) {
+  hipLaunchKernelGGL(k_fin_jacobi, dim3(1), dim3(kThreads), 0, s, partial, kCgBlocks, st, start ? 1 : 0);
+  return hipGetLastError();
+}
+hipError_t cg_update_p_jacobi(const double* r, double* p, const double* dinv, int n3, const double* st, long long n,
+                              hipStream_t s) {
+  DG_LAUNCH(k_update_p_jacobi, r, p, dinv, n3, st, n);
+}
+hipError_t cg_fin_resid(const double* partial, double* st, bool start, hipStream_t s) {
+  hipLaunchKernelGGL(k_fin_resid, dim3(1), dim3(kThreads), 0, s, partial, kCgBlocks, st, start ? 1 : 0);
+  return hipGetLastError();
+}
+hipError_t cg_cheb_init_st(const double* r, float* r32, float* x32, float* d32, const float* dinv32, int n3,
+                           const double* st, float inv_theta, long long n, hipStream_t s) {
+  DG_LAUNCH(k_cheb_init_st, r, r32, x32, d32, dinv32, n3, st, inv_theta, n);
+}
+hipError_t cg_cheb_sums(const double* r, const float* x32, const double* zold, const double* st, long long n,
+                        double* partial, hipStream_t s) {
+  DG_LAUNCH(k_cheb_sums, r, x32, zold, st, n, partial);
+}
+hipError_t cg_fin_cheb(const double* partial, double* st, bool start, hipStream_t s) {
+  hipLaunchKernelGGL(k_fin_cheb, dim3(1), dim3(kThreads), 0, s, partial, kCgBlocks, st, start ? 1 : 0);
+  return hipGetLastError();
+}
+hipError_t cg_update_p_cheb(const float* x32, double* p, double* zold, const double* st, long long n, hipStream_t s) {
+  DG_LAUNCH(k_update_p_cheb, x32, p, zold, st, n);
+}
 
 }  // namespace dgmf

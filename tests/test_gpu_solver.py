@@ -54,7 +54,10 @@ def _solve_and_check(k, N, tol_err):
         assert rep["true_rel_res"] < 1e-9, rep
         out[name] = rep
     assert out["cheb"]["iterations"] * 3 < out["jacobi"]["iterations"], out
-    assert out["cheb"]["matvec_f32"] == 4 * (out["cheb"]["iterations"] + 1)
+    # operator applications launched: iterations queued past convergence are
+    # no-ops but still counted, at most a few
+    it_c = out["cheb"]["iterations"]
+    assert 4 * (it_c + 1) <= out["cheb"]["matvec_f32"] <= 4 * (it_c + 1 + 4)
     return out
 
 
