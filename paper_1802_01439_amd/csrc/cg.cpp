@@ -1,9 +1,15 @@
 // Preconditioned CG for the SIPG pressure Poisson problem (Sec. 3.3), host
 // driver.  Everything of size N_DoFs lives on the GPU: the FP64 operator
 // applies, residuals, dot products and the x, r, p updates; with the
-// Chebyshev preconditioner the smoother runs FP32 operator applies.  The host
-// only holds the few scalars of each iteration (two device-to-host reads per
-// iteration).
+// Chebyshev preconditioner the smoother runs FP32 operator applies.  The
+// iteration scalars stay on the device; the host reads them once per batch
+// of iterations.  Vector work is fused into the operator applies where that
+// measured faster: the FP64 apply sums p.Ap in its epilogue, each FP32 apply
+// performs its Chebyshev step in the epilogue (the first one forms its
+// operand from the FP64 residual, the last one sums what the flexible beta
+// needs).  Per iteration: FP64 apply with the p.Ap
+// sums, x/r update, the FP32 applies, p update, and one-workgroup kernels
+// finishing the sums.
 //
 // Variant: flexible (Polak-Ribiere) CG, beta = r+.(z+ - z)/(r.z), so that a
 // single-precision preconditioner that is symmetric only up to rounding keeps
@@ -30,6 +36,7 @@
 
 #include "api_internal.h"
 #include "cg_kernels.h"
+#include "cg_laplace.h"
 #include "dgmf.h"
 #include "ops.h"
 
@@ -40,8 +47,9 @@ namespace {
 struct Workspace {
   long long n = 0;
   double *r = nullptr, *p = nullptr, *q = nullptr, *z = nullptr, *zold = nullptr, *tmp = nullptr;
-  float *r32 = nullptr, *x32 = nullptr, *d32 = nullptr, *t32 = nullptr;
-  double* partial = nullptr;   // 8 * kCgBlocks
+  float *r32 = nullptr, *x32 = nullptr, *d32 = nullptr, *t32 = nullptr, *za32 = nullptr, *zb32 = nullptr;
+  double* partial = nullptr;   // npartial doubles
+  long npartial = 0;
   double* res = nullptr;       // 8 results (device)
   double* host = nullptr;      // 8 results (pinned host)
   double* st = nullptr;        // main-loop state (device), kStateSize
@@ -53,9 +61,16 @@ struct Workspace {
 std::mutex g_ws_mutex;
 std::map<int, Workspace> g_ws;
 
-hipError_t ensure(Workspace& w, long long n) {
+hipError_t ensure(Workspace& w, long long n, long npartial) {
   hipError_t e;
-  if (!w.partial && (e = hipMalloc((void**)&w.partial, 8 * kCgBlocks * sizeof(double))) != hipSuccess) return e;
+  npartial = std::max<long>(npartial, 8L * kCgBlocks);
+  if (w.npartial < npartial) {
+    if (w.partial) (void)hipFree(w.partial);
+    w.partial = nullptr;
+    w.npartial = 0;
+    if ((e = hipMalloc((void**)&w.partial, npartial * sizeof(double))) != hipSuccess) return e;
+    w.npartial = npartial;
+  }
   if (!w.res && (e = hipMalloc((void**)&w.res, 8 * sizeof(double))) != hipSuccess) return e;
   if (!w.host && (e = hipHostMalloc((void**)&w.host, 8 * sizeof(double), 0)) != hipSuccess) return e;
   if (!w.st && (e = hipMalloc((void**)&w.st, kStateSize * sizeof(double))) != hipSuccess) return e;
@@ -64,7 +79,7 @@ hipError_t ensure(Workspace& w, long long n) {
   if (!w.dinv32 && (e = hipMalloc((void**)&w.dinv32, 1728 * sizeof(float))) != hipSuccess) return e;
   if (w.n >= n) return hipSuccess;
   double** d8[] = {&w.r, &w.p, &w.q, &w.z, &w.zold, &w.tmp};
-  float** d4[] = {&w.r32, &w.x32, &w.d32, &w.t32};
+  float** d4[] = {&w.r32, &w.x32, &w.d32, &w.t32, &w.za32, &w.zb32};
   for (double** pp : d8) {
     if (*pp) (void)hipFree(*pp);
     *pp = nullptr;
@@ -176,11 +191,13 @@ extern "C" int dg_cg_solve(const dg_op_desc* desc, const dg_cg_opts* opts, const
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
   Workspace& W = g_ws[dev];
-  if ((e = ensure(W, n)) != hipSuccess) return hip_fail(e, "CG workspace allocation");
+  const LaplacePlan LP = make_laplace_plan(desc, 1);
+  const long grid64 = cg_apply_grid(LP, false), grid32 = cg_apply_grid(LP, true);
+  if ((e = ensure(W, n, std::max(grid64, 3 * grid32))) != hipSuccess) return hip_fail(e, "CG workspace allocation");
 
   Solver S;
   S.desc = desc;
-  S.P = make_laplace_plan(desc, 1);
+  S.P = LP;
   S.w = &W;
   S.s = (hipStream_t)hip_stream;
   S.n = n;
@@ -273,33 +290,55 @@ extern "C" int dg_cg_solve(const dg_op_desc* desc, const dg_cg_opts* opts, const
   for (long long i = 0; i < n3; ++i) sum_d += dinv[i];
   sum_d *= (double)num_elements(desc);
   S.ok(cg_state_init(W.st, tol * tol, opts->max_iter, sum_d, n, S.project, S.s));
+  // FP32 double buffers, rotated by the host in enqueue order (iterations
+  // queued after convergence rotate them too; they no longer touch x):
+  //   Xb: intermediate Chebyshev iterates, read by one apply, written by another
+  //   Zb: smoother outputs, the current one and the one before (flexible beta)
+  float* Xb[2] = {W.x32, W.t32};
+  float* Zb[2] = {W.za32, W.zb32};
+  int zn = 0;     // Zb[zn]: next smoother output; Zb[1 - zn]: the latest one
   S.ok(cg_fill(W.p, 0.0, n, S.s));
-  S.ok(cg_fill(W.zold, 0.0, n, S.s));
-  // z = M^-1 r' and the scalars of the current residual (sums of r from the
-  // x/r update); then p = z + beta p
-  auto precondition_and_p = [&](bool start) {
+  if (cheb) S.ok(cg_fill32(Zb[1], 0.0f, n, S.s));
+  const int napp = cheb ? opts->cheb_degree - 1 : 0;
+  // scalars of the current residual (sums of r from the x/r update), then
+  // z = M^-1 r' with the sums of the flexible beta
+  auto precondition = [&](bool start) {
     if (!cheb) {
       S.ok(cg_fin_jacobi(W.partial, W.st, start, S.s));
       S.ok(cg_update_p_jacobi(W.r, W.p, W.dinv, S.n3, W.st, n, S.s));
       return;
     }
     S.ok(cg_fin_resid(W.partial, W.st, start, S.s));
-    S.ok(cg_cheb_init_st(W.r, W.r32, W.x32, W.d32, W.dinv32, S.n3, W.st, (float)(1.0 / theta), n, S.s));
+    if (napp == 0) {
+      S.ok(cg_cheb1(W.r, Zb[zn], Zb[1 - zn], W.dinv32, S.n3, W.st, (float)(1.0 / theta), n, W.partial, S.s));
+    }
     double rho_prev = delta / theta;
-    for (int k = 1; k < opts->cheb_degree; ++k) {
+    for (int j = 1; j <= napp; ++j) {
       const double rho = 1.0 / (2.0 * theta / delta - rho_prev);
-      S.apply32(W.x32, W.t32);
-      S.ok(cg_cheb_step(W.x32, W.d32, W.r32, W.t32, W.dinv32, S.n3, (float)(rho * rho_prev),
-                        (float)(2.0 * rho / delta), n, S.s));
+      ChebStepArgs a{};
+      a.r = W.r;
+      a.xin = j == 1 ? nullptr : Xb[(j - 1) % 2];
+      a.xout = j == napp ? Zb[zn] : Xb[j % 2];
+      a.d = W.d32;
+      a.r32 = W.r32;
+      a.dinv = W.dinv32;
+      a.zprev = Zb[1 - zn];
+      a.st = W.st;
+      a.partial = W.partial;
+      a.c1 = (float)(rho * rho_prev);
+      a.c2 = (float)(2.0 * rho / delta);
+      a.inv_theta = (float)(1.0 / theta);
+      ++S.matvec32;
+      S.ok(cg_apply_cheb(LP, j == 1, j == napp, a, S.s));
       rho_prev = rho;
     }
-    S.ok(cg_cheb_sums(W.r, W.x32, W.zold, W.st, n, W.partial, S.s));
-    S.ok(cg_fin_cheb(W.partial, W.st, start, S.s));
-    S.ok(cg_update_p_cheb(W.x32, W.p, W.zold, W.st, n, S.s));
+    S.ok(cg_fin_cheb(W.partial, napp == 0 ? kCgBlocks : (int)grid32, W.st, start, S.s));
+    S.ok(cg_update_p_cheb(Zb[zn], W.p, W.st, n, S.s));
+    zn = 1 - zn;
   };
   // start: alpha is 0 in the fresh state, so this only forms the sums of r0
   S.ok(cg_update_xr_st(x, W.r, W.p, W.q, W.dinv, S.n3, W.st, !cheb, n, W.partial, S.s));
-  precondition_and_p(true);
+  precondition(true);
   // batch size: up to max_batch, fewer when the observed contraction rate
   // says the tolerance is that close (keeps queued no-op iterations rare)
   const int max_batch = cheb ? 4 : 8;
@@ -321,11 +360,12 @@ extern "C" int dg_cg_solve(const dg_op_desc* desc, const dg_cg_opts* opts, const
     rn2_prev = HS[kRN2];
     it_prev = HS[kIter];
     for (int b2 = 0; b2 < batch; ++b2) {
-      S.apply64(W.p, W.q);
-      S.ok(cg_dot(W.p, W.q, n, W.partial, S.s));
-      S.ok(cg_fin_alpha(W.partial, W.st, S.s));
+      // q = A p with the p.q partials
+      ++S.matvec64;
+      S.ok(cg_apply_dot(LP, W.p, W.q, W.partial, S.s));
+      S.ok(cg_fin_alpha(W.partial, (int)grid64, W.st, S.s));
       S.ok(cg_update_xr_st(x, W.r, W.p, W.q, W.dinv, S.n3, W.st, !cheb, n, W.partial, S.s));
-      precondition_and_p(false);
+      precondition(false);
     }
     queued += batch;
     if (S.err != hipSuccess) return hip_fail(S.err, "CG iteration");

@@ -38,30 +38,23 @@ hipError_t cg_update_xr(double* x, double* r, const double* p, const double* q, 
 hipError_t cg_jacobi(double* r, double* z, const double* zold, const double* dinv, int n3, double mu_r, long long n,
                      double* partial, hipStream_t s);
 hipError_t cg_update_p(double* z, double* p, double* zold, double mu_z, double beta, long long n, hipStream_t s);
-hipError_t cg_cheb_init(double* r, float* r32, float* x32, float* d32, const float* dinv32, int n3, double mu_r,
-                        float inv_theta, long long n, hipStream_t s);
-hipError_t cg_cheb_step(float* x32, float* d32, const float* r32, const float* t32, const float* dinv32, int n3,
-                        float c1, float c2, long long n, hipStream_t s);
-hipError_t cg_cheb_final(const double* r, double* z, const double* zold, const float* x32, long long n,
-                         double* partial, hipStream_t s);
 hipError_t cg_hash_fill(double* v, unsigned long long seed, long long n, double* partial, hipStream_t s);
 hipError_t cg_axpb(double* y, const double* x, double a, double c, long long n, hipStream_t s);
 hipError_t cg_fill(double* y, double c, long long n, hipStream_t s);
 
 // main loop with device-side scalars
 hipError_t cg_state_init(double* st, double tol2, int max_it, double sum_d, long long n, bool proj, hipStream_t s);
-hipError_t cg_fin_alpha(const double* partial, double* st, hipStream_t s);
+hipError_t cg_fin_alpha(const double* partial, int nblocks, double* st, hipStream_t s);
 hipError_t cg_update_xr_st(double* x, double* r, const double* p, const double* q, const double* dinv, int n3,
                            const double* st, bool jacobi, long long n, double* partial, hipStream_t s);
 hipError_t cg_fin_jacobi(const double* partial, double* st, bool start, hipStream_t s);
+hipError_t cg_fin_resid(const double* partial, double* st, bool start, hipStream_t s);
+hipError_t cg_fin_cheb(const double* partial, int nblocks, double* st, bool start, hipStream_t s);
+hipError_t cg_cheb1(const double* r, float* z, const float* zprev, const float* dinv32, int n3, const double* st,
+                    float inv_theta, long long n, double* partial, hipStream_t s);
+hipError_t cg_fill32(float* y, float c, long long n, hipStream_t s);
 hipError_t cg_update_p_jacobi(const double* r, double* p, const double* dinv, int n3, const double* st, long long n,
                               hipStream_t s);
-hipError_t cg_fin_resid(const double* partial, double* st, bool start, hipStream_t s);
-hipError_t cg_cheb_init_st(const double* r, float* r32, float* x32, float* d32, const float* dinv32, int n3,
-                           const double* st, float inv_theta, long long n, hipStream_t s);
-hipError_t cg_cheb_sums(const double* r, const float* x32, const double* zold, const double* st, long long n,
-                        double* partial, hipStream_t s);
-hipError_t cg_fin_cheb(const double* partial, double* st, bool start, hipStream_t s);
-hipError_t cg_update_p_cheb(const float* x32, double* p, double* zold, const double* st, long long n, hipStream_t s);
+hipError_t cg_update_p_cheb(const float* z, double* p, const double* st, long long n, hipStream_t s);
 
 }  // namespace dgmf

@@ -115,51 +115,8 @@ __global__ void __launch_bounds__(kThreads) k_update_p(double* __restrict__ z, d
   }
 }
 
-// Chebyshev start (FP32): r <- r - mu_r (FP64, written back); r32 = r;
-// x32 = d32 = dinv32 * r32 / theta
-__global__ void __launch_bounds__(kThreads) k_cheb_init(double* __restrict__ r, float* __restrict__ r32,
-                                                        float* __restrict__ x32, float* __restrict__ d32,
-                                                        const float* __restrict__ dinv32, int n3, double mu_r,
-                                                        float inv_theta, long long n) {
-  for (long long i = blockIdx.x * (long long)kThreads + threadIdx.x; i < n; i += (long long)gridDim.x * kThreads) {
-    const double ri = r[i] - mu_r;
-    r[i] = ri;
-    const float rf = (float)ri;
-    r32[i] = rf;
-    const float di = dinv32[i % n3] * rf * inv_theta;
-    x32[i] = di;
-    d32[i] = di;
-  }
-}
 
-// d32 = c1 d32 + c2 dinv32 (r32 - t32); x32 += d32
-__global__ void __launch_bounds__(kThreads) k_cheb_step(float* __restrict__ x32, float* __restrict__ d32,
-                                                        const float* __restrict__ r32, const float* __restrict__ t32,
-                                                        const float* __restrict__ dinv32, int n3, float c1, float c2,
-                                                        long long n) {
-  for (long long i = blockIdx.x * (long long)kThreads + threadIdx.x; i < n; i += (long long)gridDim.x * kThreads) {
-    const float d = c1 * d32[i] + c2 * dinv32[i % n3] * (r32[i] - t32[i]);
-    d32[i] = d;
-    x32[i] += d;
-  }
-}
 
-// z = (double) x32; partials: sum z, r.z, r.zold, r.r   (r already projected)
-__global__ void __launch_bounds__(kThreads) k_cheb_final(const double* __restrict__ r, double* __restrict__ z,
-                                                         const double* __restrict__ zold, const float* __restrict__ x32,
-                                                         long long n, double* partial) {
-  double v[4] = {0, 0, 0, 0};
-  for (long long i = blockIdx.x * (long long)kThreads + threadIdx.x; i < n; i += (long long)gridDim.x * kThreads) {
-    const double ri = r[i];
-    const double zi = (double)x32[i];
-    z[i] = zi;
-    v[0] += zi;
-    v[1] += ri * zi;
-    v[2] += ri * zold[i];
-    v[3] += ri * ri;
-  }
-  block_partials<4>(v, partial);
-}
 
 // v[i] = uniform[-1,1) from a splitmix64 hash of (i, seed); partial sum v
 __global__ void __launch_bounds__(kThreads) k_hash_fill(double* __restrict__ v, unsigned long long seed, long long n,
@@ -206,26 +163,41 @@ __global__ void __launch_bounds__(kThreads) k_fill(double* __restrict__ y, doubl
 // S_rdr = sum d r^2 (S_d = sum d is a setup constant).  r itself is stored
 // unprojected; every use subtracts mu.
 
-// Sum of partial[q * nblocks + i] over i, fixed order; valid in thread 0.
-__device__ double block_sum(const double* __restrict__ partial, int nblocks, int q, double* sh) {
-  double s = 0;
-  for (int i = threadIdx.x; i < nblocks; i += kThreads) s += partial[q * nblocks + i];
-  sh[threadIdx.x] = s;
-  __syncthreads();
-  for (int st = kThreads / 2; st > 0; st >>= 1) {
-    if ((int)threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
-    __syncthreads();
+// Sums of partial[q * nblocks + i] over i for q < NQ, in a fixed order
+// (thread-strided, then across the wavefront, then across the 4 wavefronts);
+// valid in thread 0.
+template <int NQ>
+__device__ __forceinline__ void block_sums(const double* __restrict__ partial, int nblocks, double (&out)[NQ]) {
+  static_assert(kThreads == 256, "four full wavefronts");
+  __shared__ double sh[NQ][kThreads / 64];
+  double s[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) s[q] = 0.0;
+  for (int i = threadIdx.x; i < nblocks; i += kThreads) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) s[q] += partial[(size_t)q * nblocks + i];
   }
-  const double v = sh[0];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s[q] += __shfl_xor(s[q], o, 64);
+  }
+  const int w = threadIdx.x / 64;
+  if (threadIdx.x % 64 == 0) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) sh[q][w] = s[q];
+  }
   __syncthreads();
-  return v;
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) out[q] = ((sh[q][0] + sh[q][1]) + sh[q][2]) + sh[q][3];
 }
 
 // alpha = rz / p.q  (p.q from one partial), breakdown if p.q <= 0 or not finite
 __global__ void __launch_bounds__(kThreads) k_fin_alpha(const double* __restrict__ partial, int nblocks,
                                                         double* __restrict__ st) {
-  __shared__ double sh[kThreads];
-  const double pq = block_sum(partial, nblocks, 0, sh);
+  double v[1];
+  block_sums<1>(partial, nblocks, v);
+  const double pq = v[0];
   if (threadIdx.x != 0) return;
   if (st[kDone] != 0.0) {
     st[kAlpha] = 0.0;
@@ -286,9 +258,9 @@ __device__ void account(double* st, double rn2, double rz, bool start) {
 // beta = rz_new / rz (a fixed symmetric preconditioner: standard PCG)
 __global__ void __launch_bounds__(kThreads) k_fin_jacobi(const double* __restrict__ partial, int nblocks,
                                                          double* __restrict__ st, int start) {
-  __shared__ double sh[kThreads];
-  const double Sr = block_sum(partial, nblocks, 0, sh), Srr = block_sum(partial, nblocks, 1, sh);
-  const double Sdr = block_sum(partial, nblocks, 2, sh), Srdr = block_sum(partial, nblocks, 3, sh);
+  double v[4];
+  block_sums<4>(partial, nblocks, v);
+  const double Sr = v[0], Srr = v[1], Sdr = v[2], Srdr = v[3];
   if (threadIdx.x != 0) return;
   if (!start && st[kDone] != 0.0) return;
   const double n = st[kN], Sd = st[kSumD];
@@ -305,20 +277,13 @@ __global__ void __launch_bounds__(kThreads) k_fin_jacobi(const double* __restric
   account(st, rn2, rz, start != 0);
 }
 
-// p = D^-1 (r - mu) - mu_z + beta p
-__global__ void __launch_bounds__(kThreads) k_update_p_jacobi(const double* __restrict__ r, double* __restrict__ p,
-                                                              const double* __restrict__ dinv, int n3,
-                                                              const double* __restrict__ st, long long n) {
-  const double mu = st[kMuR], muz = st[kMuZ], beta = st[kBeta];
-  for (long long i = blockIdx.x * (long long)kThreads + threadIdx.x; i < n; i += (long long)gridDim.x * kThreads)
-    p[i] = fma(dinv[i % n3], r[i] - mu, -muz) + beta * p[i];
-}
 
 // Chebyshev: mean and norm of the new residual (sums from k_update_xr_st<false>)
 __global__ void __launch_bounds__(kThreads) k_fin_resid(const double* __restrict__ partial, int nblocks,
                                                         double* __restrict__ st, int start) {
-  __shared__ double sh[kThreads];
-  const double Sr = block_sum(partial, nblocks, 0, sh), Srr = block_sum(partial, nblocks, 1, sh);
+  double v[2];
+  block_sums<2>(partial, nblocks, v);
+  const double Sr = v[0], Srr = v[1];
   if (threadIdx.x != 0) return;
   if (!start && st[kDone] != 0.0) return;
   const double n = st[kN];
@@ -330,43 +295,55 @@ __global__ void __launch_bounds__(kThreads) k_fin_resid(const double* __restrict
   account(st, rn2, 1.0, start != 0);
 }
 
-// Chebyshev start (FP32): r32 = r - mu; x32 = d32 = dinv32 * r32 / theta
-__global__ void __launch_bounds__(kThreads) k_cheb_init_st(const double* __restrict__ r, float* __restrict__ r32,
-                                                           float* __restrict__ x32, float* __restrict__ d32,
-                                                           const float* __restrict__ dinv32, int n3,
-                                                           const double* __restrict__ st, float inv_theta,
-                                                           long long n) {
-  const double mu = st[kMuR];
-  for (long long i = blockIdx.x * (long long)kThreads + threadIdx.x; i < n; i += (long long)gridDim.x * kThreads) {
-    const float rf = (float)(r[i] - mu);
-    r32[i] = rf;
-    const float di = dinv32[i % n3] * rf * inv_theta;
-    x32[i] = di;
-    d32[i] = di;
-  }
+// p = D^-1 (r - mu) - mu_z + beta p
+__global__ void __launch_bounds__(kThreads) k_update_p_jacobi(const double* __restrict__ r, double* __restrict__ p,
+                                                              const double* __restrict__ dinv, int n3,
+                                                              const double* __restrict__ st, long long n) {
+  const double mu = st[kMuR], muz = st[kMuZ], beta = st[kBeta];
+  for (long long i = blockIdx.x * (long long)kThreads + threadIdx.x; i < n; i += (long long)gridDim.x * kThreads)
+    p[i] = fma(dinv[i % n3], r[i] - mu, -muz) + beta * p[i];
 }
 
-// partials of z = x32: sum z, r'.z, r'.zold
-__global__ void __launch_bounds__(kThreads) k_cheb_sums(const double* __restrict__ r, const float* __restrict__ x32,
-                                                        const double* __restrict__ zold,
-                                                        const double* __restrict__ st, long long n, double* partial) {
-  const double mu = st[kMuR];
+// p = (z - mu_z) + beta p, z the FP32 smoother output
+__global__ void __launch_bounds__(kThreads) k_update_p_cheb(const float* __restrict__ z, double* __restrict__ p,
+                                                            const double* __restrict__ st, long long n) {
+  const double muz = st[kMuZ], beta = st[kBeta];
+  for (long long i = blockIdx.x * (long long)kThreads + threadIdx.x; i < n; i += (long long)gridDim.x * kThreads)
+    p[i] = ((double)z[i] - muz) + beta * p[i];
+}
+
+// Chebyshev degree 1 (no operator apply): z = D^-1 r' / theta and the
+// partials sum z, r'.z, r'.(zprev - mu_z_prev) of the flexible beta
+__global__ void __launch_bounds__(kThreads) k_cheb1(const double* __restrict__ r, float* __restrict__ z,
+                                                    const float* __restrict__ zprev,
+                                                    const float* __restrict__ dinv32, int n3,
+                                                    const double* __restrict__ st, float inv_theta, long long n,
+                                                    double* partial) {
+  const double mu = st[kMuR], muzp = st[kMuZ];
   double v[3] = {0, 0, 0};
   for (long long i = blockIdx.x * (long long)kThreads + threadIdx.x; i < n; i += (long long)gridDim.x * kThreads) {
-    const double ri = r[i] - mu, zi = (double)x32[i];
-    v[0] += zi;
-    v[1] += ri * zi;
-    v[2] += ri * zold[i];
+    const double rp = r[i] - mu;
+    const float zf = dinv32[i % n3] * (float)rp * inv_theta;
+    z[i] = zf;
+    const double zd = (double)zf;
+    v[0] += zd;
+    v[1] += rp * zd;
+    v[2] += rp * ((double)zprev[i] - muzp);
   }
   block_partials<3>(v, partial);
+}
+
+__global__ void __launch_bounds__(kThreads) k_fill32(float* __restrict__ y, float c, long long n) {
+  for (long long i = blockIdx.x * (long long)kThreads + threadIdx.x; i < n; i += (long long)gridDim.x * kThreads)
+    y[i] = c;
 }
 
 // flexible beta = r'.(z' - zold) / rz with z' = z - mu_z
 __global__ void __launch_bounds__(kThreads) k_fin_cheb(const double* __restrict__ partial, int nblocks,
                                                        double* __restrict__ st, int start) {
-  __shared__ double sh[kThreads];
-  const double Sz = block_sum(partial, nblocks, 0, sh), Srz = block_sum(partial, nblocks, 1, sh);
-  const double Srzo = block_sum(partial, nblocks, 2, sh);
+  double v[3];
+  block_sums<3>(partial, nblocks, v);
+  const double Sz = v[0], Srz = v[1], Srzo = v[2];
   if (threadIdx.x != 0) return;
   if (!start && st[kDone] != 0.0) return;
   const double muz = st[kProj] != 0.0 ? Sz / st[kN] : 0.0;
@@ -377,18 +354,6 @@ __global__ void __launch_bounds__(kThreads) k_fin_cheb(const double* __restrict_
   if (!isfinite(rz)) {
     st[kDone] = 1.0;
     st[kStatus] = 2.0;
-  }
-}
-
-// z = x32 - mu_z; zold = z; p = z + beta p
-__global__ void __launch_bounds__(kThreads) k_update_p_cheb(const float* __restrict__ x32, double* __restrict__ p,
-                                                            double* __restrict__ zold, const double* __restrict__ st,
-                                                            long long n) {
-  const double muz = st[kMuZ], beta = st[kBeta];
-  for (long long i = blockIdx.x * (long long)kThreads + threadIdx.x; i < n; i += (long long)gridDim.x * kThreads) {
-    const double zi = (double)x32[i] - muz;
-    zold[i] = zi;
-    p[i] = zi + beta * p[i];
   }
 }
 
@@ -435,18 +400,6 @@ hipError_t cg_jacobi(double* r, double* z, const double* zold, const double* din
 hipError_t cg_update_p(double* z, double* p, double* zold, double mu_z, double beta, long long n, hipStream_t s) {
   DG_LAUNCH(k_update_p, z, p, zold, mu_z, beta, n);
 }
-hipError_t cg_cheb_init(double* r, float* r32, float* x32, float* d32, const float* dinv32, int n3, double mu_r,
-                        float inv_theta, long long n, hipStream_t s) {
-  DG_LAUNCH(k_cheb_init, r, r32, x32, d32, dinv32, n3, mu_r, inv_theta, n);
-}
-hipError_t cg_cheb_step(float* x32, float* d32, const float* r32, const float* t32, const float* dinv32, int n3,
-                        float c1, float c2, long long n, hipStream_t s) {
-  DG_LAUNCH(k_cheb_step, x32, d32, r32, t32, dinv32, n3, c1, c2, n);
-}
-hipError_t cg_cheb_final(const double* r, double* z, const double* zold, const float* x32, long long n,
-                         double* partial, hipStream_t s) {
-  DG_LAUNCH(k_cheb_final, r, z, zold, x32, n, partial);
-}
 hipError_t cg_hash_fill(double* v, unsigned long long seed, long long n, double* partial, hipStream_t s) {
   DG_LAUNCH(k_hash_fill, v, seed, n, partial);
 }
@@ -460,8 +413,8 @@ hipError_t cg_state_init(double* st, double tol2, int max_it, double sum_d, long
                      proj ? 1.0 : 0.0);
   return hipGetLastError();
 }
-hipError_t cg_fin_alpha(const double* partial, double* st, hipStream_t s) {
-  hipLaunchKernelGGL(k_fin_alpha, dim3(1), dim3(kThreads), 0, s, partial, kCgBlocks, st);
+hipError_t cg_fin_alpha(const double* partial, int nblocks, double* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_fin_alpha, dim3(1), dim3(kThreads), 0, s, partial, nblocks, st);
   return hipGetLastError();
 }
 hipError_t cg_update_xr_st(double* x, double* r, const double* p, const double* q, const double* dinv, int n3,
@@ -473,28 +426,25 @@ hipError_t cg_fin_jacobi(const double* partial, double* st, bool start, hipStrea
   hipLaunchKernelGGL(k_fin_jacobi, dim3(1), dim3(kThreads), 0, s, partial, kCgBlocks, st, start ? 1 : 0);
   return hipGetLastError();
 }
-hipError_t cg_update_p_jacobi(const double* r, double* p, const double* dinv, int n3, const double* st, long long n,
-                              hipStream_t s) {
-  DG_LAUNCH(k_update_p_jacobi, r, p, dinv, n3, st, n);
-}
 hipError_t cg_fin_resid(const double* partial, double* st, bool start, hipStream_t s) {
   hipLaunchKernelGGL(k_fin_resid, dim3(1), dim3(kThreads), 0, s, partial, kCgBlocks, st, start ? 1 : 0);
   return hipGetLastError();
 }
-hipError_t cg_cheb_init_st(const double* r, float* r32, float* x32, float* d32, const float* dinv32, int n3,
-                           const double* st, float inv_theta, long long n, hipStream_t s) {
-  DG_LAUNCH(k_cheb_init_st, r, r32, x32, d32, dinv32, n3, st, inv_theta, n);
-}
-hipError_t cg_cheb_sums(const double* r, const float* x32, const double* zold, const double* st, long long n,
-                        double* partial, hipStream_t s) {
-  DG_LAUNCH(k_cheb_sums, r, x32, zold, st, n, partial);
-}
-hipError_t cg_fin_cheb(const double* partial, double* st, bool start, hipStream_t s) {
-  hipLaunchKernelGGL(k_fin_cheb, dim3(1), dim3(kThreads), 0, s, partial, kCgBlocks, st, start ? 1 : 0);
+hipError_t cg_fin_cheb(const double* partial, int nblocks, double* st, bool start, hipStream_t s) {
+  hipLaunchKernelGGL(k_fin_cheb, dim3(1), dim3(kThreads), 0, s, partial, nblocks, st, start ? 1 : 0);
   return hipGetLastError();
 }
-hipError_t cg_update_p_cheb(const float* x32, double* p, double* zold, const double* st, long long n, hipStream_t s) {
-  DG_LAUNCH(k_update_p_cheb, x32, p, zold, st, n);
+hipError_t cg_cheb1(const double* r, float* z, const float* zprev, const float* dinv32, int n3, const double* st,
+                    float inv_theta, long long n, double* partial, hipStream_t s) {
+  DG_LAUNCH(k_cheb1, r, z, zprev, dinv32, n3, st, inv_theta, n, partial);
+}
+hipError_t cg_fill32(float* y, float c, long long n, hipStream_t s) { DG_LAUNCH(k_fill32, y, c, n); }
+hipError_t cg_update_p_jacobi(const double* r, double* p, const double* dinv, int n3, const double* st, long long n,
+                              hipStream_t s) {
+  DG_LAUNCH(k_update_p_jacobi, r, p, dinv, n3, st, n);
+}
+hipError_t cg_update_p_cheb(const float* z, double* p, const double* st, long long n, hipStream_t s) {
+  DG_LAUNCH(k_update_p_cheb, z, p, st, n);
 }
 
 }  // namespace dgmf
