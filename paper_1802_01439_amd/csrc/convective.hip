@@ -85,16 +85,22 @@ struct ConvShape {
   // than with the two that fit the budget (200 pencils in 256 threads)
   static constexpr int E0 = (52 * 1024) / BYTES;
   static constexpr int E = (N == 7 && SZ == 8) ? 3 : (E0 < 1 ? 1 : (E0 > 16 ? 16 : E0));
-  // per-component mode keeps one z pencil per thread in registers; at the
-  // highest degrees (one element, one workgroup per CU) 512 threads hide
-  // more latency, below that a larger group only lowers the register limit
+  // per-component mode keeps one z pencil per thread in registers.  Where
+  // one workgroup fills a CU's LDS (the highest degrees, FP64 k=6) 512
+  // threads hide more latency (FP64 k=6: 10 % faster than 320); below that
+  // a larger group only lowers the register limit
   static constexpr int TH0 = (E * Q * Q > 256) ? ((E * Q * Q + 63) / 64) * 64 : 256;
-  static constexpr int TH = (E == 1 && Q >= 16) ? 512 : TH0;
+  static constexpr int TH = ((E == 1 && Q >= 16) || E * BYTES > 80 * 1024) ? (TH0 > 512 ? TH0 : 512) : TH0;
+  // minimum wavefronts per SIMD (register cap) where registers, not LDS,
+  // limited the groups per CU: at 128 VGPRs FP32 k=11 fits two 512-thread
+  // groups (33 % faster despite a small spill) and FP32 k=6 four 256-thread
+  // groups (15 % faster)
+  static constexpr int MINW = (N == 12 && SZ == 4) ? 4 : (N == 7 && SZ == 4) ? 4 : 1;
   static_assert(E * PER * SZ <= 160 * 1024, "convective LDS footprint exceeds 160 KB");
 };
 
 template <int N, int Q, typename T, int E, int TH, bool ALLC>
-__global__ void __launch_bounds__(TH)
+__global__ void __launch_bounds__(TH) __attribute__((amdgpu_waves_per_eu(ConvShape<N, Q, (int)sizeof(T)>::MINW, 8)))
 convective_kernel(const T* __restrict__ u, T* __restrict__ r, MeshArgs mesh,
                   const ConvTab<N, Q, T>* __restrict__ tab, ConvScal<T> sc) {
   using Sh = ConvShape<N, Q, (int)sizeof(T)>;

@@ -372,6 +372,9 @@ laplace_batch_kernel(IO io, MeshArgs mesh, Traversal tv, const LapTab<N, T>* __r
   io.template finish<C::THREADS, sizeof(UV)>(UV);
 }
 
+// Workgroups a march launch aims at (z segments are sized for it).
+constexpr long kLapMarchWGs = 2048;
+
 // Work of one marching workgroup: tile (tx, ty) of component comp, z layers [z0, z1).
 struct LapWork {
   int ntx, nty, nseg, lz;   // tiles per direction, z segments, layers per segment
@@ -681,7 +684,7 @@ long lap_grid(const LaplacePlan& P) {
     using C = LapCfg<N>;
     const long ntx = (P.mesh.nx + C::TX - 1) / C::TX, nty = (P.mesh.ny + C::TY - 1) / C::TY;
     const long tiles = ntx * nty * P.n_comp;
-    const long want = std::max(1L, std::min<long>(P.mesh.nz, (2048 + tiles - 1) / tiles));
+    const long want = std::max(1L, std::min<long>(P.mesh.nz, (kLapMarchWGs + tiles - 1) / tiles));
     const long lz = (P.mesh.nz + want - 1) / want;
     return tiles * ((P.mesh.nz + lz - 1) / lz);
   }
@@ -704,13 +707,13 @@ hipError_t launch_laplace_io(const LaplacePlan& P, const IO& io, const LapTab<N,
     hipLaunchKernelGGL((laplace_batch_kernel<N, T, IO>), dim3((unsigned)grid), dim3(CB::THREADS), 0, stream, io,
                        P.mesh, tv, tab);
   } else {
-    // tiles x z segments x components, about 2048 workgroups
+    // tiles x z segments x components, about kLapMarchWGs workgroups
     using C = LapCfg<N>;
     LapWork wk;
     wk.ntx = (P.mesh.nx + C::TX - 1) / C::TX;
     wk.nty = (P.mesh.ny + C::TY - 1) / C::TY;
     const long tiles = (long)wk.ntx * wk.nty * P.n_comp;
-    const int want = (int)std::max(1L, std::min<long>(P.mesh.nz, (2048 + tiles - 1) / tiles));
+    const int want = (int)std::max(1L, std::min<long>(P.mesh.nz, (kLapMarchWGs + tiles - 1) / tiles));
     wk.lz = (P.mesh.nz + want - 1) / want;
     wk.nseg = (P.mesh.nz + wk.lz - 1) / wk.lz;
     const long grid = tiles * wk.nseg;
