@@ -40,7 +40,10 @@ BYTES_PER_DOF = {("laplace", "f64"): 16, ("laplace", "f32"): 8,
                  ("convective", "f64"): 16, ("convective", "f32"): 8,
                  ("vjp", "f64"): 24, ("vjp", "f32"): 12}
 KERNEL_NAME = {"laplace": "laplace_march_kernel|laplace_batch_kernel", "convective": "convective_kernel", "vjp": "convective_vjp_kernel"}
-SOURCES = {"laplace": "laplace.hip", "convective": "convective.hip", "vjp": "convective_vjp.hip"}
+# every source file that defines each kernel (the traffic record is keyed by their hash)
+SOURCES = {"laplace": ("laplace.hip", "laplace_kernels.h", "common.h"),
+           "convective": ("convective.hip", "conv_common.h", "basis_ct.h", "common.h"),
+           "vjp": ("convective_vjp.hip", "conv_common.h", "common.h")}
 
 
 def sweep_mesh(k):
@@ -61,9 +64,11 @@ def conv_flops_per_element(k):
 
 
 def source_hash(op):
-    p = os.path.join(ROOT, "paper_1802_01439_amd", "csrc", SOURCES[op])
-    with open(p, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for name in SOURCES[op]:
+        with open(os.path.join(ROOT, "paper_1802_01439_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def load_traffic(op, k, dtype):
@@ -169,10 +174,12 @@ def cpu_baseline(args):
                        + ", ".join(parts) + ")")}
 
 
-def extras(torch, dgmf, inputs, dev, args):
+def extras(torch, dgmf, inputs, dev, args, which=("vjp", "cg")):
     out = {}
     # convective VJP, k=4, 32^3, TGV + noise velocity and N(0,1) cotangent
     try:
+        if "vjp" not in which:
+            raise _Skip
         k, N = 4, 32
         d = dgmf.make_desc(k, N)
         nodes = dgmf.lgl_nodes(k)
@@ -197,10 +204,14 @@ def extras(torch, dgmf, inputs, dev, args):
             res[dtype] = {"dofs_per_s": dofs / t, "us": t * 1e6,
                           "hbm_frac": BYTES_PER_DOF[("vjp", dtype)] * dofs / t / (HBM_PEAK_GBS * 1e9)}
         out["vjp_k4_32cubed"] = res
+    except _Skip:
+        pass
     except dgmf.DgError as ex:
         out["vjp_k4_32cubed"] = {"error": str(ex)}
     # pressure Poisson CG, k=7, 24^3, rhs = d_h(TGV + noise), zero mean
     try:
+        if "cg" not in which:
+            raise _Skip
         k, N = 7, 24
         d = dgmf.make_desc(k, N)
         nodes = dgmf.lgl_nodes(k)
@@ -214,9 +225,15 @@ def extras(torch, dgmf, inputs, dev, args):
             res[name] = rep
         res["speedup_solve"] = res["jacobi_f64"]["seconds_solve"] / res["chebyshev5_f32"]["seconds_solve"]
         out["cg_k7_24cubed"] = res
+    except _Skip:
+        pass
     except dgmf.DgError as ex:
         out["cg_k7_24cubed"] = {"error": str(ex)}
     return out
+
+
+class _Skip(Exception):
+    pass
 
 
 def main():
@@ -231,6 +248,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--sweep-out", default="")
+    ap.add_argument("--extras-only", default="",
+                    help="diagnostic: run only these extras (vjp,cg), print them as one JSON line, no sweep")
     ap.add_argument("--calib-copy", type=int, default=0,
                     help="also run one plain device copy of this many bytes (counter calibration)")
     args = ap.parse_args()
@@ -246,6 +265,10 @@ def main():
     dgmf.lib()   # fail loudly if the HIP library is missing
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.extras_only:
+        which = tuple(w for w in args.extras_only.split(",") if w)
+        print(json.dumps({"extras": extras(torch, dgmf, inputs, dev, args, which)}), flush=True)
+        return
     print(f"[bench] building inputs for k={args.kmin}..{args.kmax} ops={args.ops}", file=sys.stderr, flush=True)
     cases = build_cases(args, torch, dgmf, inputs, dev)
     torch.cuda.synchronize()
