@@ -372,6 +372,14 @@ laplace_batch_kernel(IO io, MeshArgs mesh, Traversal tv, const LapTab<N, T>* __r
   io.template finish<C::THREADS, sizeof(UV)>(UV);
 }
 
+// Element rows per strip of the batch traversal (measured over 4..32: short
+// strips keep the previous plane in L2 up to n = 8, -3..-10 %; beyond that
+// long strips re-read fewer y-neighbour rows, -4..-6 %).
+template <int N>
+constexpr int lap_strip_rows() {
+  return N <= 8 ? 4 : 32;
+}
+
 // Workgroups a march launch aims at (z segments are sized for it).
 constexpr long kLapMarchWGs = 2048;
 
@@ -701,7 +709,7 @@ hipError_t launch_laplace_io(const LaplacePlan& P, const IO& io, const LapTab<N,
     Traversal tv;
     tv.PB = (P.mesh.nx * P.mesh.ny + CB::E - 1) / CB::E;
     tv.PZ = P.n_comp * P.mesh.nz;
-    tv.S = std::max(1, std::min(tv.PB, (16 * P.mesh.nx + CB::E / 2) / CB::E));
+    tv.S = std::max(1, std::min(tv.PB, (lap_strip_rows<N>() * P.mesh.nx + CB::E / 2) / CB::E));
     const long grid = (long)tv.PB * tv.PZ;
     if (grid > 0x7fffffffL) return hipErrorInvalidConfiguration;
     hipLaunchKernelGGL((laplace_batch_kernel<N, T, IO>), dim3((unsigned)grid), dim3(CB::THREADS), 0, stream, io,
