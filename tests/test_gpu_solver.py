@@ -65,6 +65,41 @@ def test_cg_small_against_fdm():
     _solve_and_check(3, 6, 1e-8)
 
 
+@pytest.mark.parametrize("k,N,cheb_degree,project", [
+    (2, 6, 5, True),    # FP64 march n=3 (252 threads), FP32 march n=3
+    (4, 5, 5, True),    # FP64 march n=5 (250 threads), FP32 march n=5
+    (5, 4, 5, True),    # batch kernels, n=6
+    (3, 4, 1, True),    # Chebyshev degree 1: no operator apply, x1 = D^-1 r / theta
+    (3, 4, 2, True),    # one FP32 apply: first and last step in one kernel
+    (3, 4, 3, True),    # first and last step, no middle one
+    (3, 4, 5, False),   # no mean projection (zero-mean rhs)
+])
+def test_cg_variants_against_fdm(k, N, cheb_degree, project):
+    msh = M.cube(N)
+    u = inputs.tgv_plus_noise(basis.lgl_nodes(k), msh.n_el, msh.length, seed=inputs.FIELD_SEED_BASE + 4)
+    b = poisson_rhs(u, k, msh)
+    x_ref = fdm_solve(b, k, msh)
+    x_ref -= x_ref.mean()
+    d = dgmf.make_desc(k, N)
+    bt = to_dev(b)
+    its = {}
+    for name, pc in (("jacobi", dgmf.DG_PC_JACOBI_F64), ("cheb", dgmf.DG_PC_CHEB_F32)):
+        announce(f"cg k={k} N={N} {name} degree={cheb_degree} project={project}")
+        x, rep, rc = dgmf.cg_solve(d, bt, precond=pc, cheb_degree=cheb_degree, rtol=1e-10, max_iter=20000,
+                                   project_mean=project)
+        assert rc == dgmf.DG_OK, rep
+        xs = x.cpu().numpy()
+        xs -= xs.mean()
+        err = np.linalg.norm(xs - x_ref) / np.linalg.norm(x_ref)
+        assert err < (1e-8 if project else 1e-7), (name, err, rep)
+        assert rep["true_rel_res"] < 1e-9, rep
+        napp = cheb_degree - 1 if name == "cheb" else 0
+        assert napp * (rep["iterations"] + 1) <= rep["matvec_f32"] <= napp * (rep["iterations"] + 5), rep
+        its[name] = rep["iterations"]
+    if cheb_degree >= 3:
+        assert its["cheb"] < its["jacobi"], its
+
+
 def test_cg_config5_full_size_against_fdm():
     """k=7, 24^3 elements (7.1M DoFs), rhs = d_h(TGV + noise) with zero mean, 1e-10."""
     out = _solve_and_check(7, 24, 1e-7)
