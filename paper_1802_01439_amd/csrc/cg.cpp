@@ -22,7 +22,10 @@
 // started from zero in FP32: theta = (lmax+lmin)/2, delta = (lmax-lmin)/2,
 // x1 = D^-1 r / theta, rho_0 = delta/theta, then for each further step
 // rho_k = 1/(2 theta/delta - rho_{k-1}),
-// d_k = rho_k rho_{k-1} d_{k-1} + (2 rho_k/delta) D^-1 (r - A x_k), x += d_k.
+// d_k = rho_k rho_{k-1} d_{k-1} + (2 rho_k/delta) D^-1 (r - A x_k), x += d_k,
+// evaluated in the equivalent three-term form x_{k+1} = x_k + rho_k rho_{k-1}
+// (x_k - x_{k-1}) + (2 rho_k/delta) D^-1 (r - A x_k) with x_0 = 0, so that
+// no step vector is stored.
 // lmax is 1.1x the largest Ritz value of 25 Lanczos steps (plain Jacobi-PCG
 // on a hashed random zero-mean vector); lmin = lmax / range.
 #include <hip/hip_runtime.h>
@@ -47,7 +50,7 @@ namespace {
 struct Workspace {
   long long n = 0;
   double *r = nullptr, *p = nullptr, *q = nullptr, *z = nullptr, *zold = nullptr, *tmp = nullptr;
-  float *r32 = nullptr, *x32 = nullptr, *d32 = nullptr, *t32 = nullptr, *za32 = nullptr, *zb32 = nullptr;
+  float *r32 = nullptr, *x32 = nullptr, *t32 = nullptr, *za32 = nullptr, *zb32 = nullptr;
   double* partial = nullptr;   // npartial doubles
   long npartial = 0;
   double* res = nullptr;       // 8 results (device)
@@ -79,7 +82,7 @@ hipError_t ensure(Workspace& w, long long n, long npartial) {
   if (!w.dinv32 && (e = hipMalloc((void**)&w.dinv32, 1728 * sizeof(float))) != hipSuccess) return e;
   if (w.n >= n) return hipSuccess;
   double** d8[] = {&w.r, &w.p, &w.q, &w.z, &w.zold, &w.tmp};
-  float** d4[] = {&w.r32, &w.x32, &w.d32, &w.t32, &w.za32, &w.zb32};
+  float** d4[] = {&w.r32, &w.x32, &w.t32, &w.za32, &w.zb32};
   for (double** pp : d8) {
     if (*pp) (void)hipFree(*pp);
     *pp = nullptr;
@@ -292,7 +295,8 @@ extern "C" int dg_cg_solve(const dg_op_desc* desc, const dg_cg_opts* opts, const
   S.ok(cg_state_init(W.st, tol * tol, opts->max_iter, sum_d, n, S.project, S.s));
   // FP32 double buffers, rotated by the host in enqueue order (iterations
   // queued after convergence rotate them too; they no longer touch x):
-  //   Xb: intermediate Chebyshev iterates, read by one apply, written by another
+  //   Xb: intermediate Chebyshev iterates x_2, x_3, ...: step j reads x_j from
+  //       Xb[j % 2] and x_{j-1} from Xb[(j + 1) % 2], which x_{j+1} overwrites
   //   Zb: smoother outputs, the current one and the one before (flexible beta)
   float* Xb[2] = {W.x32, W.t32};
   float* Zb[2] = {W.za32, W.zb32};
@@ -317,9 +321,9 @@ extern "C" int dg_cg_solve(const dg_op_desc* desc, const dg_cg_opts* opts, const
       const double rho = 1.0 / (2.0 * theta / delta - rho_prev);
       ChebStepArgs a{};
       a.r = W.r;
-      a.xin = j == 1 ? nullptr : Xb[(j - 1) % 2];
-      a.xout = j == napp ? Zb[zn] : Xb[j % 2];
-      a.d = W.d32;
+      a.xin = j >= 2 ? Xb[j % 2] : nullptr;
+      a.xprev = j >= 3 ? Xb[(j + 1) % 2] : nullptr;
+      a.xout = j == napp ? Zb[zn] : Xb[(j + 1) % 2];
       a.r32 = W.r32;
       a.dinv = W.dinv32;
       a.zprev = Zb[1 - zn];
@@ -329,7 +333,7 @@ extern "C" int dg_cg_solve(const dg_op_desc* desc, const dg_cg_opts* opts, const
       a.c2 = (float)(2.0 * rho / delta);
       a.inv_theta = (float)(1.0 / theta);
       ++S.matvec32;
-      S.ok(cg_apply_cheb(LP, j == 1, j == napp, a, S.s));
+      S.ok(cg_apply_cheb(LP, j, j == napp, a, S.s));
       rho_prev = rho;
     }
     S.ok(cg_fin_cheb(W.partial, napp == 0 ? kCgBlocks : (int)grid32, W.st, start, S.s));

@@ -1,6 +1,6 @@
-// FP32 Chebyshev steps of the CG preconditioner with the step recurrence
-// (and, for the last step, the partial sums the flexible CG needs) fused
-// into the epilogue of the Laplace apply.
+// FP32 Chebyshev steps of the CG preconditioner with the three-term
+// recurrence (and, for the last step, the partial sums the flexible CG needs)
+// fused into the epilogue of the Laplace apply.
 #include "cg_kernels.h"
 #include "cg_laplace.h"
 #include "laplace_kernels.h"
@@ -9,7 +9,11 @@ namespace dgmf {
 
 namespace {
 
-template <bool FIRST, bool LAST>
+// KIND 0: first step (x_{k-1} = x_0 = 0, operand x_1 = D^-1 r' / theta formed
+// from r); 1: second step (x_{k-1} = x_1, recomputed from r'); 2: later steps
+// (x_{k-1} read from its buffer, which x_{k+1} then overwrites in place: each
+// thread reads and writes only its own DoFs there).
+template <int KIND, bool LAST>
 struct ChebIO {
   ChebStepArgs a;
   double mu, muz_prev;
@@ -20,9 +24,8 @@ struct ChebIO {
     muz_prev = a.st[kMuZ];
     acc[0] = acc[1] = acc[2] = 0.0;
   }
-  // operand x: FIRST forms x1 = D^-1 r' / theta from r
   __device__ __forceinline__ float load(size_t i, int loc) const {
-    if constexpr (FIRST) {
+    if constexpr (KIND == 0) {
       const float rf = (float)(a.r[i] - mu);
       return a.dinv[loc] * rf * a.inv_theta;
     } else {
@@ -32,19 +35,18 @@ struct ChebIO {
   __device__ __forceinline__ void store(size_t i, int loc, float x, float t) {
     double rp = 0.0;
     float rf;
-    if constexpr (FIRST || LAST) {
+    if constexpr (KIND == 0 || LAST) {
       rp = a.r[i] - mu;
       rf = (float)rp;
     } else {
       rf = a.r32[i];
     }
-    if constexpr (FIRST && !LAST) a.r32[i] = rf;
-    float dold;
-    if constexpr (FIRST) dold = x;
-    else dold = a.d[i];
-    const float dn = a.c1 * dold + a.c2 * a.dinv[loc] * (rf - t);
-    if constexpr (!LAST) a.d[i] = dn;
-    const float xn = x + dn;
+    if constexpr (KIND == 0 && !LAST) a.r32[i] = rf;
+    const float di = a.dinv[loc];
+    float xm1 = 0.0f;
+    if constexpr (KIND == 1) xm1 = di * rf * a.inv_theta;
+    if constexpr (KIND == 2) xm1 = a.xprev[i];
+    const float xn = x + (a.c1 * (x - xm1) + a.c2 * di * (rf - t));
     a.xout[i] = xn;
     if constexpr (LAST) {
       const double z = (double)xn;
@@ -59,34 +61,35 @@ struct ChebIO {
   }
 };
 
-template <int N, bool FIRST, bool LAST>
+template <int N, int KIND, bool LAST>
 hipError_t step_n(const LaplacePlan& P, const ChebStepArgs& a, hipStream_t s) {
-  ChebIO<FIRST, LAST> io{};
+  ChebIO<KIND, LAST> io{};
   io.a = a;
   return launch_laplace_io<N, float>(P, io, nullptr, s);
 }
 
 template <int N>
-hipError_t step_fl(const LaplacePlan& P, bool first, bool last, const ChebStepArgs& a, hipStream_t s) {
-  if (first) return last ? step_n<N, true, true>(P, a, s) : step_n<N, true, false>(P, a, s);
-  return last ? step_n<N, false, true>(P, a, s) : step_n<N, false, false>(P, a, s);
+hipError_t step_fl(const LaplacePlan& P, int step, bool last, const ChebStepArgs& a, hipStream_t s) {
+  if (step == 1) return last ? step_n<N, 0, true>(P, a, s) : step_n<N, 0, false>(P, a, s);
+  if (step == 2) return last ? step_n<N, 1, true>(P, a, s) : step_n<N, 1, false>(P, a, s);
+  return last ? step_n<N, 2, true>(P, a, s) : step_n<N, 2, false>(P, a, s);
 }
 
 }  // namespace
 
-hipError_t cg_apply_cheb(const LaplacePlan& P, bool first, bool last, const ChebStepArgs& a, hipStream_t s) {
+hipError_t cg_apply_cheb(const LaplacePlan& P, int step, bool last, const ChebStepArgs& a, hipStream_t s) {
   switch (P.k) {
-    case 1: return step_fl<2>(P, first, last, a, s);
-    case 2: return step_fl<3>(P, first, last, a, s);
-    case 3: return step_fl<4>(P, first, last, a, s);
-    case 4: return step_fl<5>(P, first, last, a, s);
-    case 5: return step_fl<6>(P, first, last, a, s);
-    case 6: return step_fl<7>(P, first, last, a, s);
-    case 7: return step_fl<8>(P, first, last, a, s);
-    case 8: return step_fl<9>(P, first, last, a, s);
-    case 9: return step_fl<10>(P, first, last, a, s);
-    case 10: return step_fl<11>(P, first, last, a, s);
-    case 11: return step_fl<12>(P, first, last, a, s);
+    case 1: return step_fl<2>(P, step, last, a, s);
+    case 2: return step_fl<3>(P, step, last, a, s);
+    case 3: return step_fl<4>(P, step, last, a, s);
+    case 4: return step_fl<5>(P, step, last, a, s);
+    case 5: return step_fl<6>(P, step, last, a, s);
+    case 6: return step_fl<7>(P, step, last, a, s);
+    case 7: return step_fl<8>(P, step, last, a, s);
+    case 8: return step_fl<9>(P, step, last, a, s);
+    case 9: return step_fl<10>(P, step, last, a, s);
+    case 10: return step_fl<11>(P, step, last, a, s);
+    case 11: return step_fl<12>(P, step, last, a, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -65,6 +65,28 @@
 namespace dgmf {
 
 
+// Even-odd form of the 1D operators (used for n >= 6).  M and L = M^-1 K are
+// centro-symmetric (A[n-1-i][n-1-j] = A[i][j]: the LGL nodes are symmetric
+// and the SIPG form is invariant under x -> 1-x), and the neighbour couplings
+// are mirror images (left = reflected right for the end values, negated for
+// the half slopes).  With e_j = u_j + u_{n-1-j}, o_j = u_j - u_{n-1-j}
+// (j < h = n/2) and, for odd n, the middle value u_h:
+//   y_i = E_i + O_i,  y_{n-1-i} = E_i - O_i  (i < h),
+//   E_i = sum_j Ep[i][j] e_j + Em[i] u_h,  O_i = sum_j Op[i][j] o_j,
+//   y_h = sum_j Mr[j] e_j + Mc u_h,
+// Ep = (A[i][j] + A[i][n-1-j]) / 2, Op = (A[i][j] - A[i][n-1-j]) / 2,
+// Em[i] = A[i][h], Mr[j] = A[h][j], Mc = A[h][h]; the couplings enter E with
+// (vR + vL), (gR - gL) and O with (vR - vL), (gR + gL).  Half the
+// multiply-adds of the plain matrix-vector products.
+template <int N, typename T>
+struct LapEO {
+  static constexpr int H = N / 2, HM = H > 0 ? H : 1;
+  T MEp[HM][HM], MOp[HM][HM], MEm[HM], MMr[HM], MMc;          // mass
+  T LEp[3][HM][HM], LOp[3][HM][HM], LEm[3][HM], LMr[3][HM], LMc[3];
+  T cvE[3][HM], cgE[3][HM], cvO[3][HM], cgO[3][HM];            // couplings
+  T cvM[3], cgM[3];                                            // middle node
+};
+
 template <int N, typename T>
 struct LapTab {
   T M[N][N];      // 1D mass matrix on [0,1]
@@ -75,7 +97,11 @@ struct LapTab {
   T eL[3][N];     // c_d M^-1 (coefficient of the left neighbour's half slope)
   T hd0[N];       // 1/2 l_b'(0)
   T hd1[N];       // 1/2 l_b'(1)
+  LapEO<N, T> eo;
 };
+
+// Sweeps in even-odd form from this n on (below it saves nothing).
+constexpr int kLapEvenOddFrom = 6;
 
 // LDS layout of one element's n^3 block: node (a,b,c) at a + PX*b + PY*c,
 // elements ES apart.  The paddings (per n) keep the three pencil access
@@ -179,6 +205,40 @@ __device__ __forceinline__ NbrFace<T> nbr_face(const Tab& t, const T* uL, const 
 // to the neighbours' end values and half slopes).
 template <int N, typename T, bool ACC, typename Tab>
 __device__ __forceinline__ void l_pencil(const Tab& t, int d, const T* u, const NbrFace<T>& f, T* y) {
+  if constexpr (N >= kLapEvenOddFrom) {
+    constexpr int H = N / 2;
+    const auto& q = t.eo;
+    T e[H], o[H];
+#pragma unroll
+    for (int j = 0; j < H; ++j) {
+      e[j] = u[j] + u[N - 1 - j];
+      o[j] = u[j] - u[N - 1 - j];
+    }
+    const T sv = f.vR + f.vL, dv = f.vR - f.vL, sg = f.gR - f.gL, dg = f.gR + f.gL;
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+      T E = q.cvE[d][i] * sv;
+      E = fmadd(q.cgE[d][i], sg, E);
+#pragma unroll
+      for (int j = 0; j < H; ++j) E = fmadd(q.LEp[d][i][j], e[j], E);
+      if constexpr (N % 2) E = fmadd(q.LEm[d][i], u[H], E);
+      T O = q.cvO[d][i] * dv;
+      O = fmadd(q.cgO[d][i], dg, O);
+#pragma unroll
+      for (int j = 0; j < H; ++j) O = fmadd(q.LOp[d][i][j], o[j], O);
+      y[i] = ACC ? y[i] + (E + O) : E + O;
+      y[N - 1 - i] = ACC ? y[N - 1 - i] + (E - O) : E - O;
+    }
+    if constexpr (N % 2) {
+      T m = q.cvM[d] * sv;
+      m = fmadd(q.cgM[d], sg, m);
+      m = fmadd(q.LMc[d], u[H], m);
+#pragma unroll
+      for (int j = 0; j < H; ++j) m = fmadd(q.LMr[d][j], e[j], m);
+      y[H] = ACC ? y[H] + m : m;
+    }
+    return;
+  }
 #pragma unroll
   for (int i = 0; i < N; ++i) {
     T s = ACC ? fmadd(t.L[d][i][0], u[0], y[i]) : t.L[d][i][0] * u[0];
@@ -189,6 +249,41 @@ __device__ __forceinline__ void l_pencil(const Tab& t, int d, const T* u, const 
     s = fmadd(t.eR[d][i], f.gR, s);
     s = fmadd(t.eL[d][i], f.gL, s);
     y[i] = s;
+  }
+}
+
+// y = M x along one pencil (even-odd from kLapEvenOddFrom on)
+template <int N, typename T, typename Tab>
+__device__ __forceinline__ void mass_pencil(const Tab& t, const T* x, T* y) {
+  if constexpr (N >= kLapEvenOddFrom) {
+    constexpr int H = N / 2;
+    const auto& q = t.eo;
+    T e[H], o[H];
+#pragma unroll
+    for (int j = 0; j < H; ++j) {
+      e[j] = x[j] + x[N - 1 - j];
+      o[j] = x[j] - x[N - 1 - j];
+    }
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+      T E = q.MEp[i][0] * e[0];
+#pragma unroll
+      for (int j = 1; j < H; ++j) E = fmadd(q.MEp[i][j], e[j], E);
+      if constexpr (N % 2) E = fmadd(q.MEm[i], x[H], E);
+      T O = q.MOp[i][0] * o[0];
+#pragma unroll
+      for (int j = 1; j < H; ++j) O = fmadd(q.MOp[i][j], o[j], O);
+      y[i] = E + O;
+      y[N - 1 - i] = E - O;
+    }
+    if constexpr (N % 2) {
+      T m = q.MMc * x[H];
+#pragma unroll
+      for (int j = 0; j < H; ++j) m = fmadd(q.MMr[j], e[j], m);
+      y[H] = m;
+    }
+  } else {
+    matvec<N, T>(t.M, x, y);
   }
 }
 
@@ -317,7 +412,7 @@ __device__ __forceinline__ void laplace_batch(const LapTab<N, T>& t, const Batch
       v[a] = Ve[base + a];
     }
     l_pencil<N, T, true>(t, 0, in, I.fx, v);
-    matvec<N, T>(t.M, v, out);
+    mass_pencil<N, T>(t, v, out);
 #pragma unroll
     for (int a = 0; a < N; ++a) Ve[base + a] = out[a];
   }
@@ -327,7 +422,7 @@ __device__ __forceinline__ void laplace_batch(const LapTab<N, T>& t, const Batch
     const int base = p0 + PY * p1;
 #pragma unroll
     for (int j = 0; j < N; ++j) v[j] = Ve[base + PX * j];
-    matvec<N, T>(t.M, v, out);
+    mass_pencil<N, T>(t, v, out);
 #pragma unroll
     for (int j = 0; j < N; ++j) Ve[base + PX * j] = out[j];
   }
@@ -337,7 +432,7 @@ __device__ __forceinline__ void laplace_batch(const LapTab<N, T>& t, const Batch
     const int base = p0 + PX * p1;
 #pragma unroll
     for (int c = 0; c < N; ++c) v[c] = Ve[base + PY * c];
-    matvec<N, T>(t.M, v, out);
+    mass_pencil<N, T>(t, v, out);
     const size_t g = (size_t)b.eg * N3 + p0 + N * p1;
 #pragma unroll
     for (int c = 0; c < N; ++c) io.store(g + N2 * c, p0 + N * p1 + N2 * c, Ue[base + PY * c], out[c]);
@@ -574,7 +669,7 @@ laplace_march_kernel(IO io, MeshArgs mesh, LapWork wk, const LapTab<N, T>* __res
         v[a] = Ve[base + a];
       }
       l_pencil<N, T, true>(t, 0, in, fx, v);
-      matvec<N, T>(t.M, v, out);
+      mass_pencil<N, T>(t, v, out);
 #pragma unroll
       for (int a = 0; a < N; ++a) Ve[base + a] = out[a];
     }
@@ -586,7 +681,7 @@ laplace_march_kernel(IO io, MeshArgs mesh, LapWork wk, const LapTab<N, T>* __res
       T out[N];
 #pragma unroll
       for (int j = 0; j < N; ++j) v[j] = Ve[base + PX * j];
-      matvec<N, T>(t.M, v, out);
+      mass_pencil<N, T>(t, v, out);
 #pragma unroll
       for (int j = 0; j < N; ++j) Ve[base + PX * j] = out[j];
     }
@@ -599,7 +694,7 @@ laplace_march_kernel(IO io, MeshArgs mesh, LapWork wk, const LapTab<N, T>* __res
       T out[N];
 #pragma unroll
       for (int c = 0; c < N; ++c) v[c] = Ve[base + PY * c];
-      matvec<N, T>(t.M, v, out);
+      mass_pencil<N, T>(t, v, out);
       const size_t g = col_off(ez);
 #pragma unroll
       for (int c = 0; c < N; ++c) io.store(g + N2 * c, lz + N2 * c, cur[c], out[c]);
@@ -664,6 +759,38 @@ LapTab<N, T> make_lap_tab(const LaplacePlan& P) {
     }
     t.hd0[i] = (T)(0.5 * P.D[i]);
     t.hd1[i] = (T)(0.5 * P.D[(N - 1) * N + i]);
+  }
+  // even-odd form, from the symmetrised double-precision matrices
+  constexpr int H = N / 2;
+  auto fill = [&](auto A, auto& Ep, auto& Op, auto& Em, auto& Mr, auto& Mc) {
+    // A(i, j) in double; centro-symmetric average first
+    auto S = [&](int i, int j) { return 0.5 * (A(i, j) + A(N - 1 - i, N - 1 - j)); };
+    for (int i = 0; i < H; ++i) {
+      for (int j = 0; j < H; ++j) {
+        Ep[i][j] = (T)(0.5 * (S(i, j) + S(i, N - 1 - j)));
+        Op[i][j] = (T)(0.5 * (S(i, j) - S(i, N - 1 - j)));
+      }
+      Em[i] = (T)(N % 2 ? S(i, H) : 0.0);
+      Mr[i] = (T)(N % 2 ? S(H, i) : 0.0);
+    }
+    Mc = (T)(N % 2 ? S(H, H) : 0.0);
+  };
+  fill([&](int i, int j) { return P.Mref[i * N + j]; }, t.eo.MEp, t.eo.MOp, t.eo.MEm, t.eo.MMr, t.eo.MMc);
+  for (int d = 0; d < 3; ++d) {
+    fill([&](int i, int j) { return P.c[d] * P.Lown[i * N + j]; }, t.eo.LEp[d], t.eo.LOp[d], t.eo.LEm[d],
+         t.eo.LMr[d], t.eo.LMc[d]);
+    // mirrored couplings: aL[i] = aR[n-1-i], eL[i] = -eR[n-1-i] (averaged)
+    auto aR = [&](int i) { return 0.5 * P.c[d] * (P.cR[i] + P.cL[N - 1 - i]); };
+    auto eR = [&](int i) { return 0.5 * P.c[d] * (P.gR[i] - P.gL[N - 1 - i]); };
+    for (int i = 0; i < H; ++i) {
+      const double aRi = aR(i), aLi = aR(N - 1 - i), eRi = eR(i), eLi = -eR(N - 1 - i);
+      t.eo.cvE[d][i] = (T)(0.5 * (aRi + aLi));
+      t.eo.cgE[d][i] = (T)(0.5 * (eRi - eLi));
+      t.eo.cvO[d][i] = (T)(0.5 * (aRi - aLi));
+      t.eo.cgO[d][i] = (T)(0.5 * (eRi + eLi));
+    }
+    t.eo.cvM[d] = (T)(N % 2 ? aR(H) : 0.0);
+    t.eo.cgM[d] = (T)(N % 2 ? eR(H) : 0.0);
   }
   return t;
 }
