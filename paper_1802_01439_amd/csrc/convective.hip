@@ -89,7 +89,10 @@ struct ConvShape {
   // one workgroup fills a CU's LDS (the highest degrees, FP64 k=6) 512
   // threads hide more latency (FP64 k=6: 10 % faster than 320); below that
   // a larger group only lowers the register limit
-  static constexpr int TH0 = (E * Q * Q > 256) ? ((E * Q * Q + 63) / 64) * 64 : 256;
+  // FP64 k=7 (121 z pencils, 256 VGPRs either way) measured 5 % faster with
+  // two wavefronts than with four; elsewhere fewer threads than 256 cost
+  // occupancy (the freed register budget gets used)
+  static constexpr int TH0 = (N == 8 && SZ == 8) ? 128 : (E * Q * Q > 256) ? ((E * Q * Q + 63) / 64) * 64 : 256;
   static constexpr int TH = ((E == 1 && Q >= 16) || E * BYTES > 80 * 1024) ? (TH0 > 512 ? TH0 : 512) : TH0;
   // minimum wavefronts per SIMD (register cap) where registers, not LDS,
   // limited the groups per CU: at 128 VGPRs FP32 k=11 fits two 512-thread
