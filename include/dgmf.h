@@ -147,9 +147,11 @@ typedef struct {
 
 /*
  * Solve A x = b with the SIPG form of dg_apply_laplace (n_comp must be 1) by
- * flexible preconditioned CG (Sec. 3.3) in double precision: residuals, dot
- * products and the updates of x, r and p stay in double on the GPU; with
- * DG_PC_CHEB_F32 the preconditioner runs single-precision operator applies.
+ * preconditioned CG (Sec. 3.3) in double precision: residuals, dot products
+ * and the updates of x, r and p stay in double on the GPU.  DG_PC_JACOBI_F64
+ * uses the standard beta; with DG_PC_CHEB_F32 the preconditioner runs
+ * single-precision operator applies and beta is the flexible
+ * (Polak-Ribiere) one, r+.(z+ - z)/(r.z).
  *   b: [N_el][n^3] double (device); x: [N_el][n^3] double (device), initial
  *   guess in, solution out; report: host pointer, may be NULL.
  * Returns DG_OK, DG_NOT_CONVERGED or DG_ERR_BREAKDOWN (x holds the last
