@@ -118,6 +118,20 @@ int dg_vjp_convective(const dg_op_desc* desc, dg_dtype dtype, const void* u, con
 int dg_apply_divergence(const dg_op_desc* desc, dg_dtype dtype, const void* u, void* b,
                         void* hip_stream);
 
+/*
+ * Inverse mass matrix of the DG space (Sec. 3.3: block-diagonal, one dense
+ * block per element, inverted element by element by sum factorisation; used
+ * there for the convective step and as the preconditioner of the projection
+ * and Helmholtz equations): dst = M^-1 src with M_ij = (phi_i, phi_j), Gauss
+ * quadrature with k+1 points per direction (exact).  n_comp (1 or 3) blocks
+ * per element, layout as dg_apply_laplace.
+ *   src, dst: [n_comp][N_el][n^3] of `dtype`.  dst may equal src (in place);
+ *   any other overlap returns DG_ERR_ALIAS.  n_q < k+1 returns
+ *   DG_ERR_UNSUPPORTED (the under-integrated mass matrix is singular).
+ */
+int dg_apply_inverse_mass(const dg_op_desc* desc, dg_dtype dtype, const void* src, void* dst,
+                          void* hip_stream);
+
 enum { DG_PC_JACOBI_F64 = 0, DG_PC_CHEB_F32 = 1 };
 
 typedef struct {

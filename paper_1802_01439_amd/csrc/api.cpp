@@ -371,5 +371,29 @@ int dg_apply_divergence(const dg_op_desc* desc, dg_dtype dtype, const void* u, v
   return ok();
 }
 
+int dg_apply_inverse_mass(const dg_op_desc* desc, dg_dtype dtype, const void* src, void* dst,
+                          void* hip_stream) {
+  int rc = validate_desc(desc);
+  if (rc) return rc;
+  if (dtype != DG_F64 && dtype != DG_F32) return fail(DG_ERR_INVALID_ARG, "dtype must be DG_F64 or DG_F32");
+  if (desc->n_comp != 1 && desc->n_comp != 3) return fail(DG_ERR_INVALID_ARG, "n_comp must be 1 or 3");
+  if (!src || !dst) return fail(DG_ERR_INVALID_ARG, "src/dst is NULL");
+  if (desc->n_q != 0 && desc->n_q < desc->degree + 1)
+    return fail(DG_ERR_UNSUPPORTED, "the inverse mass needs n_q >= k+1 (exact Gauss integration)");
+  const long long nblocks = (long long)desc->n_comp * num_elements(desc);
+  const size_t bytes = (size_t)nblocks * dofs_per_element(desc) * (dtype == DG_F64 ? 8 : 4);
+  if (src != dst && overlaps(src, bytes, dst, bytes)) return fail(DG_ERR_ALIAS, "dst overlaps src (not in place)");
+  const int k = desc->degree, n = k + 1;
+  const Basis1D& B = basis(k, n);
+  std::vector<double> I(n * n, 0.0);
+  for (int i = 0; i < n; ++i) I[i * n + i] = 1.0;
+  const std::vector<double> Minv = solve_spd(B.Mref, n, I, n);
+  double vol = 1.0;
+  for (int d = 0; d < 3; ++d) vol *= desc->length[d] / desc->n_el[d];
+  hipError_t e = launch_inverse_mass(k, Minv, 1.0 / vol, nblocks, dtype == DG_F32, src, dst,
+                                     (hipStream_t)hip_stream);
+  if (e != hipSuccess) return hip_fail(e, "inverse mass kernel launch");
+  return ok();
+}
 
 }  // extern "C"

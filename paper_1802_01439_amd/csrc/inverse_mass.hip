@@ -1,0 +1,147 @@
+// Inverse mass matrix of the DG space (Sec. 3.3: block-diagonal, inverted
+// element by element by sum factorisation), FP64 and FP32, degrees 1..11.
+//
+// On an affine Cartesian cell with the LGL nodal basis and k+1 Gauss points
+// per direction (exact), the element mass matrix is h_x h_y h_z M1(x)M1(x)M1
+// with M1 the 1D mass on [0,1], so
+//   M_e^-1 = (1 / (h_x h_y h_z)) M1^-1 (x) M1^-1 (x) M1^-1,
+// three dense 1D sweeps with the host-computed M1^-1.  Element-local: no
+// neighbour data, input read once and output written once (memory bound,
+// Sec. 4.4).
+//
+// Mapping: one workgroup per batch of E = floor(256/n^2) consecutive element
+// blocks (components are further blocks of the component-major layout);
+// n^2 threads per element.  Each thread loads its z column (consecutive
+// threads read consecutive addresses), sweeps it in registers, and the y and
+// x sweeps run on LDS pencils in place; each thread then stores its z column
+// from LDS.  3 barriers.  Because every block is read completely before any
+// of it is written, src == dst (in place) is allowed.
+#include "api_internal.h"
+#include "common.h"
+#include "laplace_kernels.h"
+#include "ops.h"
+
+namespace dgmf {
+
+namespace {
+
+template <int N, typename T>
+struct InvMassTab {
+  T A[N][N];   // M1^-1 (times 1/(h_x h_y h_z) in the x sweep)
+  T scale;     // 1 / (h_x h_y h_z)
+};
+
+template <int N, typename T, typename Mat>
+__device__ __forceinline__ void mv(const Mat& A, const T* x, T* y) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    T s = A[i][0] * x[0];
+#pragma unroll
+    for (int j = 1; j < N; ++j) s = fmadd(A[i][j], x[j], s);
+    y[i] = s;
+  }
+}
+
+template <int N, typename T>
+__global__ void __launch_bounds__(LapCfgB<N>::THREADS)
+inverse_mass_kernel(const T* src, T* dst, long long nblocks, const InvMassTab<N, T>* __restrict__ tab) {
+  using C = LapCfgB<N>;
+  constexpr int N2 = N * N, N3 = N * N * N, E = C::E, ES = C::ES, PX = C::PX, PY = C::PY;
+  __shared__ T U[E * ES];
+  const int tid = threadIdx.x;
+  const int le = tid / N2, p = tid - le * N2;
+  const int p0 = p % N, p1 = p / N;
+  const long long blk = (long long)blockIdx.x * E + le;
+  const bool active = blk < nblocks;
+  T* Ue = U + le * ES;
+  T x[N], y[N];
+  // z: own column in registers
+  if (active) {
+    const auto& t = *fresh(tab);
+    const T* g = src + blk * N3 + p0 + N * p1;
+#pragma unroll
+    for (int c = 0; c < N; ++c) x[c] = g[N2 * c];
+    mv<N, T>(t.A, x, y);
+    const int base = p0 + PX * p1;
+#pragma unroll
+    for (int c = 0; c < N; ++c) Ue[base + PY * c] = y[c];
+  }
+  __syncthreads();
+  // y: pencil (a, c) = (p0, p1), in place
+  if (active) {
+    const auto& t = *fresh(tab);
+    const int base = p0 + PY * p1;
+#pragma unroll
+    for (int b = 0; b < N; ++b) x[b] = Ue[base + PX * b];
+    mv<N, T>(t.A, x, y);
+#pragma unroll
+    for (int b = 0; b < N; ++b) Ue[base + PX * b] = y[b];
+  }
+  __syncthreads();
+  // x: pencil (b, c) = (p0, p1), in place, with the cell scaling
+  if (active) {
+    const auto& t = *fresh(tab);
+    const int base = PX * p0 + PY * p1;
+#pragma unroll
+    for (int a = 0; a < N; ++a) x[a] = Ue[base + a];
+    mv<N, T>(t.A, x, y);
+#pragma unroll
+    for (int a = 0; a < N; ++a) Ue[base + a] = t.scale * y[a];
+  }
+  __syncthreads();
+  // store the z column
+  if (active) {
+    T* g = dst + blk * N3 + p0 + N * p1;
+    const int base = p0 + PX * p1;
+#pragma unroll
+    for (int c = 0; c < N; ++c) g[N2 * c] = Ue[base + PY * c];
+  }
+}
+
+template <int N, typename T>
+hipError_t launch_n(const std::vector<double>& Minv, double scale, long long nblocks, const void* src, void* dst,
+                    hipStream_t s) {
+  InvMassTab<N, T> t;
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j) t.A[i][j] = (T)Minv[i * N + j];
+  t.scale = (T)scale;
+  hipError_t err;
+  const InvMassTab<N, T>* dt = device_table_of("inverse_mass", t, &err);
+  if (!dt) return err;
+  using C = LapCfgB<N>;
+  const long long grid = (nblocks + C::E - 1) / C::E;
+  if (grid > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+  if (grid == 0) return hipSuccess;
+  hipLaunchKernelGGL((inverse_mass_kernel<N, T>), dim3((unsigned)grid), dim3(C::THREADS), 0, s, (const T*)src,
+                     (T*)dst, nblocks, dt);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_t(int k, const std::vector<double>& Minv, double scale, long long nblocks, const void* src,
+                    void* dst, hipStream_t s) {
+  switch (k) {
+    case 1: return launch_n<2, T>(Minv, scale, nblocks, src, dst, s);
+    case 2: return launch_n<3, T>(Minv, scale, nblocks, src, dst, s);
+    case 3: return launch_n<4, T>(Minv, scale, nblocks, src, dst, s);
+    case 4: return launch_n<5, T>(Minv, scale, nblocks, src, dst, s);
+    case 5: return launch_n<6, T>(Minv, scale, nblocks, src, dst, s);
+    case 6: return launch_n<7, T>(Minv, scale, nblocks, src, dst, s);
+    case 7: return launch_n<8, T>(Minv, scale, nblocks, src, dst, s);
+    case 8: return launch_n<9, T>(Minv, scale, nblocks, src, dst, s);
+    case 9: return launch_n<10, T>(Minv, scale, nblocks, src, dst, s);
+    case 10: return launch_n<11, T>(Minv, scale, nblocks, src, dst, s);
+    case 11: return launch_n<12, T>(Minv, scale, nblocks, src, dst, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_inverse_mass(int k, const std::vector<double>& Minv, double scale, long long nblocks, bool f32,
+                               const void* src, void* dst, hipStream_t s) {
+  return f32 ? launch_t<float>(k, Minv, scale, nblocks, src, dst, s)
+             : launch_t<double>(k, Minv, scale, nblocks, src, dst, s);
+}
+
+}  // namespace dgmf

@@ -54,6 +54,11 @@ struct DivPlan {
 
 hipError_t launch_divergence(const DivPlan& P, bool f32, const void* u, void* b, hipStream_t s);
 
+// x = M^-1 b on nblocks consecutive element blocks: Minv = inverse of the 1D
+// mass on [0,1] (n x n row major), scale = 1/(h_x h_y h_z).
+hipError_t launch_inverse_mass(int k, const std::vector<double>& Minv, double scale, long long nblocks, bool f32,
+                               const void* src, void* dst, hipStream_t s);
+
 int vjp_max_degree(bool f32);
 
 }  // namespace dgmf
