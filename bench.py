@@ -300,6 +300,12 @@ def main():
     torch.cuda.set_device(dev)
     if args.extras_only:
         which = tuple(w for w in args.extras_only.split(",") if w)
+        if args.calib_copy:
+            a = torch.ones(args.calib_copy // 8, dtype=torch.float64, device=dev)
+            c = torch.empty_like(a)
+            c.copy_(a)
+            torch.cuda.synchronize()
+            del a, c
         print(json.dumps({"extras": extras(torch, dgmf, inputs, dev, args, which)}), flush=True)
         return
     print(f"[bench] building inputs for k={args.kmin}..{args.kmax} ops={args.ops}", file=sys.stderr, flush=True)
