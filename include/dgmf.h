@@ -110,6 +110,17 @@ int dg_vjp_convective(const dg_op_desc* desc, dg_dtype dtype, const void* u, con
                       void* grad_u, void* hip_stream);
 
 /*
+ * Helmholtz operator of the viscous step (Sec. 3.3: gamma_0/dt M + nu L,
+ * solved with the inverse mass as preconditioner): dst = mass_factor M src +
+ * scale L src, with L the SIPG form of dg_apply_laplace (desc->scale = nu,
+ * penalty, n_q as there) and M the mass matrix of the DG space
+ * (dg_apply_inverse_mass).  mass_factor must be finite and >= 0.
+ *   src, dst: [n_comp][N_el][n^3] of `dtype`, must not overlap.
+ */
+int dg_apply_helmholtz(const dg_op_desc* desc, dg_dtype dtype, double mass_factor, const void* src, void* dst,
+                       void* hip_stream);
+
+/*
  * Velocity divergence d_h with central flux (Sec. 3.2, weak form of d_h), the
  * right-hand side of the pressure Poisson step without its -gamma_0/dt factor:
  *   b_i = -(grad phi_i, u)_K + sum_faces (phi_i, 1/2 (u- + u+) . n)

@@ -35,3 +35,11 @@ def inverse_mass_apply(u, k, mesh, elems=None):
     ue = u if elems is None else u[..., np.asarray(elems), :]
     flat = ue.reshape(-1, ue.shape[-1])
     return np.linalg.solve(M, flat.T).T.reshape(ue.shape)
+
+
+def helmholtz_apply(u, k, mesh, mass_factor, scale=1.0, penalty_factor=1.0, n_q=0):
+    """mass_factor M u + scale L u: the operator of the viscous step (Sec. 3.3,
+    gamma_0/dt M + nu L), each term evaluated by its own oracle."""
+    from .laplace import laplace_apply
+    return mass_factor * mass_apply(u, k, mesh) + laplace_apply(u, k, mesh, n_q=n_q,
+                                                                penalty_factor=penalty_factor, scale=scale)

@@ -319,6 +319,29 @@ int dg_apply_laplace(const dg_op_desc* desc, dg_dtype dtype, const void* src, vo
   return ok();
 }
 
+int dg_apply_helmholtz(const dg_op_desc* desc, dg_dtype dtype, double mass_factor, const void* src, void* dst,
+                       void* hip_stream) {
+  int rc = validate_desc(desc);
+  if (rc) return rc;
+  if (dtype != DG_F64 && dtype != DG_F32) return fail(DG_ERR_INVALID_ARG, "dtype must be DG_F64 or DG_F32");
+  if (desc->n_comp != 1 && desc->n_comp != 3) return fail(DG_ERR_INVALID_ARG, "n_comp must be 1 or 3");
+  if (!src || !dst) return fail(DG_ERR_INVALID_ARG, "src/dst is NULL");
+  if (!(mass_factor >= 0.0) || !std::isfinite(mass_factor))
+    return fail(DG_ERR_INVALID_ARG, "mass_factor must be finite and >= 0");
+  if (desc->n_q != 0 && desc->n_q < desc->degree + 1)
+    return fail(DG_ERR_UNSUPPORTED, "the Helmholtz form needs n_q >= k+1 (exact Gauss integration)");
+  const size_t bytes = (size_t)desc->n_comp * num_elements(desc) * dofs_per_element(desc) *
+                       (dtype == DG_F64 ? 8 : 4);
+  if (overlaps(src, bytes, dst, bytes)) return fail(DG_ERR_ALIAS, "dst overlaps src");
+  LaplacePlan P = make_laplace_plan(desc, desc->n_comp);
+  double vol = 1.0;
+  for (int d = 0; d < 3; ++d) vol *= desc->length[d] / desc->n_el[d];
+  P.shift = mass_factor * vol;
+  hipError_t e = launch_laplace(P, dtype == DG_F32, src, dst, (hipStream_t)hip_stream);
+  if (e != hipSuccess) return hip_fail(e, "helmholtz kernel launch");
+  return ok();
+}
+
 int dg_apply_convective(const dg_op_desc* desc, dg_dtype dtype, const void* u, void* r,
                         void* hip_stream) {
   int rc = validate_desc(desc);

@@ -750,7 +750,8 @@ LapTab<N, T> make_lap_tab(const LaplacePlan& P) {
   for (int i = 0; i < N; ++i) {
     for (int j = 0; j < N; ++j) {
       t.M[i][j] = (T)P.Mref[i * N + j];
-      for (int d = 0; d < 3; ++d) t.L[d][i][j] = (T)(P.c[d] * P.Lown[i * N + j]);
+      for (int d = 0; d < 3; ++d)
+        t.L[d][i][j] = (T)(P.c[d] * P.Lown[i * N + j] + (d == 2 && i == j ? P.shift : 0.0));
     }
     for (int d = 0; d < 3; ++d) {
       t.aR[d][i] = (T)(P.c[d] * P.cR[i]);
@@ -778,8 +779,9 @@ LapTab<N, T> make_lap_tab(const LaplacePlan& P) {
   };
   fill([&](int i, int j) { return P.Mref[i * N + j]; }, t.eo.MEp, t.eo.MOp, t.eo.MEm, t.eo.MMr, t.eo.MMc);
   for (int d = 0; d < 3; ++d) {
-    fill([&](int i, int j) { return P.c[d] * P.Lown[i * N + j]; }, t.eo.LEp[d], t.eo.LOp[d], t.eo.LEm[d],
-         t.eo.LMr[d], t.eo.LMc[d]);
+    // the mass term of a Helmholtz operator is a diagonal shift of the z matrix
+    fill([&](int i, int j) { return P.c[d] * P.Lown[i * N + j] + (d == 2 && i == j ? P.shift : 0.0); },
+         t.eo.LEp[d], t.eo.LOp[d], t.eo.LEm[d], t.eo.LMr[d], t.eo.LMc[d]);
     // mirrored couplings: aL[i] = aR[n-1-i], eL[i] = -eR[n-1-i] (averaged)
     auto aR = [&](int i) { return 0.5 * P.c[d] * (P.cR[i] + P.cL[N - 1 - i]); };
     auto eR = [&](int i) { return 0.5 * P.c[d] * (P.gR[i] - P.gL[N - 1 - i]); };

@@ -21,6 +21,7 @@ struct LaplacePlan {
   std::vector<double> cR, cL, gR, gL;  // M^-1 times the neighbour coupling columns
   double c[3] = {0, 0, 0};   // scale * vol / h_d^2
   double sigma = 0;          // penalty_factor * (k+1)^2
+  double shift = 0;          // y = (Mx(x)My(x)Mz)(shift I + sum_d c_d L_d) u: mass_factor * vol
 };
 
 hipError_t launch_laplace(const LaplacePlan& P, bool f32, const void* src, void* dst,

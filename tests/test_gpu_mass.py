@@ -77,3 +77,37 @@ def test_unsupported_and_alias():
     with pytest.raises(dgmf.DgError) as ei:
         dgmf.apply_inverse_mass(d, big[:64], out=big[1:])
     assert ei.value.code == dgmf.DG_ERR_ALIAS
+
+
+@pytest.mark.parametrize("k,dtype,ncomp", [(2, torch.float64, 1), (4, torch.float64, 3), (7, torch.float64, 1),
+                                           (11, torch.float64, 1), (3, torch.float32, 1), (8, torch.float32, 3)])
+def test_helmholtz_parity(k, dtype, ncomp):
+    from oracle.mass import helmholtz_apply
+    E = max(1, 256 // (k + 1) ** 2)
+    n_el = (2 * E + 3, 2, 2) if 2 * E + 3 < 30 else (2 * E + 3, 1, 2)
+    length = (0.9 * n_el[0], 1.1 * n_el[1], 1.0 * n_el[2])
+    msh = M.Mesh(n_el, length)
+    shape = (msh.N, (k + 1) ** 3) if ncomp == 1 else (3, msh.N, (k + 1) ** 3)
+    u = inputs.uniform(shape, seed=740 + k)
+    if dtype == torch.float32:
+        u = round_f32(u)
+    mass_factor, nu = 37.5, 0.02          # gamma_0 / dt and nu of a viscous step
+    announce(f"helmholtz k={k} {dtype} ncomp={ncomp}")
+    d = dgmf.make_desc(k, n_el, length, scale=nu, n_comp=ncomp)
+    y = dgmf.apply_helmholtz(d, to_dev(u, dtype), mass_factor).double().cpu().numpy()
+    ref = helmholtz_apply(u, k, msh, mass_factor, scale=nu)
+    assert rel_err(y, ref) < (1e-12 if dtype == torch.float64 else 1e-5)
+
+
+def test_helmholtz_without_mass_is_the_laplace_and_bad_factor():
+    k, n_el = 3, (5, 4, 3)
+    d = dgmf.make_desc(k, n_el, scale=0.5)
+    u = to_dev(inputs.uniform((60, 64), seed=9))
+    announce("helmholtz mass_factor 0")
+    a = dgmf.apply_helmholtz(d, u, 0.0)
+    b = dgmf.apply_laplace(d, u)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    with pytest.raises(dgmf.DgError) as ei:
+        dgmf.apply_helmholtz(d, u, -1.0)
+    assert ei.value.code == dgmf.DG_ERR_INVALID_ARG
