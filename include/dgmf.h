@@ -4,8 +4,8 @@
  * Operators of the discontinuous Galerkin discretisation of Sec. 3.2 on
  * periodic Cartesian hexahedral meshes with tensor-product Lagrange bases on
  * Legendre-Gauss-Lobatto (LGL) nodes of degree k and Gauss quadrature, and
- * the preconditioned CG solver of Sec. 3.3.  All compute runs in HIP kernels
- * for gfx950.
+ * the preconditioned CG solver, the inverse mass matrix and the Helmholtz
+ * operator of Sec. 3.3.  All compute runs in HIP kernels for gfx950.
  *
  * Mesh and layout (every entry point)
  *   - elements per direction n_el[d], box edge length[d]; element size
@@ -21,11 +21,13 @@
  *   - every array pointer is a caller-owned DEVICE pointer, except where a
  *     parameter says "host".  The library owns only its own small caches
  *     (1D tables, solver work vectors).
- *   - apply / vjp / divergence calls are asynchronous on `hip_stream`
+ *   - apply / vjp / divergence / inverse mass / Helmholtz calls are
+ *     asynchronous on `hip_stream`
  *     (a hipStream_t; NULL = the default stream).  dg_cg_solve blocks until
  *     it returns.
  *   - outputs are overwritten, never accumulated.  Inputs and outputs must
- *     not overlap (DG_ERR_ALIAS).
+ *     not overlap (DG_ERR_ALIAS); dg_apply_inverse_mass alone also accepts
+ *     dst == src (in place).
  *
  * Errors
  *   - 0 = DG_OK.  Negative codes are hard errors: nothing was launched and
