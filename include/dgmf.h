@@ -123,6 +123,21 @@ int dg_apply_helmholtz(const dg_op_desc* desc, dg_dtype dtype, double mass_facto
                        void* hip_stream);
 
 /*
+ * Operator of the projection step (Sec. 3.3, (M + A_D + A_C) u, with the
+ * divergence and continuity penalty terms of Sec. 3.2):
+ *   y = (v, u)_K + (div v, tau_D div u)_K + sum_faces (v . n, {tau_C} [[u]] . n)
+ * with [[u]] = u^- - u^+, {tau_C} the mean of the two elements' values and n
+ * the own element's outward normal; k+1 Gauss points per direction (n_q must
+ * be 0 or k+1, else DG_ERR_UNSUPPORTED); desc->n_comp must be 3.
+ *   u, y: [3][N_el][n^3] of `dtype`; tau_d, tau_c: [N_el] of `dtype`, the
+ *   element values of the two penalty parameters (the paper builds them from
+ *   the extrapolated velocity, h/(k+1) and the time step).  y must not
+ *   overlap u, tau_d or tau_c.
+ */
+int dg_apply_projection(const dg_op_desc* desc, dg_dtype dtype, const void* u, const void* tau_d,
+                        const void* tau_c, void* y, void* hip_stream);
+
+/*
  * Velocity divergence d_h with central flux (Sec. 3.2, weak form of d_h), the
  * right-hand side of the pressure Poisson step without its -gamma_0/dt factor:
  *   b_i = -(grad phi_i, u)_K + sum_faces (phi_i, 1/2 (u- + u+) . n)

@@ -342,6 +342,44 @@ int dg_apply_helmholtz(const dg_op_desc* desc, dg_dtype dtype, double mass_facto
   return ok();
 }
 
+int dg_apply_projection(const dg_op_desc* desc, dg_dtype dtype, const void* u, const void* tau_d,
+                        const void* tau_c, void* y, void* hip_stream) {
+  int rc = validate_desc(desc);
+  if (rc) return rc;
+  if (dtype != DG_F64 && dtype != DG_F32) return fail(DG_ERR_INVALID_ARG, "dtype must be DG_F64 or DG_F32");
+  if (desc->n_comp != 3) return fail(DG_ERR_INVALID_ARG, "the projection operator needs n_comp = 3");
+  if (!u || !tau_d || !tau_c || !y) return fail(DG_ERR_INVALID_ARG, "u/tau_d/tau_c/y is NULL");
+  if (desc->n_q != 0 && desc->n_q != desc->degree + 1)
+    return fail(DG_ERR_UNSUPPORTED, "the projection operator is built for n_q = k+1");
+  const size_t es = dtype == DG_F64 ? 8 : 4;
+  const size_t bytes = (size_t)3 * num_elements(desc) * dofs_per_element(desc) * es;
+  const size_t tb = (size_t)num_elements(desc) * es;
+  if (overlaps(u, bytes, y, bytes) || overlaps(tau_d, tb, y, bytes) || overlaps(tau_c, tb, y, bytes))
+    return fail(DG_ERR_ALIAS, "y overlaps an input");
+  const int k = desc->degree, n = k + 1;
+  const Basis1D& B = basis(k, n);
+  ProjPlan P;
+  P.k = k;
+  P.mesh = mesh_args(desc);
+  P.S = B.S;
+  P.Dg = B.Dg;
+  P.M1 = B.Mref;
+  P.w = B.wq;
+  double h[3];
+  P.vol = 1.0;
+  for (int d = 0; d < 3; ++d) {
+    h[d] = desc->length[d] / desc->n_el[d];
+    P.vol *= h[d];
+  }
+  for (int d = 0; d < 3; ++d) {
+    P.ih[d] = 1.0 / h[d];
+    P.area[d] = P.vol / h[d];
+  }
+  hipError_t e = launch_projection(P, dtype == DG_F32, u, y, tau_d, tau_c, (hipStream_t)hip_stream);
+  if (e != hipSuccess) return hip_fail(e, "projection kernel launch");
+  return ok();
+}
+
 int dg_apply_convective(const dg_op_desc* desc, dg_dtype dtype, const void* u, void* r,
                         void* hip_stream) {
   int rc = validate_desc(desc);

@@ -55,6 +55,17 @@ struct DivPlan {
 
 hipError_t launch_divergence(const DivPlan& P, bool f32, const void* u, void* b, hipStream_t s);
 
+// Projection-step operator (mass + divergence and continuity penalties):
+// 1D tables on [0,1] with k+1 Gauss points and the cell scalings.
+struct ProjPlan {
+  int k = 0;
+  MeshArgs mesh{};
+  std::vector<double> S, Dg, M1, w;   // n x n, n x n, n x n, n
+  double vol = 0, ih[3] = {0, 0, 0}, area[3] = {0, 0, 0};
+};
+hipError_t launch_projection(const ProjPlan& P, bool f32, const void* u, void* y, const void* tau_d,
+                             const void* tau_c, hipStream_t s);
+
 // x = M^-1 b on nblocks consecutive element blocks: Minv = inverse of the 1D
 // mass on [0,1] (n x n row major), scale = 1/(h_x h_y h_z).
 hipError_t launch_inverse_mass(int k, const std::vector<double>& Minv, double scale, long long nblocks, bool f32,

@@ -24,7 +24,7 @@ DG_F64, DG_F32 = 0, 1
 DG_PC_JACOBI_F64, DG_PC_CHEB_F32 = 0, 1
 
 EXPORTS = ("dg_apply_laplace", "dg_apply_convective", "dg_vjp_convective", "dg_apply_divergence",
-           "dg_apply_inverse_mass", "dg_apply_helmholtz", "dg_cg_solve", "dg_laplace_diagonal", "dg_lgl_nodes", "dg_error_string", "dg_last_error")
+           "dg_apply_inverse_mass", "dg_apply_helmholtz", "dg_apply_projection", "dg_cg_solve", "dg_laplace_diagonal", "dg_lgl_nodes", "dg_error_string", "dg_last_error")
 
 
 class OpDesc(ctypes.Structure):
@@ -73,6 +73,7 @@ def lib():
         L.dg_apply_divergence.argtypes = [pd, ctypes.c_int, vp, vp, vp]
         L.dg_apply_inverse_mass.argtypes = [pd, ctypes.c_int, vp, vp, vp]
         L.dg_apply_helmholtz.argtypes = [pd, ctypes.c_int, ctypes.c_double, vp, vp, vp]
+        L.dg_apply_projection.argtypes = [pd, ctypes.c_int, vp, vp, vp, vp, vp]
         L.dg_cg_solve.argtypes = [pd, ctypes.POINTER(CgOpts), vp, vp, ctypes.POINTER(CgReport), vp]
         L.dg_laplace_diagonal.argtypes = [pd, dp]
         L.dg_lgl_nodes.argtypes = [i32, dp]
@@ -81,7 +82,7 @@ def lib():
         L.dg_last_error.argtypes = []
         L.dg_last_error.restype = ctypes.c_char_p
         for name in ("dg_apply_laplace", "dg_apply_convective", "dg_vjp_convective", "dg_apply_divergence",
-                     "dg_apply_inverse_mass", "dg_apply_helmholtz", "dg_cg_solve", "dg_laplace_diagonal", "dg_lgl_nodes"):
+                     "dg_apply_inverse_mass", "dg_apply_helmholtz", "dg_apply_projection", "dg_cg_solve", "dg_laplace_diagonal", "dg_lgl_nodes"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -213,6 +214,24 @@ def apply_helmholtz(desc, u, mass_factor, out=None):
     _check_tensor(out, "out", shape)
     _check(lib().dg_apply_helmholtz(ctypes.byref(desc), _dtype_code(u), float(mass_factor),
                                     ctypes.c_void_p(u.data_ptr()), ctypes.c_void_p(out.data_ptr()), _stream(u)))
+    return out
+
+
+def apply_projection(desc, u, tau_d, tau_c, out=None):
+    """(M + A_D + A_C) u of the projection step; u: [3, N_el, n^3]; tau_d, tau_c: [N_el]."""
+    torch = _torch()
+    shape = (3, _nel(desc), (desc.degree + 1) ** 3)
+    _check_tensor(u, "u", shape)
+    _check_tensor(tau_d, "tau_d", (_nel(desc),))
+    _check_tensor(tau_c, "tau_c", (_nel(desc),))
+    if tau_d.dtype != u.dtype or tau_c.dtype != u.dtype:
+        raise TypeError("tau_d and tau_c must have the dtype of u")
+    if out is None:
+        out = torch.empty_like(u)
+    _check_tensor(out, "out", shape)
+    _check(lib().dg_apply_projection(ctypes.byref(desc), _dtype_code(u), ctypes.c_void_p(u.data_ptr()),
+                                     ctypes.c_void_p(tau_d.data_ptr()), ctypes.c_void_p(tau_c.data_ptr()),
+                                     ctypes.c_void_p(out.data_ptr()), _stream(u)))
     return out
 
 
