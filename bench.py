@@ -174,41 +174,17 @@ def cpu_baseline(args):
                        + ", ".join(parts) + ")")}
 
 
-def extras(torch, dgmf, inputs, dev, args, which=("vjp", "cg", "mass")):
+def extras(torch, dgmf, inputs, dev, args, which=("vjp", "cg", "mass", "proj")):
     out = {}
-    # inverse mass (element-local, memory bound), degree-sweep meshes, seeded U[-1,1];
-    # 4 input/output pairs in rotation, so that the 256 MB Infinity Cache does
-    # not hold a pair between its repeats
+    # inverse mass (element-local, memory bound) and the projection-step
+    # operator (M + A_D + A_C, three components, seeded per-element penalty
+    # parameters), degree-sweep meshes, seeded U[-1,1]
     if "mass" in which:
-        res = {}
-        R = 4
-        for k in range(args.kmin, args.kmax + 1):
-            N = sweep_mesh(k)
-            d = dgmf.make_desc(k, N)
-            g = torch.Generator(device=dev)
-            g.manual_seed(102 + 10 * k)
-            base = torch.rand((N ** 3, (k + 1) ** 3), generator=g, dtype=torch.float64, device=dev) * 2 - 1
-            for dtype, tdt in (("f64", torch.float64), ("f32", torch.float32)):
-                xs = [base.to(tdt) for _ in range(R)]
-                ys = [torch.empty_like(xs[0]) for _ in range(R)]
-                for i in range(R):
-                    dgmf.apply_inverse_mass(d, xs[i], ys[i])
-                torch.cuda.synchronize()
-                s0, e0 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                reps = 5 * R
-                s0.record()
-                for i in range(reps):
-                    dgmf.apply_inverse_mass(d, xs[i % R], ys[i % R])
-                e0.record()
-                torch.cuda.synchronize()
-                t = s0.elapsed_time(e0) / 1e3 / reps
-                n = xs[0].numel()
-                nbytes = (16 if dtype == "f64" else 8) * n
-                res[f"k{k}_{dtype}"] = {"us": t * 1e6, "dofs_per_s": n / t,
-                                        "hbm_frac": nbytes / t / (HBM_PEAK_GBS * 1e9)}
-                del xs, ys
-            del base
-        out["inverse_mass_sweep"] = res
+        out["inverse_mass_sweep"] = _sweep_extra(torch, dgmf, dev, args, 1, 102, lambda d, x, y, tau:
+                                                 dgmf.apply_inverse_mass(d, x, y))
+    if "proj" in which:
+        out["projection_sweep"] = _sweep_extra(torch, dgmf, dev, args, 3, 103, lambda d, x, y, tau:
+                                               dgmf.apply_projection(d, x, tau[0], tau[1], y))
     # convective VJP, k=4, 32^3, TGV + noise velocity and N(0,1) cotangent
     try:
         if "vjp" not in which:
@@ -265,6 +241,48 @@ def extras(torch, dgmf, inputs, dev, args, which=("vjp", "cg", "mass")):
     return out
 
 
+def _sweep_extra(torch, dgmf, dev, args, comps, seed, apply):
+    """Time one element-local operator over the degree-sweep meshes.  4 input/
+    output pairs in rotation, so that the 256 MB Infinity Cache does not hold
+    a pair between its repeats.  Algorithmic bytes: read and write every DoF
+    once, plus the two per-element penalty parameters (projection only)."""
+    res = {}
+    R = 4
+    for k in range(args.kmin, args.kmax + 1):
+        N = sweep_mesh(k)
+        d = dgmf.make_desc(k, N, n_comp=comps)
+        g = torch.Generator(device=dev)
+        g.manual_seed(seed + 10 * k)
+        shape = (N ** 3, (k + 1) ** 3) if comps == 1 else (comps, N ** 3, (k + 1) ** 3)
+        base = torch.rand(shape, generator=g, dtype=torch.float64, device=dev) * 2 - 1
+        h2 = (2 * np.pi / N) ** 2
+        taus = [(0.1 + 0.9 * torch.rand(N ** 3, generator=g, dtype=torch.float64, device=dev)) * h2
+                for _ in range(2)]
+        for dtype, tdt in (("f64", torch.float64), ("f32", torch.float32)):
+            xs = [base.to(tdt) for _ in range(R)]
+            ys = [torch.empty_like(xs[0]) for _ in range(R)]
+            tau = [t.to(tdt) for t in taus]
+            for i in range(R):
+                apply(d, xs[i], ys[i], tau)
+            torch.cuda.synchronize()
+            s0, e0 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            reps = 5 * R
+            s0.record()
+            for i in range(reps):
+                apply(d, xs[i % R], ys[i % R], tau)
+            e0.record()
+            torch.cuda.synchronize()
+            t = s0.elapsed_time(e0) / 1e3 / reps
+            n = xs[0].numel()
+            es = 8 if dtype == "f64" else 4
+            nbytes = 2 * es * n + (2 * es * N ** 3 if comps == 3 else 0)
+            res[f"k{k}_{dtype}"] = {"us": t * 1e6, "dofs_per_s": n / t,
+                                    "hbm_frac": nbytes / t / (HBM_PEAK_GBS * 1e9)}
+            del xs, ys, tau
+        del base, taus
+    return res
+
+
 class _Skip(Exception):
     pass
 
@@ -282,7 +300,7 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--sweep-out", default="")
     ap.add_argument("--extras-only", default="",
-                    help="diagnostic: run only these extras (vjp,cg,mass), print them as one JSON line, no sweep")
+                    help="diagnostic: run only these extras (vjp,cg,mass,proj), print them as one JSON line, no sweep")
     ap.add_argument("--calib-copy", type=int, default=0,
                     help="also run one plain device copy of this many bytes (counter calibration)")
     args = ap.parse_args()

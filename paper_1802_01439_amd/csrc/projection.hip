@@ -14,9 +14,10 @@
 // on the face layer (LGL face nodes, M1 the 1D mass on [0,1]).
 //
 // Mapping: one workgroup per batch of E elements, 3 n^2 threads per element
-// (component j, pencil).  Own data and the neighbours' facing layers of the
-// normal components are loaded first; the sweeps run on LDS pencils in
-// place; 13 barriers.
+// (component j, pencil); batches are mapped XCD-aware, so that the
+// neighbours' facing layers are mostly found in the same L2.  Own data and
+// the neighbours' facing layers of the normal components are loaded first;
+// the sweeps run on LDS pencils in place; 13 barriers.
 #include "api_internal.h"
 #include "common.h"
 #include "laplace_kernels.h"
@@ -57,7 +58,7 @@ projection_kernel(const T* __restrict__ u, T* __restrict__ y, const T* __restric
   const int rem = tid - le * 3 * N2;
   const int j = rem / N2, p = rem - j * N2;
   const int p0 = p % N, p1 = p / N;
-  const long long e = (long long)blockIdx.x * E + le;
+  const long long e = (long long)xcd_remap(blockIdx.x, gridDim.x) * E + le;
   const bool active = e < mesh.n_el;
   const size_t cs = (size_t)mesh.n_el * N3;
   T* L = lds + le * PER;
@@ -108,9 +109,14 @@ projection_kernel(const T* __restrict__ u, T* __restrict__ y, const T* __restric
     }
   }
   __syncthreads();
-  // ---- P1..P3: ug = S (x) S (x) S u, in place, all components
+  // ---- P1..P3: ug = S (x) S (x) S u, in place, all components; first the
+  //      face jumps u^- - u^+ of this thread's face nodes into FF
 #pragma unroll
   for (int dd = 0; dd < 3; ++dd) {
+    if (active && dd == 0) {
+#pragma unroll
+      for (int s = 0; s < 2; ++s) FF[(j * 2 + s) * N2 + p] = GF[(j * 2 + s) * N2 + p] - FF[(j * 2 + s) * N2 + p];
+    }
     if (active) {
       const auto& t = *fresh(tab);
       int base, str;
@@ -205,23 +211,28 @@ projection_kernel(const T* __restrict__ u, T* __restrict__ y, const T* __restric
     }
     __syncthreads();
   }
-  // ---- P10: continuity penalty on component j = d, face node (t0, t1) = (p0, p1)
+  // ---- P10: continuity penalty on component j = d, face node (t0, t1) = (p0, p1):
+  //      (M1 (x) M1) applied to the jump layer; the M1 rows of p0 and p1 are
+  //      held in registers and the t1 loop is not unrolled, so that the jump
+  //      layer is read one row at a time
   if (active) {
-    const auto& t = *fresh(tab);
     const int d = j;
+    T m0[N];
 #pragma unroll
+    for (int i = 0; i < N; ++i) m0[i] = tab->M1[p0][i];
+    const T* m1 = &tab->M1[p1][0];
+#pragma unroll 1
     for (int s = 0; s < 2; ++s) {
       const int nb = neighbor(mesh, ex, ey, ez, d, s);
-      const T tau = T(0.5) * (tau_c[e] + tau_c[nb]) * t.area[d];
-      const T* gf = GF + (d * 2 + s) * N2;
-      const T* ff = FF + (d * 2 + s) * N2;
+      const T tau = T(0.5) * (tau_c[e] + tau_c[nb]) * tab->area[d];
+      const T* df = FF + (d * 2 + s) * N2;
       T acc = 0;
-#pragma unroll
+#pragma unroll 1
       for (int t1 = 0; t1 < N; ++t1) {
         T row = 0;
 #pragma unroll
-        for (int t0 = 0; t0 < N; ++t0) row = fmadd(t.M1[p0][t0], gf[t0 + N * t1] - ff[t0 + N * t1], row);
-        acc = fmadd(t.M1[p1][t1], row, acc);
+        for (int t0 = 0; t0 < N; ++t0) row = fmadd(m0[t0], df[t0 + N * t1], row);
+        acc = fmadd(m1[t1], row, acc);
       }
       const int lay = s ? N - 1 : 0;
       int idx;
