@@ -15,9 +15,15 @@
 //
 // Mapping: one workgroup per batch of E elements, 3 n^2 threads per element
 // (component j, pencil); batches are mapped XCD-aware, so that the
-// neighbours' facing layers are mostly found in the same L2.  Own data and
-// the neighbours' facing layers of the normal components are loaded first;
-// the sweeps run on LDS pencils in place; 13 barriers.
+// neighbours' facing layers are mostly found in the same L2.  The z sweeps
+// of S and S^T run in registers on the loaded and stored z columns; the other
+// sweeps run on LDS pencils in place; 8 barriers.  Both point sets are
+// symmetric about 1/2, so S and S^T are centrosymmetric and Dg, Dg^T
+// centro-antisymmetric: every 1D sweep runs in even-odd form, about half the
+// multiply-adds of the dense product.
+#include <algorithm>
+#include <cmath>
+
 #include "api_internal.h"
 #include "common.h"
 #include "laplace_kernels.h"
@@ -27,12 +33,53 @@ namespace dgmf {
 
 namespace {
 
+// Even-odd form of an n x n matrix A with A[n-1-i][n-1-j] = SIG A[i][j]
+// (H = n/2): P[i][j] = (A[i][j] + A[i][n-1-j]) / 2, Q[i][j] = (A[i][j] -
+// A[i][n-1-j]) / 2 for i, j < H; for odd n also the middle column, row and
+// entry.
+template <int N, typename T>
+struct EOMat {
+  static constexpr int H = N / 2;
+  T P[H][H], Q[H][H];
+  T col[H], row[H], mid;
+};
+
+// y = A x for such a matrix, from the even and odd halves of x.
+template <int N, int SIG, typename T, typename M>
+__device__ __forceinline__ void eo_apply(const M& A, const T* x, T* y) {
+  constexpr int H = N / 2;
+  T e[H], o[H];
+#pragma unroll
+  for (int j = 0; j < H; ++j) {
+    e[j] = x[j] + x[N - 1 - j];
+    o[j] = x[j] - x[N - 1 - j];
+  }
+#pragma unroll
+  for (int i = 0; i < H; ++i) {
+    T P = A.P[i][0] * e[0];
+#pragma unroll
+    for (int j = 1; j < H; ++j) P = fmadd(A.P[i][j], e[j], P);
+    if constexpr (N % 2) P = fmadd(A.col[i], x[H], P);
+    T Q = A.Q[i][0] * o[0];
+#pragma unroll
+    for (int j = 1; j < H; ++j) Q = fmadd(A.Q[i][j], o[j], Q);
+    y[i] = P + Q;
+    y[N - 1 - i] = SIG > 0 ? P - Q : Q - P;
+  }
+  if constexpr (N % 2) {
+    T m = A.mid * x[H];
+#pragma unroll
+    for (int j = 0; j < H; ++j) m = fmadd(A.row[j], SIG > 0 ? e[j] : o[j], m);
+    y[H] = m;
+  }
+}
+
 template <int N, typename T>
 struct ProjTab {
-  T S[N][N];    // S[q][a] = l_a(z_q)
-  T Dg[N][N];   // Dg[q][r] = derivative of the Gauss Lagrange basis r at z_q
-  T M1[N][N];   // 1D mass on [0,1]
-  T w[N];       // Gauss weights on [0,1]
+  EOMat<N, T> S, St, Dg, Dt;   // S[q][a] = l_a(z_q); Dg[q][r] = derivative of
+                               // the Gauss Lagrange basis r at z_q; St, Dt transposed
+  T M1[N][N];                  // 1D mass on [0,1]
+  T w[N];                      // Gauss weights on [0,1]
   T vol, ih[3], area[3];
 };
 
@@ -64,8 +111,8 @@ projection_kernel(const T* __restrict__ u, T* __restrict__ y, const T* __restric
   T* L = lds + le * PER;
   T* A = L + j * ES;              // this thread's component
   T* DV = L + 3 * ES;
-  T* GF = L + 4 * ES;             // own face layers   [d][s][t0 + N t1]
-  T* FF = GF + 6 * N2;            // neighbour layers  [d][s][t0 + N t1]
+  T* GF = L + 4 * ES;             // own face layers, later the face terms  [d][s][t0 + N t1]
+  T* FF = GF + 6 * N2;            // neighbour layers, later the jumps        [d][s][t0 + N t1]
   const int nxy = mesh.nx * mesh.ny;
   const int ez = active ? (int)(e / nxy) : 0, exy = active ? (int)(e - (long long)ez * nxy) : 0;
   const int ey = exy / (mesh.nx > 0 ? mesh.nx : 1), ex = exy - ey * mesh.nx;
@@ -75,15 +122,14 @@ projection_kernel(const T* __restrict__ u, T* __restrict__ y, const T* __restric
     else if (dd == 1) { base = p0 + PY * p1; str = PX; }
     else { base = p0 + PX * p1; str = PY; }
   };
-  // ---- P0: own z column of component j; own face layers of the normal
-  //      component; the neighbours' facing layers of component j = d
+  const int zcol = p0 + PX * p1;   // this thread's z column (a, b) = (p0, p1)
+  // ---- P0: own z column of component j, its face values, the neighbours'
+  //      facing layers of component j = d; S along z in registers
   if (active) {
     const T* g = u + j * cs + (size_t)e * N3 + p0 + N * p1;
-    T x[N];
+    T x[N], v[N];
 #pragma unroll
     for (int c = 0; c < N; ++c) x[c] = g[N2 * c];
-#pragma unroll
-    for (int c = 0; c < N; ++c) A[p0 + PX * p1 + PY * c] = x[c];
     if (j == 0 && (p0 == 0 || p0 == N - 1)) {   // x faces: (t0, t1) = (b, c)
 #pragma unroll
       for (int c = 0; c < N; ++c) GF[(0 * 2 + (p0 ? 1 : 0)) * N2 + p1 + N * c] = x[c];
@@ -107,115 +153,63 @@ projection_kernel(const T* __restrict__ u, T* __restrict__ y, const T* __restric
       else idx = p0 + N * p1 + N2 * lay;
       FF[(j * 2 + s) * N2 + p] = u[j * cs + (size_t)nb * N3 + idx];
     }
+    eo_apply<N, 1>(fresh(tab)->S, x, v);
+#pragma unroll
+    for (int c = 0; c < N; ++c) A[zcol + PY * c] = v[c];
   }
   __syncthreads();
-  // ---- P1..P3: ug = S (x) S (x) S u, in place, all components; first the
-  //      face jumps u^- - u^+ of this thread's face nodes into FF
+  // ---- P1, P2: S along x and y on LDS pencils; first the face jumps
+  //      u^- - u^+ of this thread's face nodes into FF
 #pragma unroll
-  for (int dd = 0; dd < 3; ++dd) {
+  for (int dd = 0; dd < 2; ++dd) {
     if (active && dd == 0) {
 #pragma unroll
       for (int s = 0; s < 2; ++s) FF[(j * 2 + s) * N2 + p] = GF[(j * 2 + s) * N2 + p] - FF[(j * 2 + s) * N2 + p];
     }
     if (active) {
-      const auto& t = *fresh(tab);
       int base, str;
       pencil(dd, base, str);
       T x[N], v[N];
 #pragma unroll
       for (int a = 0; a < N; ++a) x[a] = A[base + str * a];
-#pragma unroll
-      for (int q = 0; q < N; ++q) {
-        T s = t.S[q][0] * x[0];
-#pragma unroll
-        for (int a = 1; a < N; ++a) s = fmadd(t.S[q][a], x[a], s);
-        v[q] = s;
-      }
+      eo_apply<N, 1>(fresh(tab)->S, x, v);
 #pragma unroll
       for (int q = 0; q < N; ++q) A[base + str * q] = v[q];
     }
     __syncthreads();
   }
-  // ---- P4: div = sum_j (1/h_j) Dg_j ug_j, one component after the other
+  // ---- P3: along direction j: keep vol W ug_j in registers, overwrite
+  //      ug_j with its derivative (1/h_j) Dg_j ug_j
+  int base, str;
+  pencil(j, base, str);
+  T mw[N];
+  if (active) {
+    const auto& t = *fresh(tab);
+    T x[N], v[N];
 #pragma unroll
-  for (int jj = 0; jj < 3; ++jj) {
-    if (active && j == jj) {
-      const auto& t = *fresh(tab);
-      int base, str;
-      pencil(jj, base, str);
-      T x[N];
+    for (int r = 0; r < N; ++r) x[r] = A[base + str * r];
+    // tensor weight along the pencil: the two fixed indices are (p0, p1)
+    const T w2 = t.vol * t.w[p0] * t.w[p1];
 #pragma unroll
-      for (int r = 0; r < N; ++r) x[r] = A[base + str * r];
+    for (int r = 0; r < N; ++r) mw[r] = w2 * t.w[r] * x[r];
+    eo_apply<N, -1>(t.Dg, x, v);
 #pragma unroll
-      for (int q = 0; q < N; ++q) {
-        T s = t.Dg[q][0] * x[0];
-#pragma unroll
-        for (int r = 1; r < N; ++r) s = fmadd(t.Dg[q][r], x[r], s);
-        s *= t.ih[jj];
-        DV[base + str * q] = jj == 0 ? s : DV[base + str * q] + s;
-      }
-    }
-    __syncthreads();
+    for (int q = 0; q < N; ++q) A[base + str * q] = t.ih[j] * v[q];
   }
-  // ---- P5: pointwise weights: DV <- tau_D vol W div, A_j <- vol W ug_j
+  __syncthreads();
+  // ---- P4: DV <- tau_D vol W div on z-column nodes c = j, j+3, ...;
+  //      continuity term of face node (p0, p1) of the faces normal to e_j into GF
   if (active) {
     const auto& t = *fresh(tab);
     const T td = tau_d[e] * t.vol;
-    int base, str;
-    pencil(2, base, str);   // this thread's z column (p0, p1) = (a, b)
     const T wab = t.w[p0] * t.w[p1];
+    const T* A0 = L;
 #pragma unroll
     for (int c = 0; c < N; ++c) {
-      const T wq = wab * t.w[c];
-      A[base + str * c] *= t.vol * wq;
-      if (j == 0) DV[base + str * c] *= td * wq;
+      if (c % 3 != j) continue;
+      const int i = zcol + PY * c;
+      DV[i] = td * wab * t.w[c] * (A0[i] + A0[i + ES] + A0[i + 2 * ES]);
     }
-  }
-  __syncthreads();
-  // ---- P6: A_j += (1/h_j) Dg_j^T DV
-  if (active) {
-    const auto& t = *fresh(tab);
-    int base, str;
-    pencil(j, base, str);
-    T x[N];
-#pragma unroll
-    for (int q = 0; q < N; ++q) x[q] = DV[base + str * q];
-#pragma unroll
-    for (int r = 0; r < N; ++r) {
-      T s = t.Dg[0][r] * x[0];
-#pragma unroll
-      for (int q = 1; q < N; ++q) s = fmadd(t.Dg[q][r], x[q], s);
-      A[base + str * r] = fmadd(t.ih[j], s, A[base + str * r]);
-    }
-  }
-  __syncthreads();
-  // ---- P7..P9: y = S^T (x) S^T (x) S^T z, in place
-#pragma unroll
-  for (int dd = 0; dd < 3; ++dd) {
-    if (active) {
-      const auto& t = *fresh(tab);
-      int base, str;
-      pencil(dd, base, str);
-      T x[N], v[N];
-#pragma unroll
-      for (int q = 0; q < N; ++q) x[q] = A[base + str * q];
-#pragma unroll
-      for (int a = 0; a < N; ++a) {
-        T s = t.S[0][a] * x[0];
-#pragma unroll
-        for (int q = 1; q < N; ++q) s = fmadd(t.S[q][a], x[q], s);
-        v[a] = s;
-      }
-#pragma unroll
-      for (int a = 0; a < N; ++a) A[base + str * a] = v[a];
-    }
-    __syncthreads();
-  }
-  // ---- P10: continuity penalty on component j = d, face node (t0, t1) = (p0, p1):
-  //      (M1 (x) M1) applied to the jump layer; the M1 rows of p0 and p1 are
-  //      held in registers and the t1 loop is not unrolled, so that the jump
-  //      layer is read one row at a time
-  if (active) {
     const int d = j;
     T m0[N];
 #pragma unroll
@@ -234,34 +228,98 @@ projection_kernel(const T* __restrict__ u, T* __restrict__ y, const T* __restric
         for (int t0 = 0; t0 < N; ++t0) row = fmadd(m0[t0], df[t0 + N * t1], row);
         acc = fmadd(m1[t1], row, acc);
       }
-      const int lay = s ? N - 1 : 0;
-      int idx;
-      if (d == 0) idx = lay + PX * p0 + PY * p1;
-      else if (d == 1) idx = p0 + PX * lay + PY * p1;
-      else idx = p0 + PX * p1 + PY * lay;
-      A[idx] += tau * acc;
+      GF[(d * 2 + s) * N2 + p] = tau * acc;
     }
   }
   __syncthreads();
-  // ---- P11: store the z column of component j
+  // ---- P5: z_j = vol W ug_j + (1/h_j) Dg_j^T DV along direction j
   if (active) {
+    const auto& t = *fresh(tab);
+    T x[N], v[N];
+#pragma unroll
+    for (int q = 0; q < N; ++q) x[q] = DV[base + str * q];
+    eo_apply<N, -1>(t.Dt, x, v);
+#pragma unroll
+    for (int r = 0; r < N; ++r) A[base + str * r] = fmadd(t.ih[j], v[r], mw[r]);
+  }
+  __syncthreads();
+  // ---- P6, P7: S^T along x and y
+#pragma unroll
+  for (int dd = 0; dd < 2; ++dd) {
+    if (active) {
+      int b2, s2;
+      pencil(dd, b2, s2);
+      T x[N], v[N];
+#pragma unroll
+      for (int q = 0; q < N; ++q) x[q] = A[b2 + s2 * q];
+      eo_apply<N, 1>(fresh(tab)->St, x, v);
+#pragma unroll
+      for (int a = 0; a < N; ++a) A[b2 + s2 * a] = v[a];
+    }
+    __syncthreads();
+  }
+  // ---- P8: S^T along z in registers, the continuity terms of this column's
+  //      face nodes, store
+  if (active) {
+    T x[N], v[N];
+#pragma unroll
+    for (int c = 0; c < N; ++c) x[c] = A[zcol + PY * c];
+    eo_apply<N, 1>(fresh(tab)->St, x, v);
+    if (j == 0 && (p0 == 0 || p0 == N - 1)) {
+#pragma unroll
+      for (int c = 0; c < N; ++c) v[c] += GF[(0 * 2 + (p0 ? 1 : 0)) * N2 + p1 + N * c];
+    }
+    if (j == 1 && (p1 == 0 || p1 == N - 1)) {
+#pragma unroll
+      for (int c = 0; c < N; ++c) v[c] += GF[(1 * 2 + (p1 ? 1 : 0)) * N2 + p0 + N * c];
+    }
+    if (j == 2) {
+      v[0] += GF[(2 * 2 + 0) * N2 + p];
+      v[N - 1] += GF[(2 * 2 + 1) * N2 + p];
+    }
     T* g = y + j * cs + (size_t)e * N3 + p0 + N * p1;
 #pragma unroll
-    for (int c = 0; c < N; ++c) g[N2 * c] = A[p0 + PX * p1 + PY * c];
+    for (int c = 0; c < N; ++c) g[N2 * c] = v[c];
   }
+}
+
+// Even-odd tables of the n x n row-major matrix A (parity sig); false if A
+// lacks that parity.
+template <int N, typename T>
+bool make_eo(const double* A, int sig, EOMat<N, T>& m) {
+  constexpr int H = N / 2;
+  double amax = 0;
+  for (int i = 0; i < N * N; ++i) amax = std::max(amax, std::fabs(A[i]));
+  for (int i = 0; i < N; ++i)
+    for (int k = 0; k < N; ++k)
+      if (std::fabs(A[(N - 1 - i) * N + (N - 1 - k)] - sig * A[i * N + k]) > 1e-11 * amax) return false;
+  for (int i = 0; i < H; ++i) {
+    for (int k = 0; k < H; ++k) {
+      m.P[i][k] = (T)(0.5 * (A[i * N + k] + A[i * N + N - 1 - k]));
+      m.Q[i][k] = (T)(0.5 * (A[i * N + k] - A[i * N + N - 1 - k]));
+    }
+    m.col[i] = (T)(N % 2 ? A[i * N + H] : 0.0);
+    m.row[i] = (T)(N % 2 ? A[H * N + i] : 0.0);
+  }
+  m.mid = (T)(N % 2 ? A[H * N + H] : 0.0);
+  return true;
 }
 
 template <int N, typename T>
 hipError_t launch_n(const ProjPlan& P, const void* u, void* yv, const void* td, const void* tc, hipStream_t s) {
-  ProjTab<N, T> t;
+  ProjTab<N, T> t{};
+  double St[N * N], Dt[N * N];
   for (int i = 0; i < N; ++i) {
     for (int a = 0; a < N; ++a) {
-      t.S[i][a] = (T)P.S[i * N + a];
-      t.Dg[i][a] = (T)P.Dg[i * N + a];
+      St[a * N + i] = P.S[i * N + a];
+      Dt[a * N + i] = P.Dg[i * N + a];
       t.M1[i][a] = (T)P.M1[i * N + a];
     }
     t.w[i] = (T)P.w[i];
   }
+  if (!make_eo<N, T>(P.S.data(), 1, t.S) || !make_eo<N, T>(St, 1, t.St) || !make_eo<N, T>(P.Dg.data(), -1, t.Dg) ||
+      !make_eo<N, T>(Dt, -1, t.Dt))
+    return hipErrorInvalidValue;
   t.vol = (T)P.vol;
   for (int d = 0; d < 3; ++d) {
     t.ih[d] = (T)P.ih[d];
