@@ -93,8 +93,11 @@ struct ProjCfg {
   static constexpr int PER = 4 * ES + 12 * N2;
 };
 
+// From n = 9 on, at least 4 waves per SIMD (at most 128 VGPRs): at n = 12
+// in FP64 the compiler would otherwise take 129 and halve the resident
+// workgroups.
 template <int N, typename T>
-__global__ void __launch_bounds__(ProjCfg<N>::THREADS)
+__global__ void __launch_bounds__(ProjCfg<N>::THREADS) __attribute__((amdgpu_waves_per_eu(N >= 9 ? 4 : 1, 8)))
 projection_kernel(const T* __restrict__ u, T* __restrict__ y, const T* __restrict__ tau_d,
                   const T* __restrict__ tau_c, MeshArgs mesh, const ProjTab<N, T>* __restrict__ tab) {
   using C = ProjCfg<N>;
@@ -111,8 +114,8 @@ projection_kernel(const T* __restrict__ u, T* __restrict__ y, const T* __restric
   T* L = lds + le * PER;
   T* A = L + j * ES;              // this thread's component
   T* DV = L + 3 * ES;
-  T* GF = L + 4 * ES;             // own face layers, later the face terms  [d][s][t0 + N t1]
-  T* FF = GF + 6 * N2;            // neighbour layers, later the jumps        [d][s][t0 + N t1]
+  T* GF = L + 4 * ES;             // own face layers, then half-applied face mass  [d][s][t0 + N t1]
+  T* FF = GF + 6 * N2;            // neighbour layers, then jumps, then face terms [d][s][t0 + N t1]
   const int nxy = mesh.nx * mesh.ny;
   const int ez = active ? (int)(e / nxy) : 0, exy = active ? (int)(e - (long long)ez * nxy) : 0;
   const int ey = exy / (mesh.nx > 0 ? mesh.nx : 1), ex = exy - ey * mesh.nx;
@@ -158,13 +161,28 @@ projection_kernel(const T* __restrict__ u, T* __restrict__ y, const T* __restric
     for (int c = 0; c < N; ++c) A[zcol + PY * c] = v[c];
   }
   __syncthreads();
-  // ---- P1, P2: S along x and y on LDS pencils; first the face jumps
-  //      u^- - u^+ of this thread's face nodes into FF
+  // ---- P1, P2: S along x and y on LDS pencils.  Before the x sweep the face
+  //      jumps u^- - u^+ of this thread's face nodes go into FF; before the
+  //      y sweep the first factor of (M1 (x) M1) is applied to them:
+  //      GF[d][s][p0 + N p1] = sum_t0 M1[p0][t0] jump[t0 + N p1]
 #pragma unroll
   for (int dd = 0; dd < 2; ++dd) {
     if (active && dd == 0) {
 #pragma unroll
       for (int s = 0; s < 2; ++s) FF[(j * 2 + s) * N2 + p] = GF[(j * 2 + s) * N2 + p] - FF[(j * 2 + s) * N2 + p];
+    }
+    if (active && dd == 1) {
+      T m0[N];
+#pragma unroll
+      for (int i = 0; i < N; ++i) m0[i] = tab->M1[p0][i];
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        const T* df = FF + (j * 2 + s) * N2 + N * p1;
+        T r = 0;
+#pragma unroll
+        for (int t0 = 0; t0 < N; ++t0) r = fmadd(m0[t0], df[t0], r);
+        GF[(j * 2 + s) * N2 + p] = r;
+      }
     }
     if (active) {
       int base, str;
@@ -198,7 +216,8 @@ projection_kernel(const T* __restrict__ u, T* __restrict__ y, const T* __restric
   }
   __syncthreads();
   // ---- P4: DV <- tau_D vol W div on z-column nodes c = j, j+3, ...;
-  //      continuity term of face node (p0, p1) of the faces normal to e_j into GF
+  //      second factor of (M1 (x) M1) and the penalty factor: continuity term
+  //      of face node (p0, p1) of the faces normal to e_j into FF
   if (active) {
     const auto& t = *fresh(tab);
     const T td = tau_d[e] * t.vol;
@@ -210,25 +229,18 @@ projection_kernel(const T* __restrict__ u, T* __restrict__ y, const T* __restric
       const int i = zcol + PY * c;
       DV[i] = td * wab * t.w[c] * (A0[i] + A0[i + ES] + A0[i + 2 * ES]);
     }
-    const int d = j;
-    T m0[N];
+    T m1[N];
 #pragma unroll
-    for (int i = 0; i < N; ++i) m0[i] = tab->M1[p0][i];
-    const T* m1 = &tab->M1[p1][0];
-#pragma unroll 1
+    for (int i = 0; i < N; ++i) m1[i] = tab->M1[p1][i];
+    const T tce = tau_c[e], area = t.area[j];
+#pragma unroll
     for (int s = 0; s < 2; ++s) {
-      const int nb = neighbor(mesh, ex, ey, ez, d, s);
-      const T tau = T(0.5) * (tau_c[e] + tau_c[nb]) * tab->area[d];
-      const T* df = FF + (d * 2 + s) * N2;
+      const int nb = neighbor(mesh, ex, ey, ez, j, s);
+      const T* r = GF + (j * 2 + s) * N2 + p0;
       T acc = 0;
-#pragma unroll 1
-      for (int t1 = 0; t1 < N; ++t1) {
-        T row = 0;
 #pragma unroll
-        for (int t0 = 0; t0 < N; ++t0) row = fmadd(m0[t0], df[t0 + N * t1], row);
-        acc = fmadd(m1[t1], row, acc);
-      }
-      GF[(d * 2 + s) * N2 + p] = tau * acc;
+      for (int t1 = 0; t1 < N; ++t1) acc = fmadd(m1[t1], r[N * t1], acc);
+      FF[(j * 2 + s) * N2 + p] = T(0.5) * (tce + tau_c[nb]) * area * acc;
     }
   }
   __syncthreads();
@@ -267,15 +279,15 @@ projection_kernel(const T* __restrict__ u, T* __restrict__ y, const T* __restric
     eo_apply<N, 1>(fresh(tab)->St, x, v);
     if (j == 0 && (p0 == 0 || p0 == N - 1)) {
 #pragma unroll
-      for (int c = 0; c < N; ++c) v[c] += GF[(0 * 2 + (p0 ? 1 : 0)) * N2 + p1 + N * c];
+      for (int c = 0; c < N; ++c) v[c] += FF[(0 * 2 + (p0 ? 1 : 0)) * N2 + p1 + N * c];
     }
     if (j == 1 && (p1 == 0 || p1 == N - 1)) {
 #pragma unroll
-      for (int c = 0; c < N; ++c) v[c] += GF[(1 * 2 + (p1 ? 1 : 0)) * N2 + p0 + N * c];
+      for (int c = 0; c < N; ++c) v[c] += FF[(1 * 2 + (p1 ? 1 : 0)) * N2 + p0 + N * c];
     }
     if (j == 2) {
-      v[0] += GF[(2 * 2 + 0) * N2 + p];
-      v[N - 1] += GF[(2 * 2 + 1) * N2 + p];
+      v[0] += FF[(2 * 2 + 0) * N2 + p];
+      v[N - 1] += FF[(2 * 2 + 1) * N2 + p];
     }
     T* g = y + j * cs + (size_t)e * N3 + p0 + N * p1;
 #pragma unroll
