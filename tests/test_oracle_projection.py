@@ -83,3 +83,36 @@ def test_operator_is_symmetric_positive_definite():
     pu, pv = projection_apply(u, k, msh, td, tc), projection_apply(v, k, msh, td, tc)
     assert abs(np.sum(v * pu) - np.sum(u * pv)) < 1e-12 * np.linalg.norm(pu) * np.linalg.norm(v)
     assert np.sum(u * pu) > 0
+
+
+def test_continuity_penalty_energy_against_an_independent_rule():
+    # u^T A_C u = sum over the faces (each once) of {tau_C} int_F (u^-_d - u^+_d)^2:
+    # the two elements of a face contribute u^- (u^- - u^+) and u^+ (u^+ - u^-).
+    # Traces from the Lagrange basis at xi_d = 0, 1, integrated with k+3 Gauss points.
+    k = 3
+    rng = np.random.default_rng(6)
+    msh = M.Mesh((3, 2, 2), (1.2, 0.9, 1.5))
+    n = k + 1
+    u = rng.standard_normal((3, msh.N, n ** 3))
+    tc = rng.uniform(0.5, 2.0, msh.N)
+    AC = projection_apply(u, k, msh, np.zeros(msh.N), tc) - mass_apply(u, k, msh)
+    lhs = float(np.sum(u * AC))
+    nodes = basis.lgl_nodes(k)
+    xg, wg = legendre.leggauss(k + 3)
+    xg, wg = 0.5 * (xg + 1.0), 0.5 * wg
+    L = basis.lagrange_values(nodes, xg)
+    ends = [basis.lagrange_values(nodes, [0.0]), basis.lagrange_values(nodes, [1.0])]
+    h = msh.h
+    vol = float(np.prod(h))
+    rhs = 0.0
+    for d in range(3):
+        up = msh.neighbor(d, 1)
+        for e in range(msh.N):
+            def trace(el, s):
+                f = [L, L, L]
+                f[d] = ends[s]
+                U = u[d, el].reshape(n, n, n)                  # [c, b, a]
+                return np.einsum("pa,qb,rc,cba->pqr", f[0], f[1], f[2], U).squeeze(axis=d)
+            jump = trace(e, 1) - trace(up[e], 0)
+            rhs += 0.5 * (tc[e] + tc[up[e]]) * (vol / h[d]) * float(np.sum(np.outer(wg, wg) * jump ** 2))
+    assert abs(lhs - rhs) < 1e-11 * abs(rhs)
