@@ -4,8 +4,9 @@
  * Operators of the discontinuous Galerkin discretisation of Sec. 3.2 on
  * periodic Cartesian hexahedral meshes with tensor-product Lagrange bases on
  * Legendre-Gauss-Lobatto (LGL) nodes of degree k and Gauss quadrature, and
- * the preconditioned CG solver, the inverse mass matrix and the Helmholtz
- * operator of Sec. 3.3.  All compute runs in HIP kernels for gfx950.
+ * the preconditioned CG solver, the inverse mass matrix, the Helmholtz
+ * operator and the projection-step operator of Sec. 3.3.  All compute runs
+ * in HIP kernels for gfx950.
  *
  * Mesh and layout (every entry point)
  *   - elements per direction n_el[d], box edge length[d]; element size
@@ -21,7 +22,7 @@
  *   - every array pointer is a caller-owned DEVICE pointer, except where a
  *     parameter says "host".  The library owns only its own small caches
  *     (1D tables, solver work vectors).
- *   - apply / vjp / divergence / inverse mass / Helmholtz calls are
+ *   - apply / vjp / divergence / inverse mass / Helmholtz / projection calls are
  *     asynchronous on `hip_stream`
  *     (a hipStream_t; NULL = the default stream).  dg_cg_solve blocks until
  *     it returns.
