@@ -203,6 +203,33 @@ typedef struct {
 int dg_cg_solve(const dg_op_desc* desc, const dg_cg_opts* opts, const double* b, double* x,
                 dg_cg_report* report, void* hip_stream);
 
+enum { DG_OP_HELMHOLTZ = 0, DG_OP_PROJECTION = 1 };
+
+/*
+ * Solve the Helmholtz equation of the viscous step or the projection equation
+ * by CG preconditioned with the inverse mass matrix (Sec. 3.3: the block-
+ * diagonal mass is inverted element by element at the cost of a diagonal
+ * scaling and serves as the preconditioner of both steps), in double
+ * precision, k+1 Gauss points (n_q must be 0 or k+1):
+ *   DG_OP_HELMHOLTZ:  (mass_factor M + L) x = b, L the form of
+ *                     dg_apply_laplace (scale, penalty_factor from desc),
+ *                     mass_factor > 0, n_comp 1 or 3; tau_d, tau_c unused;
+ *   DG_OP_PROJECTION: (M + A_D + A_C) x = b, the operator of
+ *                     dg_apply_projection; n_comp = 3; tau_d, tau_c: [N_el]
+ *                     doubles (device); mass_factor unused.
+ *   b, x: [n_comp][N_el][n^3] doubles (device); x: initial guess in,
+ *   solution out; must not overlap b, tau_d or tau_c.  Stops when
+ *   ||r||_2 <= rtol ||b||_2 (recursive residual); report: host pointer, may
+ *   be NULL (then no true residual is computed; lambda_max and matvec_f32
+ *   are 0).
+ * Returns DG_OK, DG_NOT_CONVERGED or DG_ERR_BREAKDOWN (x holds the last
+ * iterate), or a negative error.  Blocks the calling thread; runs on
+ * hip_stream.
+ */
+int dg_mass_pcg_solve(const dg_op_desc* desc, int32_t op, double mass_factor, const double* tau_d,
+                      const double* tau_c, const double* b, double* x, double rtol, int32_t max_iter,
+                      dg_cg_report* report, void* hip_stream);
+
 /*
  * diag(A) of the SIPG form on one element (identical on every element of a
  * uniform periodic mesh with at least 2 elements per direction): host array of

@@ -140,6 +140,39 @@ std::vector<double> solve_spd(const std::vector<double>& A, int n, const std::ve
   return X;
 }
 
+double cell_volume(const dg_op_desc* d) {
+  double vol = 1.0;
+  for (int i = 0; i < 3; ++i) vol *= d->length[i] / d->n_el[i];
+  return vol;
+}
+
+std::vector<double> inverse_mass_1d(int k) {
+  const int n = k + 1;
+  const Basis1D& B = basis(k, n);
+  std::vector<double> I(n * n, 0.0);
+  for (int i = 0; i < n; ++i) I[i * n + i] = 1.0;
+  return solve_spd(B.Mref, n, I, n);
+}
+
+ProjPlan make_proj_plan(const dg_op_desc* desc) {
+  const int k = desc->degree, n = k + 1;
+  const Basis1D& B = basis(k, n);
+  ProjPlan P;
+  P.k = k;
+  P.mesh = mesh_args(desc);
+  P.S = B.S;
+  P.Dg = B.Dg;
+  P.M1 = B.Mref;
+  P.w = B.wq;
+  P.vol = cell_volume(desc);
+  for (int i = 0; i < 3; ++i) {
+    const double h = desc->length[i] / desc->n_el[i];
+    P.ih[i] = 1.0 / h;
+    P.area[i] = P.vol / h;
+  }
+  return P;
+}
+
 LaplacePlan make_laplace_plan(const dg_op_desc* d, int n_comp) {
   const int k = d->degree;
   const int m = d->n_q ? d->n_q : k + 1;
@@ -334,9 +367,7 @@ int dg_apply_helmholtz(const dg_op_desc* desc, dg_dtype dtype, double mass_facto
                        (dtype == DG_F64 ? 8 : 4);
   if (overlaps(src, bytes, dst, bytes)) return fail(DG_ERR_ALIAS, "dst overlaps src");
   LaplacePlan P = make_laplace_plan(desc, desc->n_comp);
-  double vol = 1.0;
-  for (int d = 0; d < 3; ++d) vol *= desc->length[d] / desc->n_el[d];
-  P.shift = mass_factor * vol;
+  P.shift = mass_factor * cell_volume(desc);
   hipError_t e = launch_laplace(P, dtype == DG_F32, src, dst, (hipStream_t)hip_stream);
   if (e != hipSuccess) return hip_fail(e, "helmholtz kernel launch");
   return ok();
@@ -356,25 +387,7 @@ int dg_apply_projection(const dg_op_desc* desc, dg_dtype dtype, const void* u, c
   const size_t tb = (size_t)num_elements(desc) * es;
   if (overlaps(u, bytes, y, bytes) || overlaps(tau_d, tb, y, bytes) || overlaps(tau_c, tb, y, bytes))
     return fail(DG_ERR_ALIAS, "y overlaps an input");
-  const int k = desc->degree, n = k + 1;
-  const Basis1D& B = basis(k, n);
-  ProjPlan P;
-  P.k = k;
-  P.mesh = mesh_args(desc);
-  P.S = B.S;
-  P.Dg = B.Dg;
-  P.M1 = B.Mref;
-  P.w = B.wq;
-  double h[3];
-  P.vol = 1.0;
-  for (int d = 0; d < 3; ++d) {
-    h[d] = desc->length[d] / desc->n_el[d];
-    P.vol *= h[d];
-  }
-  for (int d = 0; d < 3; ++d) {
-    P.ih[d] = 1.0 / h[d];
-    P.area[d] = P.vol / h[d];
-  }
+  const ProjPlan P = make_proj_plan(desc);
   hipError_t e = launch_projection(P, dtype == DG_F32, u, y, tau_d, tau_c, (hipStream_t)hip_stream);
   if (e != hipSuccess) return hip_fail(e, "projection kernel launch");
   return ok();
@@ -444,15 +457,8 @@ int dg_apply_inverse_mass(const dg_op_desc* desc, dg_dtype dtype, const void* sr
   const long long nblocks = (long long)desc->n_comp * num_elements(desc);
   const size_t bytes = (size_t)nblocks * dofs_per_element(desc) * (dtype == DG_F64 ? 8 : 4);
   if (src != dst && overlaps(src, bytes, dst, bytes)) return fail(DG_ERR_ALIAS, "dst overlaps src (not in place)");
-  const int k = desc->degree, n = k + 1;
-  const Basis1D& B = basis(k, n);
-  std::vector<double> I(n * n, 0.0);
-  for (int i = 0; i < n; ++i) I[i * n + i] = 1.0;
-  const std::vector<double> Minv = solve_spd(B.Mref, n, I, n);
-  double vol = 1.0;
-  for (int d = 0; d < 3; ++d) vol *= desc->length[d] / desc->n_el[d];
-  hipError_t e = launch_inverse_mass(k, Minv, 1.0 / vol, nblocks, dtype == DG_F32, src, dst,
-                                     (hipStream_t)hip_stream);
+  hipError_t e = launch_inverse_mass(desc->degree, inverse_mass_1d(desc->degree), 1.0 / cell_volume(desc), nblocks,
+                                     dtype == DG_F32, src, dst, (hipStream_t)hip_stream);
   if (e != hipSuccess) return hip_fail(e, "inverse mass kernel launch");
   return ok();
 }

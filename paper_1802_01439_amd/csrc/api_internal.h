@@ -2,6 +2,7 @@
 #pragma once
 
 #include <string>
+#include <vector>
 
 #include "basis1d.h"
 #include "dgmf.h"
@@ -22,6 +23,10 @@ long long dofs_per_element(const dg_op_desc* d);
 bool overlaps(const void* a, size_t na, const void* b, size_t nb);
 MeshArgs mesh_args(const dg_op_desc* d);
 LaplacePlan make_laplace_plan(const dg_op_desc* d, int n_comp);
+double cell_volume(const dg_op_desc* d);
+// M1^-1 of the 1D LGL mass on [0,1] (row major, n x n)
+std::vector<double> inverse_mass_1d(int k);
+ProjPlan make_proj_plan(const dg_op_desc* d);
 int default_conv_nq(int k);
 int make_conv_plan(const dg_op_desc* d, ConvPlan& P);
 

@@ -41,6 +41,7 @@ hipError_t cg_update_p(double* z, double* p, double* zold, double mu_z, double b
 hipError_t cg_hash_fill(double* v, unsigned long long seed, long long n, double* partial, hipStream_t s);
 hipError_t cg_axpb(double* y, const double* x, double a, double c, long long n, hipStream_t s);
 hipError_t cg_fill(double* y, double c, long long n, hipStream_t s);
+hipError_t cg_xpby(double* y, const double* x, double b, long long n, hipStream_t s);   // y = x + b y
 
 // main loop with device-side scalars
 hipError_t cg_state_init(double* st, double tol2, int max_it, double sum_d, long long n, bool proj, hipStream_t s);

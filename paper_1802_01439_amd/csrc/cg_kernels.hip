@@ -134,6 +134,13 @@ __global__ void __launch_bounds__(kThreads) k_hash_fill(double* __restrict__ v, 
   block_partials<1>(s, partial);
 }
 
+// y = x + b y
+__global__ void __launch_bounds__(kThreads) k_xpby(double* __restrict__ y, const double* __restrict__ x, double b,
+                                                   long long n) {
+  for (long long i = blockIdx.x * (long long)kThreads + threadIdx.x; i < n; i += (long long)gridDim.x * kThreads)
+    y[i] = x[i] + b * y[i];
+}
+
 __global__ void __launch_bounds__(kThreads) k_axpb(double* __restrict__ y, const double* __restrict__ x, double a,
                                                    double c, long long n) {
   // y = a * x + c
@@ -407,6 +414,7 @@ hipError_t cg_axpb(double* y, const double* x, double a, double c, long long n, 
   DG_LAUNCH(k_axpb, y, x, a, c, n);
 }
 hipError_t cg_fill(double* y, double c, long long n, hipStream_t s) { DG_LAUNCH(k_fill, y, c, n); }
+hipError_t cg_xpby(double* y, const double* x, double b, long long n, hipStream_t s) { DG_LAUNCH(k_xpby, y, x, b, n); }
 
 hipError_t cg_state_init(double* st, double tol2, int max_it, double sum_d, long long n, bool proj, hipStream_t s) {
   hipLaunchKernelGGL(k_state_init, dim3(1), dim3(64), 0, s, st, tol2, (double)max_it, sum_d, (double)n,

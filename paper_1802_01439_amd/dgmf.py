@@ -22,9 +22,10 @@ DG_NOT_CONVERGED = 1
 DG_ERR_BREAKDOWN = 2
 DG_F64, DG_F32 = 0, 1
 DG_PC_JACOBI_F64, DG_PC_CHEB_F32 = 0, 1
+DG_OP_HELMHOLTZ, DG_OP_PROJECTION = 0, 1
 
 EXPORTS = ("dg_apply_laplace", "dg_apply_convective", "dg_vjp_convective", "dg_apply_divergence",
-           "dg_apply_inverse_mass", "dg_apply_helmholtz", "dg_apply_projection", "dg_cg_solve", "dg_laplace_diagonal", "dg_lgl_nodes", "dg_error_string", "dg_last_error")
+           "dg_apply_inverse_mass", "dg_apply_helmholtz", "dg_apply_projection", "dg_cg_solve", "dg_mass_pcg_solve", "dg_laplace_diagonal", "dg_lgl_nodes", "dg_error_string", "dg_last_error")
 
 
 class OpDesc(ctypes.Structure):
@@ -75,6 +76,8 @@ def lib():
         L.dg_apply_helmholtz.argtypes = [pd, ctypes.c_int, ctypes.c_double, vp, vp, vp]
         L.dg_apply_projection.argtypes = [pd, ctypes.c_int, vp, vp, vp, vp, vp]
         L.dg_cg_solve.argtypes = [pd, ctypes.POINTER(CgOpts), vp, vp, ctypes.POINTER(CgReport), vp]
+        L.dg_mass_pcg_solve.argtypes = [pd, ctypes.c_int32, ctypes.c_double, vp, vp, vp, vp, ctypes.c_double,
+                                         ctypes.c_int32, ctypes.POINTER(CgReport), vp]
         L.dg_laplace_diagonal.argtypes = [pd, dp]
         L.dg_lgl_nodes.argtypes = [i32, dp]
         L.dg_error_string.argtypes = [ctypes.c_int]
@@ -82,7 +85,7 @@ def lib():
         L.dg_last_error.argtypes = []
         L.dg_last_error.restype = ctypes.c_char_p
         for name in ("dg_apply_laplace", "dg_apply_convective", "dg_vjp_convective", "dg_apply_divergence",
-                     "dg_apply_inverse_mass", "dg_apply_helmholtz", "dg_apply_projection", "dg_cg_solve", "dg_laplace_diagonal", "dg_lgl_nodes"):
+                     "dg_apply_inverse_mass", "dg_apply_helmholtz", "dg_apply_projection", "dg_cg_solve", "dg_mass_pcg_solve", "dg_laplace_diagonal", "dg_lgl_nodes"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -269,6 +272,32 @@ def cg_solve(desc, b, x=None, precond=DG_PC_CHEB_F32, cheb_degree=5, cheb_range=
     rep = CgReport()
     rc = _check(lib().dg_cg_solve(ctypes.byref(desc), ctypes.byref(o), ctypes.c_void_p(b.data_ptr()),
                                   ctypes.c_void_p(x.data_ptr()), ctypes.byref(rep), _stream(b)), soft_ok=True)
+    return x, rep.as_dict(), rc
+
+
+def mass_pcg_solve(desc, op, b, x=None, mass_factor=0.0, tau_d=None, tau_c=None, rtol=1e-10, max_iter=1000):
+    """FP64 CG preconditioned with the inverse mass matrix for the Helmholtz
+    (op = DG_OP_HELMHOLTZ) or projection (DG_OP_PROJECTION) equation; returns
+    (x, report dict, return code)."""
+    torch = _torch()
+    shape = (desc.n_comp, _nel(desc), (desc.degree + 1) ** 3) if desc.n_comp > 1 else (_nel(desc), (desc.degree + 1) ** 3)
+    _check_tensor(b, "b", shape)
+    if b.dtype != torch.float64:
+        raise TypeError("b must be float64")
+    if x is None:
+        x = torch.zeros_like(b)
+    _check_tensor(x, "x", shape)
+    ptr = [None, None]
+    if op == DG_OP_PROJECTION:
+        for i, t in enumerate((tau_d, tau_c)):
+            _check_tensor(t, "tau", (_nel(desc),))
+            if t.dtype != torch.float64:
+                raise TypeError("tau_d and tau_c must be float64")
+            ptr[i] = ctypes.c_void_p(t.data_ptr())
+    rep = CgReport()
+    rc = _check(lib().dg_mass_pcg_solve(ctypes.byref(desc), int(op), float(mass_factor), ptr[0], ptr[1],
+                                        ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(x.data_ptr()), float(rtol),
+                                        int(max_iter), ctypes.byref(rep), _stream(b)), soft_ok=True)
     return x, rep.as_dict(), rc
 
 

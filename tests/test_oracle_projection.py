@@ -116,3 +116,33 @@ def test_continuity_penalty_energy_against_an_independent_rule():
             jump = trace(e, 1) - trace(up[e], 0)
             rhs += 0.5 * (tc[e] + tc[up[e]]) * (vol / h[d]) * float(np.sum(np.outer(wg, wg) * jump ** 2))
     assert abs(lhs - rhs) < 1e-11 * abs(rhs)
+
+
+def _dense(apply, shape):
+    n = int(np.prod(shape))
+    A = np.zeros((n, n))
+    for i in range(n):
+        e = np.zeros(n)
+        e[i] = 1.0
+        A[:, i] = apply(e.reshape(shape)).ravel()
+    return A
+
+
+def test_mass_preconditioned_cg_solves_the_projection_and_helmholtz_equations():
+    # the oracle's PCG with the inverse mass as preconditioner (Sec. 3.3)
+    # against a dense direct solve of the assembled operators
+    from oracle.mass import helmholtz_apply, inverse_mass_apply
+    from oracle.solvers import pcg
+    k = 1
+    msh = M.Mesh((2, 2, 1), (1.0, 0.8, 0.6))
+    rng = np.random.default_rng(9)
+    td, tc = rng.uniform(0.1, 1.0, msh.N), rng.uniform(0.1, 1.0, msh.N)
+    shape = (3, msh.N, (k + 1) ** 3)
+    cases = [lambda v: projection_apply(v, k, msh, td, tc), lambda v: helmholtz_apply(v, k, msh, 5.0)]
+    for apply in cases:
+        b = rng.standard_normal(shape)
+        A = _dense(apply, shape)
+        x_direct = np.linalg.solve(A, b.ravel()).reshape(shape)
+        x, info = pcg(apply, b, precond=lambda r: inverse_mass_apply(r, k, msh), rtol=1e-13, flexible=False)
+        assert np.linalg.norm(x - x_direct) < 1e-10 * np.linalg.norm(x_direct)
+        assert info["iterations"] < 60
