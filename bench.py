@@ -174,7 +174,7 @@ def cpu_baseline(args):
                        + ", ".join(parts) + ")")}
 
 
-def extras(torch, dgmf, inputs, dev, args, which=("vjp", "cg", "mass", "proj")):
+def extras(torch, dgmf, inputs, dev, args, which=("vjp", "cg", "mass", "proj", "mpcg")):
     out = {}
     # inverse mass (element-local, memory bound) and the projection-step
     # operator (M + A_D + A_C, three components, seeded per-element penalty
@@ -185,6 +185,16 @@ def extras(torch, dgmf, inputs, dev, args, which=("vjp", "cg", "mass", "proj")):
     if "proj" in which:
         out["projection_sweep"] = _sweep_extra(torch, dgmf, dev, args, 3, 103, lambda d, x, y, tau:
                                                dgmf.apply_projection(d, x, tau[0], tau[1], y))
+    # the projection and Helmholtz equations of one time step, k=5, 16^3,
+    # solved by CG with the inverse mass as preconditioner (Sec. 3.3)
+    try:
+        if "mpcg" not in which:
+            raise _Skip
+        out["mass_pcg_k5_16cubed"] = mass_pcg_extra(torch, dgmf, inputs, dev)
+    except _Skip:
+        pass
+    except dgmf.DgError as ex:
+        out["mass_pcg_k5_16cubed"] = {"error": str(ex)}
     # convective VJP, k=4, 32^3, TGV + noise velocity and N(0,1) cotangent
     try:
         if "vjp" not in which:
@@ -239,6 +249,51 @@ def extras(torch, dgmf, inputs, dev, args, which=("vjp", "cg", "mass", "proj")):
     except dgmf.DgError as ex:
         out["cg_k7_24cubed"] = {"error": str(ex)}
     return out
+
+
+def mass_pcg_extra(torch, dgmf, inputs, dev, k=5, N=16):
+    """Velocity = TGV + N(0, 0.01) noise at the LGL nodes; time step from the
+    CFL condition with Cr = 0.2, r = 1.5, U0 = 1; penalty parameters
+    tau_D = |u|_e h/(k+1) dt, tau_C = |u|_e dt (zeta = 1) with |u|_e the mean
+    nodal velocity magnitude of the element; Helmholtz with gamma_0 = 3/2
+    (BDF2) and nu = 1/1600.  Right-hand sides M u and (1/dt) M u, zero start,
+    relative tolerance 1e-6 (the paper's) and 1e-10.  Bytes per iteration:
+    144 per DoF (operator 16, p.q 16, x/r update 48, inverse mass 16, r.z and
+    r.r 24, direction update 24)."""
+    L = 2 * np.pi
+    h = L / N
+    dt = 0.2 / k ** 1.5 * h / 1.0
+    nodes = dgmf.lgl_nodes(k)
+    u = inputs.tgv_plus_noise(nodes, (N, N, N), (L,) * 3, seed=inputs.FIELD_SEED_BASE + 2)
+    umag = np.sqrt((u ** 2).sum(axis=0)).mean(axis=1)
+    td = umag * h / (k + 1) * dt
+    tc = umag * dt
+    d3 = dgmf.make_desc(k, N, n_comp=3)
+    ut = torch.from_numpy(u).to(dev)
+    b = torch.empty_like(ut)
+    dm = dgmf.make_desc(k, N, n_comp=3, scale=0.0)   # Helmholtz with a zero Laplace scale: M u
+    dgmf.apply_helmholtz(dm, ut, 1.0, b)
+    tdd, tcd = torch.from_numpy(td).to(dev), torch.from_numpy(tc).to(dev)
+    dofs = u.size
+    res = {"dt": dt, "dofs": dofs}
+    dh = dgmf.make_desc(k, N, n_comp=3, scale=1.0 / 1600)
+    for rtol in (1e-6, 1e-10):
+        for name, call in (
+                ("projection", lambda: dgmf.mass_pcg_solve(d3, dgmf.DG_OP_PROJECTION, b, tau_d=tdd, tau_c=tcd,
+                                                           rtol=rtol)),
+                ("helmholtz", lambda: dgmf.mass_pcg_solve(dh, dgmf.DG_OP_HELMHOLTZ, b / dt, mass_factor=1.5 / dt,
+                                                          rtol=rtol))):
+            call()   # warm-up (tables, work vectors)
+            torch.cuda.synchronize()
+            x, rep, rc = call()
+            it = max(rep["iterations"], 1)
+            per_it = rep["seconds_solve"] / it
+            res[f"{name}_rtol{rtol:g}"] = {"rc": rc, "iterations": rep["iterations"],
+                                          "seconds_solve": rep["seconds_solve"],
+                                          "us_per_iteration": per_it * 1e6,
+                                          "true_rel_res": rep["true_rel_res"],
+                                          "hbm_frac_per_iteration": 144 * dofs / per_it / (HBM_PEAK_GBS * 1e9)}
+    return res
 
 
 def _sweep_extra(torch, dgmf, dev, args, comps, seed, apply):
@@ -300,7 +355,7 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--sweep-out", default="")
     ap.add_argument("--extras-only", default="",
-                    help="diagnostic: run only these extras (vjp,cg,mass,proj), print them as one JSON line, no sweep")
+                    help="diagnostic: run only these extras (vjp,cg,mass,proj,mpcg), print them as one JSON line, no sweep")
     ap.add_argument("--calib-copy", type=int, default=0,
                     help="also run one plain device copy of this many bytes (counter calibration)")
     args = ap.parse_args()
