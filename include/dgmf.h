@@ -222,6 +222,9 @@ enum { DG_OP_HELMHOLTZ = 0, DG_OP_PROJECTION = 1 };
  *   ||r||_2 <= rtol ||b||_2 (recursive residual); report: host pointer, may
  *   be NULL (then no true residual is computed; lambda_max and matvec_f32
  *   are 0).
+ * The iteration scalars stay on the device; the host checks the state once
+ * per batch of iterations (report->matvec_f64 counts the no-op iterations
+ * that may end the last batch).
  * Returns DG_OK, DG_NOT_CONVERGED or DG_ERR_BREAKDOWN (x holds the last
  * iterate), or a negative error.  Blocks the calling thread; runs on
  * hip_stream.

@@ -3,14 +3,15 @@
 // applied matrix-free at the cost of a diagonal scaling, which makes it the
 // preconditioner of both steps).  FP64 throughout.
 //
-// Per iteration: q = A p (projection or Helmholtz kernel), p.q, x += alpha p
-// and r -= alpha q, z = M^-1 r (inverse mass kernel), r.z and r.r, p = z +
-// beta p.  The scalars come back to the host twice per iteration (after p.q
-// and after r.z, r.r): the preconditioned operator is well conditioned, so
-// the solves take tens of iterations and the two reads are a small part of
-// each one.
+// Per iteration: q = A p (projection or Helmholtz kernel), p.q and alpha,
+// x += alpha p and r -= alpha q with the partial sums of r.r, z = M^-1 r
+// (inverse mass kernel), r.z, the convergence test and beta, p = z + beta p.
+// The scalars stay on the device; the host reads the state once per batch of
+// iterations, sized from the observed contraction rate.  Once converged, the
+// remaining iterations of a batch change nothing (alpha = 0).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <map>
@@ -31,6 +32,8 @@ struct MassPcgWs {
   double* partial = nullptr;   // 4 * kCgBlocks
   double* res = nullptr;       // 4 results (device)
   double* host = nullptr;      // 4 results (pinned host)
+  double* st = nullptr;        // iteration state (device), kStateSize
+  double* host_st = nullptr;   // its pinned host copy
 };
 
 std::mutex g_mpcg_mutex;
@@ -41,6 +44,8 @@ hipError_t ensure(MassPcgWs& w, long long n) {
   if (!w.partial && (e = hipMalloc((void**)&w.partial, 4 * kCgBlocks * sizeof(double))) != hipSuccess) return e;
   if (!w.res && (e = hipMalloc((void**)&w.res, 4 * sizeof(double))) != hipSuccess) return e;
   if (!w.host && (e = hipHostMalloc((void**)&w.host, 4 * sizeof(double), 0)) != hipSuccess) return e;
+  if (!w.st && (e = hipMalloc((void**)&w.st, kStateSize * sizeof(double))) != hipSuccess) return e;
+  if (!w.host_st && (e = hipHostMalloc((void**)&w.host_st, kStateSize * sizeof(double), 0)) != hipSuccess) return e;
   if (w.n < n) {
     double** v[4] = {&w.r, &w.z, &w.p, &w.q};
     for (double** pp : v) {
@@ -136,42 +141,47 @@ extern "C" int dg_mass_pcg_solve(const dg_op_desc* desc, int32_t op, double mass
   if (bb == 0.0) {   // A x = 0 has the solution 0
     MPCG_CHECK(cg_fill(x, 0.0, n, s), "fill");
     rr = 0.0;
-  } else {
+  } else if (rr > rtol * rtol * bb) {
     const double tol2 = rtol * rtol * bb;
-    double rz = 0.0;
-    if (rr > tol2) {
-      MPCG_CHECK(precond(w.r, w.z), "inverse mass launch");
-      MPCG_CHECK(cg_dot(w.r, w.z, n, w.partial, s), "dot");
-      MPCG_CHECK(read_sums(w, 1, s), "sums");
-      rz = w.host[0];
-      MPCG_CHECK(cg_axpb(w.p, w.z, 1.0, 0.0, n, s), "copy");
-    }
-    while (rr > tol2) {
-      if (it >= max_iter) {
+    MPCG_CHECK(cg_state_init(w.st, tol2, max_iter, 0.0, n, false, s), "state");
+    MPCG_CHECK(precond(w.r, w.z), "inverse mass launch");
+    MPCG_CHECK(cg_dot(w.r, w.z, n, w.partial, s), "dot");
+    MPCG_CHECK(mpcg_start(w.partial, w.st, s), "start");
+    MPCG_CHECK(cg_axpb(w.p, w.z, 1.0, 0.0, n, s), "copy");
+    int batch = std::max(1, std::min(4, (int)max_iter)), launched = 0;
+    double rr_prev = rr;
+    for (;;) {
+      if (max_iter == 0) {
         status = DG_NOT_CONVERGED;
         break;
       }
-      MPCG_CHECK(apply(w.p, w.q), "operator launch");
-      ++matvec;
-      MPCG_CHECK(cg_dot(w.p, w.q, n, w.partial, s), "dot");
-      MPCG_CHECK(read_sums(w, 1, s), "sums");
-      const double pq = w.host[0];
-      if (!(pq > 0.0) || !(rz > 0.0)) {
-        status = DG_ERR_BREAKDOWN;
+      for (int i = 0; i < batch; ++i) {
+        MPCG_CHECK(apply(w.p, w.q), "operator launch");
+        MPCG_CHECK(cg_dot(w.p, w.q, n, w.partial, s), "dot");
+        MPCG_CHECK(cg_fin_alpha(w.partial, kCgBlocks, w.st, s), "alpha");
+        MPCG_CHECK(cg_update_xr_st(x, w.r, w.p, w.q, nullptr, 1, w.st, false, n, w.partial, s), "update");
+        MPCG_CHECK(precond(w.r, w.z), "inverse mass launch");
+        MPCG_CHECK(cg_dot(w.r, w.z, n, w.partial + 2 * kCgBlocks, s), "dot");
+        MPCG_CHECK(mpcg_beta(w.partial + kCgBlocks, w.partial + 2 * kCgBlocks, w.st, s), "beta");
+        MPCG_CHECK(mpcg_xpby(w.p, w.z, w.st, n, s), "direction update");
+      }
+      matvec += batch;
+      launched += batch;
+      MPCG_CHECK(hipMemcpyAsync(w.host_st, w.st, kStateSize * sizeof(double), hipMemcpyDeviceToHost, s), "state copy");
+      MPCG_CHECK(hipStreamSynchronize(s), "state sync");
+      it = (int)w.host_st[kIter];
+      rr = w.host_st[kRN2];
+      if (w.host_st[kDone] != 0.0) {
+        const int st_code = (int)w.host_st[kStatus];
+        status = st_code == 2 ? DG_ERR_BREAKDOWN : st_code == 1 ? DG_NOT_CONVERGED : DG_OK;
         break;
       }
-      const double alpha = rz / pq;
-      MPCG_CHECK(cg_update_xr(x, w.r, w.p, w.q, alpha, n, w.partial, s), "update");
-      MPCG_CHECK(precond(w.r, w.z), "inverse mass launch");
-      MPCG_CHECK(cg_dot(w.r, w.z, n, w.partial, s), "dot");
-      MPCG_CHECK(cg_dot(w.r, w.r, n, w.partial + kCgBlocks, s), "dot");
-      MPCG_CHECK(read_sums(w, 2, s), "sums");
-      ++it;
-      const double rz_new = w.host[0];
-      rr = w.host[1];
-      if (rr <= tol2) break;
-      MPCG_CHECK(cg_xpby(w.p, w.z, rz_new / rz, n, s), "direction update");
-      rz = rz_new;
+      // next batch: the iterations the observed contraction rate still needs (1..8)
+      const double rho = std::pow(rr / rr_prev, 1.0 / batch);
+      int need = 8;
+      if (rho > 0.0 && rho < 1.0) need = (int)std::ceil(std::log(tol2 / rr) / std::log(rho));
+      batch = std::max(1, std::min(8, std::min(need, max_iter - launched)));
+      rr_prev = rr;
     }
   }
   const auto t2 = std::chrono::steady_clock::now();

@@ -47,7 +47,8 @@ def test_projection_solve_parity(k, n_el):
     assert rel_err(x.cpu().numpy(), xr) < 1e-9
     assert abs(rep["iterations"] - info["iterations"]) <= 1
     assert rep["true_rel_res"] < 1e-11
-    assert rep["matvec_f64"] == rep["iterations"] + 2
+    # initial and true residual, plus at most 7 no-op iterations that end a batch
+    assert rep["iterations"] + 2 <= rep["matvec_f64"] <= rep["iterations"] + 9
 
 
 @pytest.mark.parametrize("k,n_comp", [(3, 1), (6, 3)])
