@@ -19,29 +19,32 @@ import numpy as np
 from .tables import tables
 
 
-def projection_apply(u, k, mesh, tau_d, tau_c):
-    """y = (M + A_D + A_C) u; u: [3, N_el, (k+1)^3]; tau_d, tau_c: [N_el]."""
+def projection_apply(u, k, mesh, tau_d, tau_c, elems=None):
+    """y = (M + A_D + A_C) u; u: [3, N_el, (k+1)^3]; tau_d, tau_c: [N_el].
+    With elems, only the rows of those elements: [3, len(elems), (k+1)^3]."""
     T = tables(k, k + 1)
     h = mesh.h
     vol = float(np.prod(h))
     u = np.asarray(u, dtype=np.float64)
     tau_d = np.asarray(tau_d, dtype=np.float64)
     tau_c = np.asarray(tau_c, dtype=np.float64)
+    el = np.arange(mesh.N) if elems is None else np.asarray(elems)
+    ue = u[:, el]
     # mass
     Mb = vol * (T.B.T * T.W) @ T.B
-    y = u @ Mb.T
+    y = ue @ Mb.T
     # divergence penalty: div u at the cell points, tested with div v
-    div = sum((u[j] @ T.G[j].T) / h[j] for j in range(3))          # [N_el, points]
-    dw = div * T.W[None, :] * (vol * tau_d)[:, None]
+    div = sum((ue[j] @ T.G[j].T) / h[j] for j in range(3))         # [elements, points]
+    dw = div * T.W[None, :] * (vol * tau_d[el])[:, None]
     for i in range(3):
         y[i] += (dw @ T.G[i]) / h[i]
     # continuity penalty on the normal component
     for d in range(3):
         area = vol / h[d]
         for s in range(2):
-            nb = mesh.neighbor(d, s)
-            own = u[d] @ T.FV[d][s].T
+            nb = mesh.neighbor(d, s, el)
+            own = ue[d] @ T.FV[d][s].T
             other = u[d][nb] @ T.FV[d][1 - s].T
-            tau = 0.5 * (tau_c + tau_c[nb])
+            tau = 0.5 * (tau_c[el] + tau_c[nb])
             y[d] += area * ((tau[:, None] * T.WF[None, :] * (own - other)) @ T.FV[d][s])
     return y

@@ -102,3 +102,27 @@ def test_argument_errors():
         dgmf.mass_pcg_solve(d1, 7, b1, mass_factor=1.0)
     with pytest.raises(dgmf.DgError):   # x aliases b
         dgmf.mass_pcg_solve(d3, dgmf.DG_OP_PROJECTION, b3, x=b3, tau_d=t, tau_c=t)
+
+
+def test_projection_solve_at_the_benchmark_size():
+    # k = 5, 16^3, TGV + noise velocity, tau from the CFL time step (Cr = 0.2,
+    # r = 1.5), rhs M u: the GPU solution has a small residual under the
+    # oracle's operator
+    from oracle import basis
+    from oracle.mass import mass_apply
+    k, N = 5, 16
+    L = 2 * np.pi
+    h = L / N
+    dt = 0.2 / k ** 1.5 * h
+    msh = M.cube(N)
+    u = inputs.tgv_plus_noise(basis.lgl_nodes(k), (N, N, N), (L,) * 3, seed=inputs.FIELD_SEED_BASE + 2)
+    umag = np.sqrt((u ** 2).sum(axis=0)).mean(axis=1)
+    td, tc = umag * h / (k + 1) * dt, umag * dt
+    b = mass_apply(u, k, msh)
+    announce("mass-preconditioned CG, projection, k=5 16^3")
+    d = dgmf.make_desc(k, N, n_comp=3)
+    x, rep, rc = dgmf.mass_pcg_solve(d, dgmf.DG_OP_PROJECTION, to_dev(b), tau_d=to_dev(td), tau_c=to_dev(tc),
+                                     rtol=1e-10)
+    assert rc == dgmf.DG_OK and rep["iterations"] < 60
+    res = b - projection_apply(x.cpu().numpy(), k, msh, td, tc)
+    assert np.linalg.norm(res) < 1e-9 * np.linalg.norm(b)

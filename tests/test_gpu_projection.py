@@ -6,7 +6,8 @@ oracle applied to the FP32-rounded inputs.  Meshes span several workgroup
 batches with a ragged last batch, on anisotropic boxes, with random
 per-element penalty parameters; one-element directions (the element is its
 own neighbour); the special cases tau = 0 (the mass matrix) and the symmetry
-of the operator at a larger size.
+of the operator at a larger size; the degree-sweep meshes the benchmark
+times, on 64 sampled elements (the first and last among them).
 """
 import numpy as np
 import pytest
@@ -105,3 +106,23 @@ def test_projection_rejects_bad_arguments():
     assert rc == dgmf.DG_ERR_ALIAS
     with pytest.raises(TypeError):
         dgmf.apply_projection(d3, u, t.float(), t)
+
+
+@pytest.mark.parametrize("k,dtype", [(3, torch.float64), (7, torch.float64), (9, torch.float32)])
+def test_projection_full_size_sampled(k, dtype):
+    # the degree-sweep mesh the benchmark times: N = round(256/(k+1)) elements
+    # per direction on [-pi, pi]^3, three components, tau ~ U[0.1, 1] h^2
+    N = int(round(256.0 / (k + 1)))
+    msh = M.cube(N)
+    u = inputs.uniform((3, msh.N, (k + 1) ** 3), seed=890 + k)
+    h2 = float(msh.h[0]) ** 2
+    td = inputs.uniform((msh.N,), seed=891 + k, lo=0.1, hi=1.0) * h2
+    tc = inputs.uniform((msh.N,), seed=892 + k, lo=0.1, hi=1.0) * h2
+    if dtype == torch.float32:
+        u, td, tc = round_f32(u), round_f32(td), round_f32(tc)
+    announce(f"projection full size k={k} N={N} {dtype}")
+    y = _run(k, msh, u, td, tc, dtype)
+    rng = np.random.default_rng(893 + k)
+    el = np.concatenate([[0, msh.N - 1], rng.choice(msh.N, 62, replace=False)])
+    ref = projection_apply(u, k, msh, td, tc, elems=el)
+    assert rel_err(y[:, el], ref) < (1e-12 if dtype == torch.float64 else 1e-5)

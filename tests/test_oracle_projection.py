@@ -146,3 +146,16 @@ def test_mass_preconditioned_cg_solves_the_projection_and_helmholtz_equations():
         x, info = pcg(apply, b, precond=lambda r: inverse_mass_apply(r, k, msh), rtol=1e-13, flexible=False)
         assert np.linalg.norm(x - x_direct) < 1e-10 * np.linalg.norm(x_direct)
         assert info["iterations"] < 60
+
+
+def test_sampled_rows_equal_the_full_apply():
+    k = 2
+    rng = np.random.default_rng(11)
+    msh = M.Mesh((3, 4, 2), (1.0, 2.0, 1.5))
+    u = rng.standard_normal((3, msh.N, (k + 1) ** 3))
+    td, tc = rng.uniform(0.1, 1.0, msh.N), rng.uniform(0.1, 1.0, msh.N)
+    full = projection_apply(u, k, msh, td, tc)
+    el = np.array([0, 5, 23, 7, 7])
+    part = projection_apply(u, k, msh, td, tc, elems=el)
+    # the same sums; a matrix product over fewer rows may round differently
+    assert np.max(np.abs(part - full[:, el])) <= 1e-14 * np.max(np.abs(full))
