@@ -22,7 +22,8 @@
  *   - every array pointer is a caller-owned DEVICE pointer, except where a
  *     parameter says "host".  The library owns only its own small caches
  *     (1D tables, solver work vectors).
- *   - apply / vjp / divergence / inverse mass / Helmholtz / projection calls are
+ *   - apply / vjp / divergence / gradient / inverse mass / Helmholtz /
+ *     projection calls are
  *     asynchronous on `hip_stream`
  *     (a hipStream_t; NULL = the default stream).  dg_cg_solve blocks until
  *     it returns.
@@ -137,6 +138,18 @@ int dg_apply_helmholtz(const dg_op_desc* desc, dg_dtype dtype, double mass_facto
  */
 int dg_apply_projection(const dg_op_desc* desc, dg_dtype dtype, const void* u, const void* tau_d,
                         const void* tau_c, void* y, void* hip_stream);
+
+/*
+ * Pressure gradient g_h with central flux (Sec. 3.2, weak form of g_h), the
+ * pressure term of the projection step's right-hand side without its
+ * dt/gamma_0 factor:
+ *   y_j,i = -(d_j phi_i, p)_K + sum over the faces normal to e_j of
+ *           n_j (phi_i, 1/2 (p- + p+))
+ * On the periodic mesh it is minus the transpose of dg_apply_divergence.
+ *   p: [N_el][n^3], y: [3][N_el][n^3] of `dtype`; y must not overlap p.
+ *   Uses n_q (default k+1).
+ */
+int dg_apply_gradient(const dg_op_desc* desc, dg_dtype dtype, const void* p, void* y, void* hip_stream);
 
 /*
  * Velocity divergence d_h with central flux (Sec. 3.2, weak form of d_h), the

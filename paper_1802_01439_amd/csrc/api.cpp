@@ -445,6 +445,20 @@ int dg_apply_divergence(const dg_op_desc* desc, dg_dtype dtype, const void* u, v
   return ok();
 }
 
+int dg_apply_gradient(const dg_op_desc* desc, dg_dtype dtype, const void* p, void* y, void* hip_stream) {
+  int rc = validate_desc(desc);
+  if (rc) return rc;
+  if (dtype != DG_F64 && dtype != DG_F32) return fail(DG_ERR_INVALID_ARG, "dtype must be DG_F64 or DG_F32");
+  if (!p || !y) return fail(DG_ERR_INVALID_ARG, "p/y is NULL");
+  const size_t es = dtype == DG_F64 ? 8 : 4;
+  const size_t np = (size_t)num_elements(desc) * dofs_per_element(desc) * es;
+  if (overlaps(p, np, y, 3 * np)) return fail(DG_ERR_ALIAS, "y overlaps p");
+  DivPlan P = make_div_plan(desc);
+  hipError_t e = launch_gradient(P, dtype == DG_F32, p, y, (hipStream_t)hip_stream);
+  if (e != hipSuccess) return hip_fail(e, "gradient kernel launch");
+  return ok();
+}
+
 int dg_apply_inverse_mass(const dg_op_desc* desc, dg_dtype dtype, const void* src, void* dst,
                           void* hip_stream) {
   int rc = validate_desc(desc);

@@ -54,6 +54,8 @@ struct DivPlan {
 };
 
 hipError_t launch_divergence(const DivPlan& P, bool f32, const void* u, void* b, hipStream_t s);
+// pressure gradient: the divergence's 1D tables, G = -B^T
+hipError_t launch_gradient(const DivPlan& P, bool f32, const void* p, void* y, hipStream_t s);
 
 // Projection-step operator (mass + divergence and continuity penalties):
 // 1D tables on [0,1] with k+1 Gauss points and the cell scalings.

@@ -25,7 +25,7 @@ DG_PC_JACOBI_F64, DG_PC_CHEB_F32 = 0, 1
 DG_OP_HELMHOLTZ, DG_OP_PROJECTION = 0, 1
 
 EXPORTS = ("dg_apply_laplace", "dg_apply_convective", "dg_vjp_convective", "dg_apply_divergence",
-           "dg_apply_inverse_mass", "dg_apply_helmholtz", "dg_apply_projection", "dg_cg_solve", "dg_mass_pcg_solve", "dg_laplace_diagonal", "dg_lgl_nodes", "dg_error_string", "dg_last_error")
+           "dg_apply_inverse_mass", "dg_apply_helmholtz", "dg_apply_projection", "dg_apply_gradient", "dg_cg_solve", "dg_mass_pcg_solve", "dg_laplace_diagonal", "dg_lgl_nodes", "dg_error_string", "dg_last_error")
 
 
 class OpDesc(ctypes.Structure):
@@ -75,6 +75,7 @@ def lib():
         L.dg_apply_inverse_mass.argtypes = [pd, ctypes.c_int, vp, vp, vp]
         L.dg_apply_helmholtz.argtypes = [pd, ctypes.c_int, ctypes.c_double, vp, vp, vp]
         L.dg_apply_projection.argtypes = [pd, ctypes.c_int, vp, vp, vp, vp, vp]
+        L.dg_apply_gradient.argtypes = [pd, ctypes.c_int, vp, vp, vp]
         L.dg_cg_solve.argtypes = [pd, ctypes.POINTER(CgOpts), vp, vp, ctypes.POINTER(CgReport), vp]
         L.dg_mass_pcg_solve.argtypes = [pd, ctypes.c_int32, ctypes.c_double, vp, vp, vp, vp, ctypes.c_double,
                                          ctypes.c_int32, ctypes.POINTER(CgReport), vp]
@@ -85,7 +86,7 @@ def lib():
         L.dg_last_error.argtypes = []
         L.dg_last_error.restype = ctypes.c_char_p
         for name in ("dg_apply_laplace", "dg_apply_convective", "dg_vjp_convective", "dg_apply_divergence",
-                     "dg_apply_inverse_mass", "dg_apply_helmholtz", "dg_apply_projection", "dg_cg_solve", "dg_mass_pcg_solve", "dg_laplace_diagonal", "dg_lgl_nodes"):
+                     "dg_apply_inverse_mass", "dg_apply_helmholtz", "dg_apply_projection", "dg_apply_gradient", "dg_cg_solve", "dg_mass_pcg_solve", "dg_laplace_diagonal", "dg_lgl_nodes"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -203,6 +204,21 @@ def apply_divergence(desc, u, out=None):
     _check_tensor(out, "out", (_nel(desc), n3))
     _check(lib().dg_apply_divergence(ctypes.byref(desc), _dtype_code(u), ctypes.c_void_p(u.data_ptr()),
                                      ctypes.c_void_p(out.data_ptr()), _stream(u)))
+    return out
+
+
+def apply_gradient(desc, p, out=None):
+    """Central-flux pressure gradient g_h(phi_i e_j, p); p: [N_el, n^3] -> [3, N_el, n^3]."""
+    torch = _torch()
+    n3 = (desc.degree + 1) ** 3
+    _check_tensor(p, "p", (_nel(desc), n3))
+    if out is None:
+        out = torch.empty((3, _nel(desc), n3), dtype=p.dtype, device=p.device)
+    _check_tensor(out, "out", (3, _nel(desc), n3))
+    if out.dtype != p.dtype:
+        raise TypeError("out must have the dtype of p")
+    _check(lib().dg_apply_gradient(ctypes.byref(desc), _dtype_code(p), ctypes.c_void_p(p.data_ptr()),
+                                   ctypes.c_void_p(out.data_ptr()), _stream(p)))
     return out
 
 
