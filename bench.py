@@ -174,7 +174,7 @@ def cpu_baseline(args):
                        + ", ".join(parts) + ")")}
 
 
-def extras(torch, dgmf, inputs, dev, args, which=("vjp", "cg", "mass", "proj", "mpcg")):
+def extras(torch, dgmf, inputs, dev, args, which=("vjp", "cg", "mass", "proj", "mpcg", "grad")):
     out = {}
     # inverse mass (element-local, memory bound) and the projection-step
     # operator (M + A_D + A_C, three components, seeded per-element penalty
@@ -182,6 +182,8 @@ def extras(torch, dgmf, inputs, dev, args, which=("vjp", "cg", "mass", "proj", "
     if "mass" in which:
         out["inverse_mass_sweep"] = _sweep_extra(torch, dgmf, dev, args, 1, 102, lambda d, x, y, tau:
                                                  dgmf.apply_inverse_mass(d, x, y))
+    if "grad" in which:
+        out["gradient_sweep"] = _grad_sweep(torch, dgmf, dev, args)
     if "proj" in which:
         out["projection_sweep"] = _sweep_extra(torch, dgmf, dev, args, 3, 103, lambda d, x, y, tau:
                                                dgmf.apply_projection(d, x, tau[0], tau[1], y))
@@ -296,6 +298,41 @@ def mass_pcg_extra(torch, dgmf, inputs, dev, k=5, N=16):
     return res
 
 
+def _grad_sweep(torch, dgmf, dev, args):
+    """Pressure gradient on the degree-sweep meshes, seeded U[-1,1] pressure;
+    4 input/output pairs in rotation.  Algorithmic bytes: the scalar read
+    once, three components written once (4 values per pressure DoF)."""
+    res = {}
+    R = 4
+    for k in range(args.kmin, args.kmax + 1):
+        N = sweep_mesh(k)
+        d = dgmf.make_desc(k, N)
+        g = torch.Generator(device=dev)
+        g.manual_seed(104 + 10 * k)
+        base = torch.rand((N ** 3, (k + 1) ** 3), generator=g, dtype=torch.float64, device=dev) * 2 - 1
+        for dtype, tdt in (("f64", torch.float64), ("f32", torch.float32)):
+            xs = [base.to(tdt) for _ in range(R)]
+            ys = [torch.empty((3,) + tuple(base.shape), dtype=tdt, device=dev) for _ in range(R)]
+            for i in range(R):
+                dgmf.apply_gradient(d, xs[i], ys[i])
+            torch.cuda.synchronize()
+            s0, e0 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            reps = 5 * R
+            s0.record()
+            for i in range(reps):
+                dgmf.apply_gradient(d, xs[i % R], ys[i % R])
+            e0.record()
+            torch.cuda.synchronize()
+            t = s0.elapsed_time(e0) / 1e3 / reps
+            n = xs[0].numel()
+            nbytes = 4 * (8 if dtype == "f64" else 4) * n
+            res[f"k{k}_{dtype}"] = {"us": t * 1e6, "dofs_per_s": n / t,
+                                    "hbm_frac": nbytes / t / (HBM_PEAK_GBS * 1e9)}
+            del xs, ys
+        del base
+    return res
+
+
 def _sweep_extra(torch, dgmf, dev, args, comps, seed, apply):
     """Time one element-local operator over the degree-sweep meshes.  4 input/
     output pairs in rotation, so that the 256 MB Infinity Cache does not hold
@@ -355,7 +392,7 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--sweep-out", default="")
     ap.add_argument("--extras-only", default="",
-                    help="diagnostic: run only these extras (vjp,cg,mass,proj,mpcg), print them as one JSON line, no sweep")
+                    help="diagnostic: run only these extras (vjp,cg,mass,proj,mpcg,grad), print them as one JSON line, no sweep")
     ap.add_argument("--calib-copy", type=int, default=0,
                     help="also run one plain device copy of this many bytes (counter calibration)")
     args = ap.parse_args()
