@@ -60,7 +60,7 @@ hipError_t cg_update_p_cheb(const float* z, double* p, const double* st, long lo
 
 // inverse-mass-preconditioned CG with device-side scalars (same state layout)
 hipError_t mpcg_start(const double* partial, double* st, hipStream_t s);
-hipError_t mpcg_beta(const double* rr_partial, const double* rz_partial, double* st, hipStream_t s);
+hipError_t mpcg_beta(const double* rr_partial, const double* rz_partial, int nblocks, double* st, hipStream_t s);
 hipError_t mpcg_xpby(double* p, const double* z, const double* st, long long n, hipStream_t s);
 
 }  // namespace dgmf

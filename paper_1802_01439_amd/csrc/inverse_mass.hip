@@ -17,6 +17,7 @@
 // from LDS.  3 barriers.  Because every block is read completely before any
 // of it is written, src == dst (in place) is allowed.
 #include "api_internal.h"
+#include "cg_kernels.h"
 #include "common.h"
 #include "laplace_kernels.h"
 #include "ops.h"
@@ -98,6 +99,116 @@ inverse_mass_kernel(const T* src, T* dst, long long nblocks, const InvMassTab<N,
   }
 }
 
+// One step of the inverse-mass-preconditioned CG on element blocks (FP64):
+// x += alpha p and r -= alpha q (alpha from the solver state; nothing is
+// written while it is 0), z = M^-1 r, and the block sums of r.r and r.z into
+// partial[blockIdx.x] and partial[gridDim.x + blockIdx.x].  Each thread keeps
+// its updated r column in registers for r.z.
+template <int N>
+__global__ void __launch_bounds__(LapCfgB<N>::THREADS)
+pcg_precond_kernel(double* __restrict__ x, double* __restrict__ r, const double* __restrict__ p,
+                   const double* __restrict__ q, double* __restrict__ z, const double* __restrict__ st,
+                   long long nblocks, const InvMassTab<N, double>* __restrict__ tab, double* __restrict__ partial) {
+  using C = LapCfgB<N>;
+  constexpr int N2 = N * N, N3 = N * N * N, E = C::E, ES = C::ES, PX = C::PX, PY = C::PY;
+  __shared__ double U[E * ES];
+  __shared__ double red[2][C::THREADS];
+  const int tid = threadIdx.x;
+  const int le = tid / N2, pp = tid - le * N2;
+  const int p0 = pp % N, p1 = pp / N;
+  const long long blk = (long long)blockIdx.x * E + le;
+  const bool active = blk < nblocks;
+  double* Ue = U + le * ES;
+  double rc[N], y[N];
+  double rr = 0, rz = 0;
+  if (active) {
+    const double alpha = st[kAlpha];
+    const size_t o = blk * N3 + p0 + N * p1;
+#pragma unroll
+    for (int c = 0; c < N; ++c) rc[c] = r[o + N2 * c];
+    if (alpha != 0.0) {
+#pragma unroll
+      for (int c = 0; c < N; ++c) {
+        x[o + N2 * c] += alpha * p[o + N2 * c];
+        rc[c] -= alpha * q[o + N2 * c];
+        r[o + N2 * c] = rc[c];
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < N; ++c) rr = fmadd(rc[c], rc[c], rr);
+    const auto& t = *fresh(tab);
+    mv<N, double>(t.A, rc, y);
+    const int base = p0 + PX * p1;
+#pragma unroll
+    for (int c = 0; c < N; ++c) Ue[base + PY * c] = y[c];
+  }
+  __syncthreads();
+  if (active) {
+    const auto& t = *fresh(tab);
+    const int base = p0 + PY * p1;
+    double v[N];
+#pragma unroll
+    for (int b = 0; b < N; ++b) v[b] = Ue[base + PX * b];
+    mv<N, double>(t.A, v, y);
+#pragma unroll
+    for (int b = 0; b < N; ++b) Ue[base + PX * b] = y[b];
+  }
+  __syncthreads();
+  if (active) {
+    const auto& t = *fresh(tab);
+    const int base = PX * p0 + PY * p1;
+    double v[N];
+#pragma unroll
+    for (int a = 0; a < N; ++a) v[a] = Ue[base + a];
+    mv<N, double>(t.A, v, y);
+#pragma unroll
+    for (int a = 0; a < N; ++a) Ue[base + a] = t.scale * y[a];
+  }
+  __syncthreads();
+  if (active) {
+    double* g = z + blk * N3 + p0 + N * p1;
+    const int base = p0 + PX * p1;
+#pragma unroll
+    for (int c = 0; c < N; ++c) {
+      const double zc = Ue[base + PY * c];
+      g[N2 * c] = zc;
+      rz = fmadd(rc[c], zc, rz);
+    }
+  }
+  red[0][tid] = rr;
+  red[1][tid] = rz;
+  __syncthreads();
+  if (tid == 0) {
+    double a = 0, b = 0;
+    for (int i = 0; i < C::THREADS; ++i) {
+      a += red[0][i];
+      b += red[1][i];
+    }
+    partial[blockIdx.x] = a;
+    partial[gridDim.x + blockIdx.x] = b;
+  }
+}
+
+template <int N>
+hipError_t launch_pcg_n(const std::vector<double>& Minv, double scale, long long nblocks, double* x, double* r,
+                        const double* p, const double* q, double* z, const double* st, double* partial,
+                        hipStream_t s) {
+  InvMassTab<N, double> t;
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j) t.A[i][j] = Minv[i * N + j];
+  t.scale = scale;
+  hipError_t err;
+  const InvMassTab<N, double>* dt = device_table_of("inverse_mass", t, &err);
+  if (!dt) return err;
+  using C = LapCfgB<N>;
+  const long long grid = (nblocks + C::E - 1) / C::E;
+  if (grid > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+  if (grid == 0) return hipSuccess;
+  hipLaunchKernelGGL((pcg_precond_kernel<N>), dim3((unsigned)grid), dim3(C::THREADS), 0, s, x, r, p, q, z, st,
+                     nblocks, dt, partial);
+  return hipGetLastError();
+}
+
 template <int N, typename T>
 hipError_t launch_n(const std::vector<double>& Minv, double scale, long long nblocks, const void* src, void* dst,
                     hipStream_t s) {
@@ -136,7 +247,48 @@ hipError_t launch_t(int k, const std::vector<double>& Minv, double scale, long l
   }
 }
 
+template <int N>
+long long pcg_grid_n(long long nblocks) {
+  return (nblocks + LapCfgB<N>::E - 1) / LapCfgB<N>::E;
+}
+
 }  // namespace
+
+long long pcg_precond_grid(int k, long long nblocks) {
+  switch (k) {
+    case 1: return pcg_grid_n<2>(nblocks);
+    case 2: return pcg_grid_n<3>(nblocks);
+    case 3: return pcg_grid_n<4>(nblocks);
+    case 4: return pcg_grid_n<5>(nblocks);
+    case 5: return pcg_grid_n<6>(nblocks);
+    case 6: return pcg_grid_n<7>(nblocks);
+    case 7: return pcg_grid_n<8>(nblocks);
+    case 8: return pcg_grid_n<9>(nblocks);
+    case 9: return pcg_grid_n<10>(nblocks);
+    case 10: return pcg_grid_n<11>(nblocks);
+    case 11: return pcg_grid_n<12>(nblocks);
+    default: return 0;
+  }
+}
+
+hipError_t launch_pcg_precond(int k, const std::vector<double>& Minv, double scale, long long nblocks, double* x,
+                              double* r, const double* p, const double* q, double* z, const double* st,
+                              double* partial, hipStream_t s) {
+  switch (k) {
+    case 1: return launch_pcg_n<2>(Minv, scale, nblocks, x, r, p, q, z, st, partial, s);
+    case 2: return launch_pcg_n<3>(Minv, scale, nblocks, x, r, p, q, z, st, partial, s);
+    case 3: return launch_pcg_n<4>(Minv, scale, nblocks, x, r, p, q, z, st, partial, s);
+    case 4: return launch_pcg_n<5>(Minv, scale, nblocks, x, r, p, q, z, st, partial, s);
+    case 5: return launch_pcg_n<6>(Minv, scale, nblocks, x, r, p, q, z, st, partial, s);
+    case 6: return launch_pcg_n<7>(Minv, scale, nblocks, x, r, p, q, z, st, partial, s);
+    case 7: return launch_pcg_n<8>(Minv, scale, nblocks, x, r, p, q, z, st, partial, s);
+    case 8: return launch_pcg_n<9>(Minv, scale, nblocks, x, r, p, q, z, st, partial, s);
+    case 9: return launch_pcg_n<10>(Minv, scale, nblocks, x, r, p, q, z, st, partial, s);
+    case 10: return launch_pcg_n<11>(Minv, scale, nblocks, x, r, p, q, z, st, partial, s);
+    case 11: return launch_pcg_n<12>(Minv, scale, nblocks, x, r, p, q, z, st, partial, s);
+    default: return hipErrorInvalidValue;
+  }
+}
 
 hipError_t launch_inverse_mass(int k, const std::vector<double>& Minv, double scale, long long nblocks, bool f32,
                                const void* src, void* dst, hipStream_t s) {

@@ -1,7 +1,8 @@
 // Scalar steps of the inverse-mass-preconditioned CG with its scalars kept on
 // the device (the state array of the CG solver: kRZ, kBeta, kRN2, kDone,
 // kStatus, kIter, kTol2, kMaxIt), so that iterations run in batches between
-// host reads.  The x/r update and p.Ap come from the CG vector kernels.
+// host reads.  p.Ap and alpha come from the CG kernels, the x/r update with
+// z = M^-1 r and the sums r.r, r.z from the fused inverse mass kernel.
 #include "cg_kernels.h"
 
 namespace dgmf {
@@ -87,8 +88,8 @@ hipError_t mpcg_start(const double* partial, double* st, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t mpcg_beta(const double* rr_partial, const double* rz_partial, double* st, hipStream_t s) {
-  hipLaunchKernelGGL(k_mp_beta, dim3(1), dim3(kThreads), 0, s, rr_partial, rz_partial, kCgBlocks, st);
+hipError_t mpcg_beta(const double* rr_partial, const double* rz_partial, int nblocks, double* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_mp_beta, dim3(1), dim3(kThreads), 0, s, rr_partial, rz_partial, nblocks, st);
   return hipGetLastError();
 }
 

@@ -54,6 +54,12 @@ struct DivPlan {
 };
 
 hipError_t launch_divergence(const DivPlan& P, bool f32, const void* u, void* b, hipStream_t s);
+// inverse-mass-preconditioned CG step on element blocks (FP64): x += alpha p,
+// r -= alpha q, z = M^-1 r, block sums of r.r and r.z (2 * grid doubles)
+long long pcg_precond_grid(int k, long long nblocks);
+hipError_t launch_pcg_precond(int k, const std::vector<double>& Minv, double scale, long long nblocks, double* x,
+                              double* r, const double* p, const double* q, double* z, const double* st,
+                              double* partial, hipStream_t s);
 // pressure gradient: the divergence's 1D tables, G = -B^T
 hipError_t launch_gradient(const DivPlan& P, bool f32, const void* p, void* y, hipStream_t s);
 
