@@ -488,7 +488,8 @@ def main():
     del cases
     torch.cuda.empty_cache()
     if not args.no_extras:
-        print("[bench] extras: VJP and CG", file=sys.stderr, flush=True)
+        print("[bench] extras: inverse mass, gradient, projection, mass-preconditioned solves, VJP, CG",
+              file=sys.stderr, flush=True)
         res["extras"] = extras(torch, dgmf, inputs, dev, args)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
