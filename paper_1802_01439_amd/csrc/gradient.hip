@@ -17,7 +17,8 @@
 //   X   Rx = Gx p;  Ry <- Mx Ry;  y_z = c_z Mx Rz (stored)
 //   Y   Rx <- My Rx
 //   Z   y_x = c_x Mz Rx, y_y = c_y Mz Ry (stored)
-// E elements per workgroup, one pencil per thread per phase, LDS between.
+// E elements per workgroup, one pencil per thread per phase, LDS between
+// (three arrays of E n^3 values: Rx takes the place of p in the X phase).
 #include "api_internal.h"
 #include "common.h"
 #include "ops.h"
@@ -56,19 +57,16 @@ gradient_kernel(const T* __restrict__ p, T* __restrict__ y, MeshArgs mesh, const
                 T cx, T cy, T cz) {
   using C = GradCfg<N>;
   constexpr int N2 = C::N2, N3 = C::N3, E = C::E;
+  // RX overwrites P pencil by pencil in the X phase (each thread reads its
+  // whole x pencil of P before writing it), so three arrays suffice
   __shared__ T P[E * N3];
-  __shared__ T RX[E * N3];
   __shared__ T RY[E * N3];
   __shared__ T RZ[E * N3];
+  T* RX = P;
   const int tid = threadIdx.x;
   const int e0 = xcd_remap(blockIdx.x, gridDim.x) * E;
   const int ne = min(E, mesh.n_el - e0);
   const size_t cs = (size_t)mesh.n_el * N3;
-  {
-    const T* g = p + (size_t)e0 * N3;
-    for (int i = tid; i < ne * N3; i += C::THREADS) P[i] = g[i];
-  }
-  __syncthreads();
   const int le = tid / N2, q = tid - le * N2;
   const int q0 = q % N, q1 = q / N;
   const bool active = le < ne;
@@ -77,14 +75,18 @@ gradient_kernel(const T* __restrict__ p, T* __restrict__ y, MeshArgs mesh, const
   const int ez = active ? e / (mesh.nx * mesh.ny) : 0;
   const int off = le * N3;
   T in[N], out[N];
-  // Z: Rz = Gz p, neighbour layers along z
+  // Z: own z column of p from global memory (consecutive threads, consecutive
+  // addresses) into registers and LDS; Rz = Gz p, neighbour layers along z
   if (active) {
     const auto& t = *fresh(tab);
     const int base = q0 + N * q1;
+    const T* gc = p + (size_t)e * N3 + base;
     const T* gl = p + (size_t)neighbor(mesh, ex, ey, ez, 2, 0) * N3 + base;
     const T* gr = p + (size_t)neighbor(mesh, ex, ey, ez, 2, 1) * N3 + base;
 #pragma unroll
-    for (int c = 0; c < N; ++c) in[c] = P[off + base + N2 * c];
+    for (int c = 0; c < N; ++c) in[c] = gc[N2 * c];
+#pragma unroll
+    for (int c = 0; c < N; ++c) P[off + base + N2 * c] = in[c];
     gmv<N, T>(t.G, in, out);
     out[N - 1] += T(0.5) * gr[0];
     out[0] -= T(0.5) * gl[N2 * (N - 1)];
