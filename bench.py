@@ -183,7 +183,8 @@ def extras(torch, dgmf, inputs, dev, args, which=("vjp", "cg", "mass", "proj", "
         out["inverse_mass_sweep"] = _sweep_extra(torch, dgmf, dev, args, 1, 102, lambda d, x, y, tau:
                                                  dgmf.apply_inverse_mass(d, x, y))
     if "grad" in which:
-        out["gradient_sweep"] = _grad_sweep(torch, dgmf, dev, args)
+        out["gradient_sweep"] = _grad_sweep(torch, dgmf, dev, args, "gradient")
+        out["divergence_sweep"] = _grad_sweep(torch, dgmf, dev, args, "divergence")
     if "proj" in which:
         out["projection_sweep"] = _sweep_extra(torch, dgmf, dev, args, 3, 103, lambda d, x, y, tau:
                                                dgmf.apply_projection(d, x, tau[0], tau[1], y))
@@ -298,33 +299,38 @@ def mass_pcg_extra(torch, dgmf, inputs, dev, k=5, N=16):
     return res
 
 
-def _grad_sweep(torch, dgmf, dev, args):
-    """Pressure gradient on the degree-sweep meshes, seeded U[-1,1] pressure;
-    4 input/output pairs in rotation.  Algorithmic bytes: the scalar read
-    once, three components written once (4 values per pressure DoF)."""
+def _grad_sweep(torch, dgmf, dev, args, op):
+    """Pressure gradient (scalar -> 3 components) or velocity divergence
+    (3 components -> scalar) on the degree-sweep meshes, seeded U[-1,1] input;
+    4 input/output pairs in rotation.  Algorithmic bytes: input read once,
+    output written once, 4 values per pressure DoF either way."""
     res = {}
     R = 4
+    grad = op == "gradient"
     for k in range(args.kmin, args.kmax + 1):
         N = sweep_mesh(k)
         d = dgmf.make_desc(k, N)
         g = torch.Generator(device=dev)
-        g.manual_seed(104 + 10 * k)
-        base = torch.rand((N ** 3, (k + 1) ** 3), generator=g, dtype=torch.float64, device=dev) * 2 - 1
+        g.manual_seed((104 if grad else 105) + 10 * k)
+        scalar = (N ** 3, (k + 1) ** 3)
+        vector = (3,) + scalar
+        base = torch.rand(scalar if grad else vector, generator=g, dtype=torch.float64, device=dev) * 2 - 1
         for dtype, tdt in (("f64", torch.float64), ("f32", torch.float32)):
             xs = [base.to(tdt) for _ in range(R)]
-            ys = [torch.empty((3,) + tuple(base.shape), dtype=tdt, device=dev) for _ in range(R)]
+            ys = [torch.empty(vector if grad else scalar, dtype=tdt, device=dev) for _ in range(R)]
+            call = dgmf.apply_gradient if grad else dgmf.apply_divergence
             for i in range(R):
-                dgmf.apply_gradient(d, xs[i], ys[i])
+                call(d, xs[i], ys[i])
             torch.cuda.synchronize()
             s0, e0 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             reps = 5 * R
             s0.record()
             for i in range(reps):
-                dgmf.apply_gradient(d, xs[i % R], ys[i % R])
+                call(d, xs[i % R], ys[i % R])
             e0.record()
             torch.cuda.synchronize()
             t = s0.elapsed_time(e0) / 1e3 / reps
-            n = xs[0].numel()
+            n = N ** 3 * (k + 1) ** 3
             nbytes = 4 * (8 if dtype == "f64" else 4) * n
             res[f"k{k}_{dtype}"] = {"us": t * 1e6, "dofs_per_s": n / t,
                                     "hbm_frac": nbytes / t / (HBM_PEAK_GBS * 1e9)}

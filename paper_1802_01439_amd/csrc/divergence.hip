@@ -10,8 +10,9 @@
 // with B the 1D operator on [0,1]: B[i][j] = -sum_q w_q l_i'(z_q) l_j(z_q) plus
 // the own-side central-flux terms 1/2 l_i(1) l_j(1) - 1/2 l_i(0) l_j(0), and
 // the neighbour coupling 1/2 uR(0) at the right end, -1/2 uL(1) at the left.
-// Same GPU mapping as the Laplace kernel: E elements per workgroup, one pencil
-// per thread per phase, LDS between phases.
+// GPU mapping: E elements per workgroup, one pencil per thread per phase,
+// LDS between phases; each thread loads its own z columns straight into
+// registers, and four LDS arrays of E n^3 values carry the rest.
 #include "api_internal.h"
 #include "common.h"
 #include "ops.h"
@@ -36,8 +37,8 @@ struct DivCfg {
   static constexpr int THREADS = E * N2;
 };
 
-template <int N, typename T>
-__device__ __forceinline__ void dmv(const T (&A)[N][N], const T* x, T* y) {
+template <int N, typename T, typename Mat>
+__device__ __forceinline__ void dmv(const Mat& A, const T* x, T* y) {
 #pragma unroll
   for (int i = 0; i < N; ++i) {
     T s = A[i][0] * x[0];
@@ -51,37 +52,42 @@ template <int N, typename T>
 __global__ void __launch_bounds__(DivCfg<N>::THREADS)
 divergence_kernel(const T* __restrict__ u, T* __restrict__ b, MeshArgs mesh,
                   const DivTab<N, T>* __restrict__ tab, DivScal<T> sc) {
-  const DivTab<N, T>& t = *tab;
   using C = DivCfg<N>;
   constexpr int N2 = C::N2, N3 = C::N3, E = C::E;
-  __shared__ T U[3][E * N3];
+  // u_x and u_y columns; P = c_x Bx u_x later takes the place of u_x and
+  // c_y Mx Q the place of Q (pencil by pencil: each thread reads its whole
+  // pencil before writing it); u_z stays in registers
+  __shared__ T UX[E * N3];
+  __shared__ T UY[E * N3];
   __shared__ T B1[E * N3];
   __shared__ T B2[E * N3];
-  __shared__ T B3[E * N3];
   const int tid = threadIdx.x;
   const int e0 = xcd_remap(blockIdx.x, gridDim.x) * E;
   const int ne = min(E, mesh.n_el - e0);
   const size_t cs = (size_t)mesh.n_el * N3;
-  for (int d = 0; d < 3; ++d) {
-    const T* g = u + d * cs + (size_t)e0 * N3;
-    for (int i = tid; i < ne * N3; i += C::THREADS) U[d][i] = g[i];
-  }
-  __syncthreads();
   const int le = tid / N2, p = tid - le * N2;
   const int p0 = p % N, p1 = p / N;
   const bool active = le < ne;
   const int e = e0 + le;
-  const int ex = e % mesh.nx, ey = (e / mesh.nx) % mesh.ny, ez = e / (mesh.nx * mesh.ny);
+  const int ex = active ? e % mesh.nx : 0, ey = active ? (e / mesh.nx) % mesh.ny : 0;
+  const int ez = active ? e / (mesh.nx * mesh.ny) : 0;
   T in[N], out[N], tmp[N];
   const int off = le * N3;
 
-  // Z: R = Bz u_z
+  // Z: own z columns of the three components from global memory (consecutive
+  // threads, consecutive addresses); R = Bz u_z
   if (active) {
+    const auto& t = *fresh(tab);
     const int base = p0 + N * p1;
+    const T* gc = u + (size_t)e * N3 + base;
+#pragma unroll
+    for (int c = 0; c < N; ++c) {
+      UX[off + base + N2 * c] = gc[N2 * c];
+      UY[off + base + N2 * c] = gc[cs + N2 * c];
+      in[c] = gc[2 * cs + N2 * c];
+    }
     const T* gl = u + 2 * cs + (size_t)neighbor(mesh, ex, ey, ez, 2, 0) * N3 + base;
     const T* gr = u + 2 * cs + (size_t)neighbor(mesh, ex, ey, ez, 2, 1) * N3 + base;
-#pragma unroll
-    for (int c = 0; c < N; ++c) in[c] = U[2][off + base + N2 * c];
     dmv<N, T>(t.B, in, out);
     out[N - 1] += T(0.5) * gr[0];
     out[0] -= T(0.5) * gl[N2 * (N - 1)];
@@ -91,12 +97,13 @@ divergence_kernel(const T* __restrict__ u, T* __restrict__ b, MeshArgs mesh,
   __syncthreads();
   // Y: Q = By u_y; R <- My R
   if (active) {
+    const auto& t = *fresh(tab);
     const int base = p0 + N2 * p1;
     const T* gl = u + 1 * cs + (size_t)neighbor(mesh, ex, ey, ez, 1, 0) * N3 + base;
     const T* gr = u + 1 * cs + (size_t)neighbor(mesh, ex, ey, ez, 1, 1) * N3 + base;
 #pragma unroll
     for (int j = 0; j < N; ++j) {
-      in[j] = U[1][off + base + N * j];
+      in[j] = UY[off + base + N * j];
       tmp[j] = B1[off + base + N * j];
     }
     dmv<N, T>(t.B, in, out);
@@ -109,24 +116,26 @@ divergence_kernel(const T* __restrict__ u, T* __restrict__ b, MeshArgs mesh,
     for (int j = 0; j < N; ++j) B1[off + base + N * j] = out[j];
   }
   __syncthreads();
-  // X: P = Bx u_x; Q <- Mx Q; R <- Mx R
+  // X: UX <- c_x Bx u_x; B2 <- c_y Mx Q; B1 <- c_z Mx R
   if (active) {
+    const auto& t = *fresh(tab);
     const int base = N * p0 + N2 * p1;
     const T* gl = u + (size_t)neighbor(mesh, ex, ey, ez, 0, 0) * N3 + base;
     const T* gr = u + (size_t)neighbor(mesh, ex, ey, ez, 0, 1) * N3 + base;
 #pragma unroll
-    for (int a = 0; a < N; ++a) in[a] = U[0][off + base + a];
+    for (int a = 0; a < N; ++a) in[a] = UX[off + base + a];
     dmv<N, T>(t.B, in, out);
     out[N - 1] += T(0.5) * gr[0];
     out[0] -= T(0.5) * gl[N - 1];
 #pragma unroll
-    for (int a = 0; a < N; ++a) tmp[a] = B2[off + base + a];
-#pragma unroll
-    for (int a = 0; a < N; ++a) B2[off + base + a] = sc.c[0] * out[a];
+    for (int a = 0; a < N; ++a) {
+      UX[off + base + a] = sc.c[0] * out[a];
+      tmp[a] = B2[off + base + a];
+    }
     dmv<N, T>(t.M, tmp, out);
 #pragma unroll
     for (int a = 0; a < N; ++a) {
-      B3[off + base + a] = sc.c[1] * out[a];
+      B2[off + base + a] = sc.c[1] * out[a];
       tmp[a] = B1[off + base + a];
     }
     dmv<N, T>(t.M, tmp, out);
@@ -136,19 +145,21 @@ divergence_kernel(const T* __restrict__ u, T* __restrict__ b, MeshArgs mesh,
   __syncthreads();
   // Y again: S = My (c_x P) + c_y Q
   if (active) {
+    const auto& t = *fresh(tab);
     const int base = p0 + N2 * p1;
 #pragma unroll
-    for (int j = 0; j < N; ++j) tmp[j] = B2[off + base + N * j];
+    for (int j = 0; j < N; ++j) tmp[j] = UX[off + base + N * j];
     dmv<N, T>(t.M, tmp, out);
 #pragma unroll
-    for (int j = 0; j < N; ++j) B3[off + base + N * j] += out[j];
+    for (int j = 0; j < N; ++j) B2[off + base + N * j] += out[j];
   }
   __syncthreads();
   // Z again: b = Mz S + c_z R
   if (active) {
+    const auto& t = *fresh(tab);
     const int base = p0 + N * p1;
 #pragma unroll
-    for (int c = 0; c < N; ++c) tmp[c] = B3[off + base + N2 * c];
+    for (int c = 0; c < N; ++c) tmp[c] = B2[off + base + N2 * c];
     dmv<N, T>(t.M, tmp, out);
     T* g = b + (size_t)e * N3 + base;
 #pragma unroll
