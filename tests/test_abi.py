@@ -78,3 +78,34 @@ def test_host_diagonal_matches_oracle(k, n_el, pen, scale):
     ref = laplace_diagonal(k, msh, penalty_factor=pen, scale=scale)
     got = dgmf.laplace_diagonal(dgmf.make_desc(k, n_el, length, penalty_factor=pen, scale=scale))
     np.testing.assert_allclose(got, ref, rtol=1e-13)
+
+
+def test_validation_errors_of_the_widening_entry_points_without_gpu():
+    L = dgmf.lib()
+    vp = ctypes.c_void_p
+    fa, fb, fc, fd = 0x10000000, 0x20000000, 0x30000000, 0x40000000   # never dereferenced
+    d1 = dgmf.make_desc(3, 4)
+    d3 = dgmf.make_desc(3, 4, n_comp=3)
+    # projection operator: three components, n_q = k+1, no aliasing
+    assert L.dg_apply_projection(ctypes.byref(d1), 0, vp(fa), vp(fb), vp(fc), vp(fd), None) == dgmf.DG_ERR_INVALID_ARG
+    dq = dgmf.make_desc(3, 4, n_comp=3, n_q=6)
+    assert L.dg_apply_projection(ctypes.byref(dq), 0, vp(fa), vp(fb), vp(fc), vp(fd), None) == dgmf.DG_ERR_UNSUPPORTED
+    assert L.dg_apply_projection(ctypes.byref(d3), 0, vp(fa), vp(fb), None, vp(fd), None) == dgmf.DG_ERR_INVALID_ARG
+    assert L.dg_apply_projection(ctypes.byref(d3), 0, vp(fa), vp(fb), vp(fc), vp(fa + 8), None) == dgmf.DG_ERR_ALIAS
+    # gradient: y (3 components) must not overlap p
+    assert L.dg_apply_gradient(ctypes.byref(d1), 0, vp(fa), None, None) == dgmf.DG_ERR_INVALID_ARG
+    assert L.dg_apply_gradient(ctypes.byref(d1), 0, vp(fa + 8), vp(fa), None) == dgmf.DG_ERR_ALIAS
+    # Helmholtz and inverse mass
+    assert L.dg_apply_helmholtz(ctypes.byref(d1), 0, -1.0, vp(fa), vp(fb), None) == dgmf.DG_ERR_INVALID_ARG
+    assert L.dg_apply_inverse_mass(ctypes.byref(d1), 0, vp(fa), vp(fa + 8), None) == dgmf.DG_ERR_ALIAS
+    # mass-preconditioned CG
+    def solve(desc, op, mf, td, tc, b, x, rtol=1e-10, it=10):
+        return L.dg_mass_pcg_solve(ctypes.byref(desc), op, mf, td, tc, vp(b), vp(x), rtol, it, None, None)
+    assert solve(d1, 7, 1.0, None, None, fa, fb) == dgmf.DG_ERR_INVALID_ARG
+    assert solve(d1, dgmf.DG_OP_HELMHOLTZ, 0.0, None, None, fa, fb) == dgmf.DG_ERR_INVALID_ARG
+    assert solve(d1, dgmf.DG_OP_HELMHOLTZ, 1.0, None, None, fa, fb, rtol=0.0) == dgmf.DG_ERR_INVALID_ARG
+    assert solve(d1, dgmf.DG_OP_HELMHOLTZ, 1.0, None, None, fa, fb, it=-1) == dgmf.DG_ERR_INVALID_ARG
+    assert solve(d1, dgmf.DG_OP_PROJECTION, 0.0, vp(fc), vp(fd), fa, fb) == dgmf.DG_ERR_INVALID_ARG
+    assert solve(d3, dgmf.DG_OP_PROJECTION, 0.0, None, vp(fd), fa, fb) == dgmf.DG_ERR_INVALID_ARG
+    assert solve(d3, dgmf.DG_OP_PROJECTION, 0.0, vp(fc), vp(fd), fa, fa + 8) == dgmf.DG_ERR_ALIAS
+    assert solve(d1, dgmf.DG_OP_HELMHOLTZ, 1.0, None, None, fa, fa) == dgmf.DG_ERR_ALIAS
