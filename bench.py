@@ -171,7 +171,55 @@ def cpu_baseline(args):
             "sample": (f"oracle (float64, explicit 3D tables) FP64 applies on the first elements of each "
                        f"degree-sweep mesh, k={args.kmin}..{args.kmax}, Laplace and convective, at least "
                        f"{budget} s of oracle work each ({tot_dofs} DoFs in {tot_t:.1f} s; "
-                       + ", ".join(parts) + ")")}
+                       + ", ".join(parts) + ")"),
+            "rows": oracle_rows(args)}
+
+
+def oracle_rows(args, budget=0.15):
+    """The oracle beside the other measured rows: DoFs/s of its FP64 inverse
+    mass, gradient, divergence and projection operator on the first elements
+    of each degree-sweep mesh (at least `budget` s of work per row and
+    degree, one call at the least), for comparison with the GPU figures of the
+    same rows in `extras`."""
+    from oracle import mesh as M
+    from oracle.divergence import divergence_apply
+    from oracle.gradient import gradient_apply
+    from oracle.mass import inverse_mass_apply
+    from oracle.projection import projection_apply
+    from paper_1802_01439_amd import inputs
+    names = ("inverse_mass", "gradient", "divergence", "projection")
+    dofs = dict.fromkeys(names, 0)
+    secs = dict.fromkeys(names, 0.0)
+    for k in range(args.kmin, args.kmax + 1):
+        N = sweep_mesh(k)
+        msh = M.cube(N)
+        n3 = (k + 1) ** 3
+        ne = max(2, int(1e4 / n3))
+        nel = min(msh.N, 32 * ne)
+        full = np.zeros((3, msh.N, n3))
+        full[:, :nel] = inputs.uniform((3, nel, n3), seed=inputs.FIELD_SEED_BASE + 30 + k)
+        tau = np.full(msh.N, 1e-3)
+        for name in names:
+            done, t_k = 0, 0.0
+            while (t_k < budget or done == 0) and done + ne <= nel:
+                E = np.arange(done, done + ne)
+                t0 = time.perf_counter()
+                if name == "inverse_mass":
+                    inverse_mass_apply(full[0], k, msh, elems=E)
+                elif name == "gradient":
+                    gradient_apply(full[0], k, msh, elems=E)
+                elif name == "divergence":
+                    divergence_apply(full, k, msh, elems=E)
+                else:
+                    projection_apply(full, k, msh, tau, tau, elems=E)
+                t_k += time.perf_counter() - t0
+                done += ne
+            dofs[name] += done * n3 * (3 if name == "projection" else 1)
+            secs[name] += t_k
+        del full
+    return {name: {"dofs_per_s": dofs[name] / secs[name],
+                   "sample": f"k={args.kmin}..{args.kmax}, {dofs[name]} DoFs in {secs[name]:.1f} s"}
+            for name in names}
 
 
 def extras(torch, dgmf, inputs, dev, args, which=("vjp", "cg", "mass", "proj", "mpcg", "grad")):
