@@ -3,7 +3,8 @@
 // applied matrix-free at the cost of a diagonal scaling, which makes it the
 // preconditioner of both steps).  FP64 throughout.
 //
-// Per iteration: q = A p (projection or Helmholtz kernel), p.q and alpha;
+// Per iteration: q = A p (projection or Helmholtz kernel, with the partial
+// sums of p.q in its epilogue) and alpha;
 // one fused kernel for x += alpha p, r -= alpha q, z = M^-1 r and the sums
 // r.r, r.z (56 B/DoF instead of 80 for the three separate passes); the
 // convergence test and beta; p = z + beta p.
@@ -20,6 +21,7 @@
 
 #include "api_internal.h"
 #include "cg_kernels.h"
+#include "cg_laplace.h"
 #include "dgmf.h"
 #include "ops.h"
 
@@ -124,13 +126,21 @@ extern "C" int dg_mass_pcg_solve(const dg_op_desc* desc, int32_t op, double mass
   std::lock_guard<std::mutex> lock(g_mpcg_mutex);
   MassPcgWs& w = g_mpcg[dev];
   const long long pgrid = pcg_precond_grid(desc->degree, nblocks);
-  if (pgrid <= 0 || pgrid > (1LL << 30)) return fail(DG_ERR_INVALID_ARG, "mesh too large for the fused step");
-  if ((e = ensure(w, n, 2 * pgrid)) != hipSuccess) return hip_fail(e, "work vectors");
+  // workgroups of the operator launch, each writing one partial sum of p.q
+  const long long qgrid = op == DG_OP_PROJECTION ? projection_grid(PP) : cg_apply_grid(LP, false);
+  if (pgrid <= 0 || pgrid > (1LL << 30) || qgrid <= 0 || qgrid > (1LL << 30))
+    return fail(DG_ERR_INVALID_ARG, "mesh too large for the fused steps");
+  if ((e = ensure(w, n, std::max(2 * pgrid, qgrid))) != hipSuccess) return hip_fail(e, "work vectors");
   const std::vector<double> Minv = inverse_mass_1d(desc->degree);
   const double ivol = 1.0 / cell_volume(desc);
   auto apply = [&](const double* src, double* dst) {
     return op == DG_OP_PROJECTION ? launch_projection(PP, false, src, dst, tau_d, tau_c, s)
                                   : launch_laplace(LP, false, src, dst, s);
+  };
+  // q = A p with the partial sums of p.q
+  auto apply_dot = [&](const double* src, double* dst, double* partial) {
+    return op == DG_OP_PROJECTION ? launch_projection(PP, false, src, dst, tau_d, tau_c, s, partial)
+                                  : cg_apply_dot(LP, src, dst, partial, s);
   };
   auto precond = [&](const double* src, double* dst) {
     return launch_inverse_mass(desc->degree, Minv, ivol, nblocks, false, src, dst, s);
@@ -167,9 +177,8 @@ extern "C" int dg_mass_pcg_solve(const dg_op_desc* desc, int32_t op, double mass
         break;
       }
       for (int i = 0; i < batch; ++i) {
-        MPCG_CHECK(apply(w.p, w.q), "operator launch");
-        MPCG_CHECK(cg_dot(w.p, w.q, n, w.partial, s), "dot");
-        MPCG_CHECK(cg_fin_alpha(w.partial, kCgBlocks, w.st, s), "alpha");
+        MPCG_CHECK(apply_dot(w.p, w.q, w.partial), "operator launch");
+        MPCG_CHECK(cg_fin_alpha(w.partial, (int)qgrid, w.st, s), "alpha");
         MPCG_CHECK(launch_pcg_precond(desc->degree, Minv, ivol, nblocks, x, w.r, w.p, w.q, w.z, w.st, w.partial, s),
                    "update and inverse mass");
         MPCG_CHECK(mpcg_beta(w.partial, w.partial + pgrid, (int)pgrid, w.st, s), "beta");

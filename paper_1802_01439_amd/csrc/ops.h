@@ -71,8 +71,11 @@ struct ProjPlan {
   std::vector<double> S, Dg, M1, w;   // n x n, n x n, n x n, n
   double vol = 0, ih[3] = {0, 0, 0}, area[3] = {0, 0, 0};
 };
+// dot_partial (optional): one partial sum of u.y per workgroup,
+// projection_grid(P) of them
 hipError_t launch_projection(const ProjPlan& P, bool f32, const void* u, void* y, const void* tau_d,
-                             const void* tau_c, hipStream_t s);
+                             const void* tau_c, hipStream_t s, void* dot_partial = nullptr);
+long long projection_grid(const ProjPlan& P);
 
 // x = M^-1 b on nblocks consecutive element blocks: Minv = inverse of the 1D
 // mass on [0,1] (n x n row major), scale = 1/(h_x h_y h_z).

@@ -99,7 +99,8 @@ struct ProjCfg {
 template <int N, typename T>
 __global__ void __launch_bounds__(ProjCfg<N>::THREADS) __attribute__((amdgpu_waves_per_eu(N >= 9 ? 4 : 1, 8)))
 projection_kernel(const T* __restrict__ u, T* __restrict__ y, const T* __restrict__ tau_d,
-                  const T* __restrict__ tau_c, MeshArgs mesh, const ProjTab<N, T>* __restrict__ tab) {
+                  const T* __restrict__ tau_c, MeshArgs mesh, const ProjTab<N, T>* __restrict__ tab,
+                  T* __restrict__ dot) {
   using C = ProjCfg<N>;
   constexpr int N2 = C::N2, N3 = C::N3, E = C::E, PX = C::PX, PY = C::PY, ES = C::ES, PER = C::PER;
   __shared__ T lds[E * PER];
@@ -126,6 +127,7 @@ projection_kernel(const T* __restrict__ u, T* __restrict__ y, const T* __restric
     else { base = p0 + PX * p1; str = PY; }
   };
   const int zcol = p0 + PX * p1;   // this thread's z column (a, b) = (p0, p1)
+  T acc = 0;                       // this thread's part of u.y (dot only)
   // ---- P0: own z column of component j, its face values, the neighbours'
   //      facing layers of component j = d; S along z in registers
   if (active) {
@@ -292,6 +294,24 @@ projection_kernel(const T* __restrict__ u, T* __restrict__ y, const T* __restric
     T* g = y + j * cs + (size_t)e * N3 + p0 + N * p1;
 #pragma unroll
     for (int c = 0; c < N; ++c) g[N2 * c] = v[c];
+    if (dot) {   // u.y of this column (the input column again, from cache)
+      const T* gu = u + j * cs + (size_t)e * N3 + p0 + N * p1;
+      T sdot = 0;
+#pragma unroll
+      for (int c = 0; c < N; ++c) sdot = fmadd(gu[N2 * c], v[c], sdot);
+      acc = sdot;
+    }
+  }
+  // ---- optional: workgroup sum of u.y into dot[blockIdx.x] (fixed order)
+  if (dot) {
+    __syncthreads();
+    lds[tid] = acc;
+    __syncthreads();
+    if (tid == 0) {
+      T s = 0;
+      for (int i = 0; i < C::THREADS; ++i) s += lds[i];
+      dot[blockIdx.x] = s;
+    }
   }
 }
 
@@ -318,7 +338,8 @@ bool make_eo(const double* A, int sig, EOMat<N, T>& m) {
 }
 
 template <int N, typename T>
-hipError_t launch_n(const ProjPlan& P, const void* u, void* yv, const void* td, const void* tc, hipStream_t s) {
+hipError_t launch_n(const ProjPlan& P, const void* u, void* yv, const void* td, const void* tc, hipStream_t s,
+                    void* dot) {
   ProjTab<N, T> t{};
   double St[N * N], Dt[N * N];
   for (int i = 0; i < N; ++i) {
@@ -344,33 +365,58 @@ hipError_t launch_n(const ProjPlan& P, const void* u, void* yv, const void* td, 
   const long long grid = ((long long)P.mesh.n_el + C::E - 1) / C::E;
   if (grid > 0x7fffffffLL) return hipErrorInvalidConfiguration;
   hipLaunchKernelGGL((projection_kernel<N, T>), dim3((unsigned)grid), dim3(C::THREADS), 0, s, (const T*)u,
-                     (T*)yv, (const T*)td, (const T*)tc, P.mesh, dt);
+                     (T*)yv, (const T*)td, (const T*)tc, P.mesh, dt, (T*)dot);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_t(const ProjPlan& P, const void* u, void* y, const void* td, const void* tc, hipStream_t s) {
+hipError_t launch_t(const ProjPlan& P, const void* u, void* y, const void* td, const void* tc, hipStream_t s,
+                    void* dot) {
   switch (P.k) {
-    case 1: return launch_n<2, T>(P, u, y, td, tc, s);
-    case 2: return launch_n<3, T>(P, u, y, td, tc, s);
-    case 3: return launch_n<4, T>(P, u, y, td, tc, s);
-    case 4: return launch_n<5, T>(P, u, y, td, tc, s);
-    case 5: return launch_n<6, T>(P, u, y, td, tc, s);
-    case 6: return launch_n<7, T>(P, u, y, td, tc, s);
-    case 7: return launch_n<8, T>(P, u, y, td, tc, s);
-    case 8: return launch_n<9, T>(P, u, y, td, tc, s);
-    case 9: return launch_n<10, T>(P, u, y, td, tc, s);
-    case 10: return launch_n<11, T>(P, u, y, td, tc, s);
-    case 11: return launch_n<12, T>(P, u, y, td, tc, s);
+    case 1: return launch_n<2, T>(P, u, y, td, tc, s, dot);
+    case 2: return launch_n<3, T>(P, u, y, td, tc, s, dot);
+    case 3: return launch_n<4, T>(P, u, y, td, tc, s, dot);
+    case 4: return launch_n<5, T>(P, u, y, td, tc, s, dot);
+    case 5: return launch_n<6, T>(P, u, y, td, tc, s, dot);
+    case 6: return launch_n<7, T>(P, u, y, td, tc, s, dot);
+    case 7: return launch_n<8, T>(P, u, y, td, tc, s, dot);
+    case 8: return launch_n<9, T>(P, u, y, td, tc, s, dot);
+    case 9: return launch_n<10, T>(P, u, y, td, tc, s, dot);
+    case 10: return launch_n<11, T>(P, u, y, td, tc, s, dot);
+    case 11: return launch_n<12, T>(P, u, y, td, tc, s, dot);
     default: return hipErrorInvalidValue;
   }
+}
+
+template <int N>
+long long grid_n(long long n_el) {
+  return (n_el + ProjCfg<N>::E - 1) / ProjCfg<N>::E;
 }
 
 }  // namespace
 
 hipError_t launch_projection(const ProjPlan& P, bool f32, const void* u, void* y, const void* tau_d,
-                             const void* tau_c, hipStream_t s) {
-  return f32 ? launch_t<float>(P, u, y, tau_d, tau_c, s) : launch_t<double>(P, u, y, tau_d, tau_c, s);
+                             const void* tau_c, hipStream_t s, void* dot_partial) {
+  return f32 ? launch_t<float>(P, u, y, tau_d, tau_c, s, dot_partial)
+             : launch_t<double>(P, u, y, tau_d, tau_c, s, dot_partial);
+}
+
+long long projection_grid(const ProjPlan& P) {
+  const long long n = P.mesh.n_el;
+  switch (P.k) {
+    case 1: return grid_n<2>(n);
+    case 2: return grid_n<3>(n);
+    case 3: return grid_n<4>(n);
+    case 4: return grid_n<5>(n);
+    case 5: return grid_n<6>(n);
+    case 6: return grid_n<7>(n);
+    case 7: return grid_n<8>(n);
+    case 8: return grid_n<9>(n);
+    case 9: return grid_n<10>(n);
+    case 10: return grid_n<11>(n);
+    case 11: return grid_n<12>(n);
+    default: return 0;
+  }
 }
 
 }  // namespace dgmf
