@@ -152,6 +152,22 @@ int dg_apply_projection(const dg_op_desc* desc, dg_dtype dtype, const void* u, c
 int dg_apply_gradient(const dg_op_desc* desc, dg_dtype dtype, const void* p, void* y, void* hip_stream);
 
 /*
+ * Level transfers of the h-multigrid hierarchy (Sec. 3.3: geometric multigrid
+ * with matrix-free transfers).  `coarse` describes the coarse mesh; the fine
+ * mesh has 2*n_el[d] elements per direction on the same box, same degree.
+ * dg_prolongate embeds the coarse DG space in the fine one: the fine element
+ * with child index (cx, cy, cz) of its parent gets the parent's polynomial
+ * at its nodes, u_f = (P_cx (x) P_cy (x) P_cz) u_parent with
+ * P_c[i][a] = l_a((xi_i + c)/2).  dg_restrict applies the transpose, summing
+ * the eight children of each coarse element.
+ *   uc, rc: [n_comp][N_el][n^3] on the coarse mesh; uf, rf: [n_comp][8 N_el][n^3]
+ *   on the fine mesh (element numbering of the fine mesh); `dtype`; n_comp
+ *   1 or 3; src and dst must not overlap.
+ */
+int dg_prolongate(const dg_op_desc* coarse, dg_dtype dtype, const void* uc, void* uf, void* hip_stream);
+int dg_restrict(const dg_op_desc* coarse, dg_dtype dtype, const void* rf, void* rc, void* hip_stream);
+
+/*
  * Velocity divergence d_h with central flux (Sec. 3.2, weak form of d_h), the
  * right-hand side of the pressure Poisson step without its -gamma_0/dt factor:
  *   b_i = -(grad phi_i, u)_K + sum_faces (phi_i, 1/2 (u- + u+) . n)

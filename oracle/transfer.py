@@ -7,8 +7,10 @@ prolongation is the embedding of the coarse DG space in the fine one: the
 fine nodal values are the coarse element's polynomial evaluated at the fine
 nodes.  The restriction is its transpose.  Each fine element's values are a
 dense matrix (rows: fine nodes, columns: coarse basis functions, every entry
-a product of three explicit Lagrange evaluations) times its parent's values.
+a product of three Lagrange evaluations) times its parent's values.
 """
+from functools import lru_cache
+
 import numpy as np
 
 from . import basis
@@ -19,25 +21,17 @@ def fine_mesh(coarse):
     return Mesh(tuple(2 * n for n in coarse.n_el), coarse.length)
 
 
+@lru_cache(maxsize=64)
 def child_matrix(k, child):
     """Phi[i, a] = l_a(x_i) over the 3D nodes: fine node i of the child
-    (cx, cy, cz) mapped into the parent's reference cube, coarse basis a."""
+    (cx, cy, cz) mapped into the parent's reference cube, coarse basis a; the
+    tensor product of the three 1D evaluation matrices (rows i + n(j + n l),
+    columns a + n(b + n c))."""
     xi = basis.lgl_nodes(k)
     n = k + 1
-    pts = [(xi + c) / 2.0 for c in child]              # per direction, in the parent
-    Phi = np.zeros((n ** 3, n ** 3))
-    for l in range(n):
-        for j in range(n):
-            for i in range(n):
-                row = i + n * (j + n * l)
-                vx = basis.lagrange_values(xi, [pts[0][i]])[0]
-                vy = basis.lagrange_values(xi, [pts[1][j]])[0]
-                vz = basis.lagrange_values(xi, [pts[2][l]])[0]
-                for c in range(n):
-                    for b in range(n):
-                        for a in range(n):
-                            Phi[row, a + n * (b + n * c)] = vx[a] * vy[b] * vz[c]
-    return Phi
+    L = [basis.lagrange_values(xi, (xi + c) / 2.0) for c in child]   # per direction: [fine node, coarse basis]
+    # Phi[(l, j, i), (c, b, a)] = Lz[l, c] Ly[j, b] Lx[i, a]
+    return np.einsum("lc,jb,ia->ljicba", L[2], L[1], L[0]).reshape(n ** 3, n ** 3)
 
 
 def _children(coarse):
@@ -58,8 +52,8 @@ def prolongate(u, k, coarse):
         for cy in range(2):
             for cz in range(2):
                 sel = np.nonzero((child[:, 0] == cx) & (child[:, 1] == cy) & (child[:, 2] == cz))[0]
-                Phi = child_matrix(k, (cx, cy, cz))
-                out[..., sel, :] = u[..., parent[sel], :] @ Phi.T
+                PhiT = np.ascontiguousarray(child_matrix(k, (cx, cy, cz)).T)
+                out[..., sel, :] = u[..., parent[sel], :] @ PhiT
     return out
 
 

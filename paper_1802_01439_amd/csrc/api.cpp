@@ -459,6 +459,41 @@ int dg_apply_gradient(const dg_op_desc* desc, dg_dtype dtype, const void* p, voi
   return ok();
 }
 
+static int transfer(const dg_op_desc* coarse, dg_dtype dtype, bool prolong, const void* src, void* dst,
+                    void* hip_stream) {
+  int rc = validate_desc(coarse);
+  if (rc) return rc;
+  if (dtype != DG_F64 && dtype != DG_F32) return fail(DG_ERR_INVALID_ARG, "dtype must be DG_F64 or DG_F32");
+  if (coarse->n_comp != 1 && coarse->n_comp != 3) return fail(DG_ERR_INVALID_ARG, "n_comp must be 1 or 3");
+  if (!src || !dst) return fail(DG_ERR_INVALID_ARG, "src/dst is NULL");
+  for (int d = 0; d < 3; ++d)
+    if (coarse->n_el[d] > (1 << 29)) return fail(DG_ERR_INVALID_ARG, "fine mesh too large");
+  const long long nc = num_elements(coarse);
+  if (8 * nc > (1LL << 31) - 1) return fail(DG_ERR_INVALID_ARG, "fine mesh too large");
+  const size_t es = dtype == DG_F64 ? 8 : 4;
+  const size_t cb = (size_t)coarse->n_comp * nc * dofs_per_element(coarse) * es;
+  if (overlaps(src, prolong ? cb : 8 * cb, dst, prolong ? 8 * cb : cb)) return fail(DG_ERR_ALIAS, "dst overlaps src");
+  TransferPlan P;
+  P.k = coarse->degree;
+  P.nxc = coarse->n_el[0];
+  P.nyc = coarse->n_el[1];
+  P.nzc = coarse->n_el[2];
+  P.n_comp = coarse->n_comp;
+  P.P[0] = child_interp(P.k, 0);
+  P.P[1] = child_interp(P.k, 1);
+  hipError_t e = launch_transfer(P, prolong, dtype == DG_F32, src, dst, (hipStream_t)hip_stream);
+  if (e != hipSuccess) return hip_fail(e, prolong ? "prolongation kernel launch" : "restriction kernel launch");
+  return ok();
+}
+
+int dg_prolongate(const dg_op_desc* coarse, dg_dtype dtype, const void* uc, void* uf, void* hip_stream) {
+  return transfer(coarse, dtype, true, uc, uf, hip_stream);
+}
+
+int dg_restrict(const dg_op_desc* coarse, dg_dtype dtype, const void* rf, void* rc, void* hip_stream) {
+  return transfer(coarse, dtype, false, rf, rc, hip_stream);
+}
+
 int dg_apply_inverse_mass(const dg_op_desc* desc, dg_dtype dtype, const void* src, void* dst,
                           void* hip_stream) {
   int rc = validate_desc(desc);

@@ -116,6 +116,16 @@ std::vector<double> colloc_deriv(const std::vector<double>& z) {
 
 }  // namespace
 
+std::vector<double> child_interp(int k, int c) {
+  const int n = k + 1;
+  std::vector<double> xi(n);
+  lgl_nodes(k, xi.data());
+  std::vector<double> P(n * n);
+  for (int i = 0; i < n; ++i)
+    for (int a = 0; a < n; ++a) P[i * n + a] = lag(xi, a, 0.5 * (xi[i] + c));
+  return P;
+}
+
 Basis1D make_basis(int k, int m) {
   Basis1D B;
   B.k = k;

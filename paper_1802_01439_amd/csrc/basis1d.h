@@ -14,6 +14,9 @@ namespace dgmf {
 void lgl_nodes(int k, double* x);
 // m-point Gauss-Legendre rule on [0,1].
 void gauss_rule(int m, double* x, double* w);
+// Embedding of the degree-k LGL basis of [0,1] in its half c (0: [0,1/2],
+// 1: [1/2,1]) mapped to [0,1]: P[i*n+a] = l_a((xi_i + c)/2), n = k+1.
+std::vector<double> child_interp(int k, int c);
 
 struct Basis1D {
   int k = 0, n = 0, m = 0;

@@ -60,6 +60,15 @@ long long pcg_precond_grid(int k, long long nblocks);
 hipError_t launch_pcg_precond(int k, const std::vector<double>& Minv, double scale, long long nblocks, double* x,
                               double* r, const double* p, const double* q, double* z, const double* st,
                               double* partial, hipStream_t s);
+// h-multigrid level transfers between a mesh (coarse) and the mesh with every
+// element split in two per direction: P[c] = child_interp(k, c)
+struct TransferPlan {
+  int k = 0, nxc = 0, nyc = 0, nzc = 0, n_comp = 1;
+  std::vector<double> P[2];
+};
+hipError_t launch_transfer(const TransferPlan& P, bool prolong, bool f32, const void* src, void* dst,
+                           hipStream_t s);
+
 // pressure gradient: the divergence's 1D tables, G = -B^T
 hipError_t launch_gradient(const DivPlan& P, bool f32, const void* p, void* y, hipStream_t s);
 

@@ -1,0 +1,257 @@
+// Level transfers of the h-multigrid hierarchy (Sec. 3.3: geometric
+// multigrid with matrix-free transfers), FP64 and FP32, degrees 1..11.
+//
+// The fine mesh splits every element of the coarse one in two per direction
+// (same degree).  Prolongation embeds the coarse DG space: the fine element
+// with child index (cx, cy, cz) gets
+//   u_f = (P_cx (x) P_cy (x) P_cz) u_parent,   P_c[i][a] = l_a((xi_i + c)/2);
+// restriction is the transpose, summed over the eight children:
+//   r_c = sum_children (P_cx^T (x) P_cy^T (x) P_cz^T) r_child.
+// Element-local apart from the parent/child gather; memory bound.
+//
+// Prolongation: one workgroup per batch of E = floor(256/n^2) fine elements,
+// n^2 threads each; the z sweep runs on the parent's column in registers,
+// the y and x sweeps on LDS pencils in place (3 barriers).  Restriction: one
+// workgroup per batch of E coarse elements; per child a z sweep from the
+// child's column, a y sweep in LDS, and an x sweep whose result each thread
+// accumulates in registers for its own x pencil of the coarse element
+// (3 barriers per child).
+#include "api_internal.h"
+#include "common.h"
+#include "laplace_kernels.h"
+#include "ops.h"
+
+namespace dgmf {
+
+namespace {
+
+template <int N, typename T>
+struct TransferTab {
+  T P[2][N][N];   // P[c][i][a] = l_a((xi_i + c)/2)
+};
+
+struct LevelArgs {
+  int nxc, nyc, nzc;   // coarse elements per direction (fine: twice as many)
+  long long ncoarse;   // nxc * nyc * nzc
+};
+
+template <int N, typename T>
+__global__ void __launch_bounds__(LapCfgB<N>::THREADS)
+prolongate_kernel(const T* __restrict__ uc, T* __restrict__ uf, LevelArgs lv,
+                  const TransferTab<N, T>* __restrict__ tab) {
+  using C = LapCfgB<N>;
+  constexpr int N2 = N * N, N3 = N * N * N, E = C::E, ES = C::ES, PX = C::PX, PY = C::PY;
+  __shared__ T U[E * ES];
+  const int tid = threadIdx.x;
+  const int le = tid / N2, p = tid - le * N2;
+  const int p0 = p % N, p1 = p / N;
+  const long long nfine = 8 * lv.ncoarse;
+  const long long f = (long long)xcd_remap(blockIdx.x, gridDim.x) * E + le;
+  const bool active = f < nfine;
+  const int comp = blockIdx.y;
+  const int nxf = 2 * lv.nxc, nyf = 2 * lv.nyc;
+  int cx = 0, cy = 0, cz = 0;
+  long long parent = 0;
+  if (active) {
+    const long long fz = f / ((long long)nxf * nyf);
+    const long long r = f - fz * nxf * nyf;
+    const int fy = (int)(r / nxf), fx = (int)(r - (long long)fy * nxf);
+    cx = fx & 1;
+    cy = fy & 1;
+    cz = (int)(fz & 1);
+    parent = (fx >> 1) + (long long)lv.nxc * ((fy >> 1) + (long long)lv.nyc * (fz >> 1));
+  }
+  T* Ue = U + le * ES;
+  T x[N], y[N];
+  // z: parent column (a, b) = (p0, p1) in registers, P_cz
+  if (active) {
+    const T* g = uc + (size_t)comp * lv.ncoarse * N3 + (size_t)parent * N3 + p0 + N * p1;
+#pragma unroll
+    for (int c = 0; c < N; ++c) x[c] = g[N2 * c];
+#pragma unroll
+    for (int l = 0; l < N; ++l) {
+      T s = tab->P[cz][l][0] * x[0];
+#pragma unroll
+      for (int c = 1; c < N; ++c) s = fmadd(tab->P[cz][l][c], x[c], s);
+      y[l] = s;
+    }
+    const int base = p0 + PX * p1;
+#pragma unroll
+    for (int l = 0; l < N; ++l) Ue[base + PY * l] = y[l];
+  }
+  __syncthreads();
+  // y: pencil (a, l) = (p0, p1), P_cy, in place
+  if (active) {
+    const int base = p0 + PY * p1;
+#pragma unroll
+    for (int b = 0; b < N; ++b) x[b] = Ue[base + PX * b];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      T s = tab->P[cy][j][0] * x[0];
+#pragma unroll
+      for (int b = 1; b < N; ++b) s = fmadd(tab->P[cy][j][b], x[b], s);
+      y[j] = s;
+    }
+#pragma unroll
+    for (int j = 0; j < N; ++j) Ue[base + PX * j] = y[j];
+  }
+  __syncthreads();
+  // x: pencil (j, l) = (p0, p1), P_cx, in place
+  if (active) {
+    const int base = PX * p0 + PY * p1;
+#pragma unroll
+    for (int a = 0; a < N; ++a) x[a] = Ue[base + a];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      T s = tab->P[cx][i][0] * x[0];
+#pragma unroll
+      for (int a = 1; a < N; ++a) s = fmadd(tab->P[cx][i][a], x[a], s);
+      y[i] = s;
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i) Ue[base + i] = y[i];
+  }
+  __syncthreads();
+  // store the fine z column (i, j) = (p0, p1)
+  if (active) {
+    T* g = uf + (size_t)comp * nfine * N3 + (size_t)f * N3 + p0 + N * p1;
+    const int base = p0 + PX * p1;
+#pragma unroll
+    for (int l = 0; l < N; ++l) g[N2 * l] = Ue[base + PY * l];
+  }
+}
+
+template <int N, typename T>
+__global__ void __launch_bounds__(LapCfgB<N>::THREADS)
+restrict_kernel(const T* __restrict__ rf, T* __restrict__ rc, LevelArgs lv,
+                const TransferTab<N, T>* __restrict__ tab) {
+  using C = LapCfgB<N>;
+  constexpr int N2 = N * N, N3 = N * N * N, E = C::E, ES = C::ES, PX = C::PX, PY = C::PY;
+  __shared__ T U[E * ES];
+  const int tid = threadIdx.x;
+  const int le = tid / N2, p = tid - le * N2;
+  const int p0 = p % N, p1 = p / N;
+  const long long e = (long long)xcd_remap(blockIdx.x, gridDim.x) * E + le;
+  const bool active = e < lv.ncoarse;
+  const int comp = blockIdx.y;
+  const long long nfine = 8 * lv.ncoarse;
+  const int nxf = 2 * lv.nxc, nyf = 2 * lv.nyc;
+  int ex = 0, ey = 0, ez = 0;
+  if (active) {
+    ez = (int)(e / ((long long)lv.nxc * lv.nyc));
+    const long long r = e - (long long)ez * lv.nxc * lv.nyc;
+    ey = (int)(r / lv.nxc);
+    ex = (int)(r - (long long)ey * lv.nxc);
+  }
+  T* Ue = U + le * ES;
+  T x[N], y[N], acc[N];
+#pragma unroll
+  for (int a = 0; a < N; ++a) acc[a] = 0;
+  for (int ch = 0; ch < 8; ++ch) {
+    const int cx = ch & 1, cy = (ch >> 1) & 1, cz = ch >> 2;
+    // z: the child's column (i, j) = (p0, p1), P_cz^T
+    if (active) {
+      const long long f = (2 * ex + cx) + (long long)nxf * ((2 * ey + cy) + (long long)nyf * (2 * ez + cz));
+      const T* g = rf + (size_t)comp * nfine * N3 + (size_t)f * N3 + p0 + N * p1;
+#pragma unroll
+      for (int l = 0; l < N; ++l) x[l] = g[N2 * l];
+#pragma unroll
+      for (int c = 0; c < N; ++c) {
+        T s = tab->P[cz][0][c] * x[0];
+#pragma unroll
+        for (int l = 1; l < N; ++l) s = fmadd(tab->P[cz][l][c], x[l], s);
+        y[c] = s;
+      }
+      const int base = p0 + PX * p1;
+#pragma unroll
+      for (int c = 0; c < N; ++c) Ue[base + PY * c] = y[c];
+    }
+    __syncthreads();
+    // y: pencil (i, c) = (p0, p1), P_cy^T, in place
+    if (active) {
+      const int base = p0 + PY * p1;
+#pragma unroll
+      for (int j = 0; j < N; ++j) x[j] = Ue[base + PX * j];
+#pragma unroll
+      for (int b = 0; b < N; ++b) {
+        T s = tab->P[cy][0][b] * x[0];
+#pragma unroll
+        for (int j = 1; j < N; ++j) s = fmadd(tab->P[cy][j][b], x[j], s);
+        y[b] = s;
+      }
+#pragma unroll
+      for (int b = 0; b < N; ++b) Ue[base + PX * b] = y[b];
+    }
+    __syncthreads();
+    // x: pencil (b, c) = (p0, p1), P_cx^T, accumulated in registers
+    if (active) {
+      const int base = PX * p0 + PY * p1;
+#pragma unroll
+      for (int i = 0; i < N; ++i) x[i] = Ue[base + i];
+#pragma unroll
+      for (int a = 0; a < N; ++a) {
+        T s = tab->P[cx][0][a] * x[0];
+#pragma unroll
+        for (int i = 1; i < N; ++i) s = fmadd(tab->P[cx][i][a], x[i], s);
+        acc[a] += s;
+      }
+    }
+    __syncthreads();
+  }
+  // store the coarse x pencil (b, c) = (p0, p1)
+  if (active) {
+    T* g = rc + (size_t)comp * lv.ncoarse * N3 + (size_t)e * N3 + N * p0 + N2 * p1;
+#pragma unroll
+    for (int a = 0; a < N; ++a) g[a] = acc[a];
+  }
+}
+
+template <int N, typename T>
+hipError_t launch_n(const TransferPlan& P, bool prolong, const void* src, void* dst, hipStream_t s) {
+  TransferTab<N, T> t;
+  for (int c = 0; c < 2; ++c)
+    for (int i = 0; i < N; ++i)
+      for (int a = 0; a < N; ++a) t.P[c][i][a] = (T)P.P[c][i * N + a];
+  hipError_t err;
+  const TransferTab<N, T>* dt = device_table_of("transfer", t, &err);
+  if (!dt) return err;
+  LevelArgs lv{P.nxc, P.nyc, P.nzc, (long long)P.nxc * P.nyc * P.nzc};
+  using C = LapCfgB<N>;
+  const long long items = prolong ? 8 * lv.ncoarse : lv.ncoarse;
+  const long long grid = (items + C::E - 1) / C::E;
+  if (grid > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+  if (grid == 0) return hipSuccess;
+  const dim3 g((unsigned)grid, (unsigned)P.n_comp);
+  if (prolong)
+    hipLaunchKernelGGL((prolongate_kernel<N, T>), g, dim3(C::THREADS), 0, s, (const T*)src, (T*)dst, lv, dt);
+  else
+    hipLaunchKernelGGL((restrict_kernel<N, T>), g, dim3(C::THREADS), 0, s, (const T*)src, (T*)dst, lv, dt);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_t(const TransferPlan& P, bool prolong, const void* src, void* dst, hipStream_t s) {
+  switch (P.k) {
+    case 1: return launch_n<2, T>(P, prolong, src, dst, s);
+    case 2: return launch_n<3, T>(P, prolong, src, dst, s);
+    case 3: return launch_n<4, T>(P, prolong, src, dst, s);
+    case 4: return launch_n<5, T>(P, prolong, src, dst, s);
+    case 5: return launch_n<6, T>(P, prolong, src, dst, s);
+    case 6: return launch_n<7, T>(P, prolong, src, dst, s);
+    case 7: return launch_n<8, T>(P, prolong, src, dst, s);
+    case 8: return launch_n<9, T>(P, prolong, src, dst, s);
+    case 9: return launch_n<10, T>(P, prolong, src, dst, s);
+    case 10: return launch_n<11, T>(P, prolong, src, dst, s);
+    case 11: return launch_n<12, T>(P, prolong, src, dst, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_transfer(const TransferPlan& P, bool prolong, bool f32, const void* src, void* dst,
+                           hipStream_t s) {
+  return f32 ? launch_t<float>(P, prolong, src, dst, s) : launch_t<double>(P, prolong, src, dst, s);
+}
+
+}  // namespace dgmf

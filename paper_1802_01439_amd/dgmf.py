@@ -25,7 +25,7 @@ DG_PC_JACOBI_F64, DG_PC_CHEB_F32 = 0, 1
 DG_OP_HELMHOLTZ, DG_OP_PROJECTION = 0, 1
 
 EXPORTS = ("dg_apply_laplace", "dg_apply_convective", "dg_vjp_convective", "dg_apply_divergence",
-           "dg_apply_inverse_mass", "dg_apply_helmholtz", "dg_apply_projection", "dg_apply_gradient", "dg_cg_solve", "dg_mass_pcg_solve", "dg_laplace_diagonal", "dg_lgl_nodes", "dg_error_string", "dg_last_error")
+           "dg_apply_inverse_mass", "dg_apply_helmholtz", "dg_apply_projection", "dg_apply_gradient", "dg_prolongate", "dg_restrict", "dg_cg_solve", "dg_mass_pcg_solve", "dg_laplace_diagonal", "dg_lgl_nodes", "dg_error_string", "dg_last_error")
 
 
 class OpDesc(ctypes.Structure):
@@ -76,6 +76,8 @@ def lib():
         L.dg_apply_helmholtz.argtypes = [pd, ctypes.c_int, ctypes.c_double, vp, vp, vp]
         L.dg_apply_projection.argtypes = [pd, ctypes.c_int, vp, vp, vp, vp, vp]
         L.dg_apply_gradient.argtypes = [pd, ctypes.c_int, vp, vp, vp]
+        L.dg_prolongate.argtypes = [pd, ctypes.c_int, vp, vp, vp]
+        L.dg_restrict.argtypes = [pd, ctypes.c_int, vp, vp, vp]
         L.dg_cg_solve.argtypes = [pd, ctypes.POINTER(CgOpts), vp, vp, ctypes.POINTER(CgReport), vp]
         L.dg_mass_pcg_solve.argtypes = [pd, ctypes.c_int32, ctypes.c_double, vp, vp, vp, vp, ctypes.c_double,
                                          ctypes.c_int32, ctypes.POINTER(CgReport), vp]
@@ -86,7 +88,7 @@ def lib():
         L.dg_last_error.argtypes = []
         L.dg_last_error.restype = ctypes.c_char_p
         for name in ("dg_apply_laplace", "dg_apply_convective", "dg_vjp_convective", "dg_apply_divergence",
-                     "dg_apply_inverse_mass", "dg_apply_helmholtz", "dg_apply_projection", "dg_apply_gradient", "dg_cg_solve", "dg_mass_pcg_solve", "dg_laplace_diagonal", "dg_lgl_nodes"):
+                     "dg_apply_inverse_mass", "dg_apply_helmholtz", "dg_apply_projection", "dg_apply_gradient", "dg_prolongate", "dg_restrict", "dg_cg_solve", "dg_mass_pcg_solve", "dg_laplace_diagonal", "dg_lgl_nodes"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -219,6 +221,44 @@ def apply_gradient(desc, p, out=None):
         raise TypeError("out must have the dtype of p")
     _check(lib().dg_apply_gradient(ctypes.byref(desc), _dtype_code(p), ctypes.c_void_p(p.data_ptr()),
                                    ctypes.c_void_p(out.data_ptr()), _stream(p)))
+    return out
+
+
+def _level_shapes(coarse):
+    n3 = (coarse.degree + 1) ** 3
+    nc = _nel(coarse)
+    if coarse.n_comp == 1:
+        return (nc, n3), (8 * nc, n3)
+    return (coarse.n_comp, nc, n3), (coarse.n_comp, 8 * nc, n3)
+
+
+def prolongate(coarse, uc, out=None):
+    """Coarse -> fine (every element split in two per direction); coarse describes the coarse mesh."""
+    torch = _torch()
+    sc, sf = _level_shapes(coarse)
+    _check_tensor(uc, "uc", sc)
+    if out is None:
+        out = torch.empty(sf, dtype=uc.dtype, device=uc.device)
+    _check_tensor(out, "out", sf)
+    if out.dtype != uc.dtype:
+        raise TypeError("out must have the dtype of uc")
+    _check(lib().dg_prolongate(ctypes.byref(coarse), _dtype_code(uc), ctypes.c_void_p(uc.data_ptr()),
+                               ctypes.c_void_p(out.data_ptr()), _stream(uc)))
+    return out
+
+
+def restrict(coarse, rf, out=None):
+    """Fine -> coarse, the transpose of prolongate."""
+    torch = _torch()
+    sc, sf = _level_shapes(coarse)
+    _check_tensor(rf, "rf", sf)
+    if out is None:
+        out = torch.empty(sc, dtype=rf.dtype, device=rf.device)
+    _check_tensor(out, "out", sc)
+    if out.dtype != rf.dtype:
+        raise TypeError("out must have the dtype of rf")
+    _check(lib().dg_restrict(ctypes.byref(coarse), _dtype_code(rf), ctypes.c_void_p(rf.data_ptr()),
+                             ctypes.c_void_p(out.data_ptr()), _stream(rf)))
     return out
 
 
