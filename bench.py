@@ -217,12 +217,27 @@ def oracle_rows(args, budget=0.15):
             dofs[name] += done * n3 * (3 if name == "projection" else 1)
             secs[name] += t_k
         del full
-    return {name: {"dofs_per_s": dofs[name] / secs[name],
-                   "sample": f"k={args.kmin}..{args.kmax}, {dofs[name]} DoFs in {secs[name]:.1f} s"}
-            for name in names}
+    out = {name: {"dofs_per_s": dofs[name] / secs[name],
+                  "sample": f"k={args.kmin}..{args.kmax}, {dofs[name]} DoFs in {secs[name]:.1f} s"}
+           for name in names}
+    # prolongation (fine DoFs per second) on a 4 x 2 x 2 coarse mesh per degree
+    from oracle.transfer import prolongate
+    fd, ft = 0, 0.0
+    for k in range(args.kmin, args.kmax + 1):
+        coarse = M.Mesh((4, 2, 2), (1.0, 1.0, 1.0))
+        n3 = (k + 1) ** 3
+        u = inputs.uniform((coarse.N, n3), seed=inputs.FIELD_SEED_BASE + 50 + k)
+        prolongate(u, k, coarse)          # the child matrices are built once per degree
+        t0 = time.perf_counter()
+        prolongate(u, k, coarse)
+        ft += time.perf_counter() - t0
+        fd += 8 * coarse.N * n3
+    out["prolongation"] = {"dofs_per_s": fd / ft, "sample": f"k={args.kmin}..{args.kmax}, 4x2x2 coarse meshes, "
+                                                            f"{fd} fine DoFs in {ft:.2f} s"}
+    return out
 
 
-def extras(torch, dgmf, inputs, dev, args, which=("vjp", "cg", "mass", "proj", "mpcg", "grad")):
+def extras(torch, dgmf, inputs, dev, args, which=("vjp", "cg", "mass", "proj", "mpcg", "grad", "xfer")):
     out = {}
     # inverse mass (element-local, memory bound) and the projection-step
     # operator (M + A_D + A_C, three components, seeded per-element penalty
@@ -230,6 +245,8 @@ def extras(torch, dgmf, inputs, dev, args, which=("vjp", "cg", "mass", "proj", "
     if "mass" in which:
         out["inverse_mass_sweep"] = _sweep_extra(torch, dgmf, dev, args, 1, 102, lambda d, x, y, tau:
                                                  dgmf.apply_inverse_mass(d, x, y))
+    if "xfer" in which:
+        out["transfer_sweep"] = _xfer_sweep(torch, dgmf, dev, args)
     if "grad" in which:
         out["gradient_sweep"] = _grad_sweep(torch, dgmf, dev, args, "gradient")
         out["divergence_sweep"] = _grad_sweep(torch, dgmf, dev, args, "divergence")
@@ -347,6 +364,44 @@ def mass_pcg_extra(torch, dgmf, inputs, dev, k=5, N=16):
     return res
 
 
+def _xfer_sweep(torch, dgmf, dev, args):
+    """h-multigrid prolongation and restriction between the mesh of N/2 and N
+    elements per direction, N = the degree-sweep mesh rounded to even;
+    seeded U[-1,1] input, 4 input/output pairs in rotation.  Algorithmic
+    bytes: 9/8 values per fine DoF either way (coarse read or written once,
+    fine written or read once)."""
+    res = {}
+    R = 4
+    for k in range(args.kmin, args.kmax + 1):
+        Nc = sweep_mesh(k) // 2
+        d = dgmf.make_desc(k, Nc)
+        n3 = (k + 1) ** 3
+        g = torch.Generator(device=dev)
+        g.manual_seed(106 + 10 * k)
+        coarse = torch.rand((Nc ** 3, n3), generator=g, dtype=torch.float64, device=dev) * 2 - 1
+        fine = torch.rand((8 * Nc ** 3, n3), generator=g, dtype=torch.float64, device=dev) * 2 - 1
+        nf = fine.numel()
+        for dtype, tdt in (("f64", torch.float64), ("f32", torch.float32)):
+            es = 8 if dtype == "f64" else 4
+            for name, src, call in (("prolongate", coarse, dgmf.prolongate), ("restrict", fine, dgmf.restrict)):
+                xs = [src.to(tdt) for _ in range(R)]
+                ys = [call(d, xs[i]) for i in range(R)]
+                torch.cuda.synchronize()
+                s0, e0 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                reps = 5 * R
+                s0.record()
+                for i in range(reps):
+                    call(d, xs[i % R], ys[i % R])
+                e0.record()
+                torch.cuda.synchronize()
+                t = s0.elapsed_time(e0) / 1e3 / reps
+                res[f"{name}_k{k}_{dtype}"] = {"us": t * 1e6, "fine_dofs_per_s": nf / t,
+                                               "hbm_frac": 9 / 8 * es * nf / t / (HBM_PEAK_GBS * 1e9)}
+                del xs, ys
+        del coarse, fine
+    return res
+
+
 def _grad_sweep(torch, dgmf, dev, args, op):
     """Pressure gradient (scalar -> 3 components) or velocity divergence
     (3 components -> scalar) on the degree-sweep meshes, seeded U[-1,1] input;
@@ -446,7 +501,7 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--sweep-out", default="")
     ap.add_argument("--extras-only", default="",
-                    help="diagnostic: run only these extras (vjp,cg,mass,proj,mpcg,grad), print them as one JSON line, no sweep")
+                    help="diagnostic: run only these extras (vjp,cg,mass,proj,mpcg,grad,xfer), print them as one JSON line, no sweep")
     ap.add_argument("--calib-copy", type=int, default=0,
                     help="also run one plain device copy of this many bytes (counter calibration)")
     args = ap.parse_args()

@@ -9,11 +9,13 @@
 //   r_c = sum_children (P_cx^T (x) P_cy^T (x) P_cz^T) r_child.
 // Element-local apart from the parent/child gather; memory bound.
 //
-// Prolongation: one workgroup per batch of E = floor(256/n^2) fine elements,
-// n^2 threads each; the z sweep runs on the parent's column in registers,
-// the y and x sweeps on LDS pencils in place (3 barriers).  Restriction: one
-// workgroup per batch of E coarse elements; per child a z sweep from the
-// child's column, a y sweep in LDS, and an x sweep whose result each thread
+// Both run one workgroup per batch of E = floor(256/n^2) coarse elements,
+// n^2 threads each, and loop over the eight children, so the child's 1D
+// matrices are uniform (scalar loads).  Prolongation: the parent's column is
+// read once into registers; per child the z sweep runs on it, the y and x
+// sweeps on LDS pencils in place, and the child's z columns are stored
+// (3 barriers per child).  Restriction: per child a z sweep from the child's
+// column, a y sweep in LDS, and an x sweep whose result each thread
 // accumulates in registers for its own x pencil of the coarse element
 // (3 barriers per child).
 #include "api_internal.h"
@@ -45,79 +47,79 @@ prolongate_kernel(const T* __restrict__ uc, T* __restrict__ uf, LevelArgs lv,
   const int tid = threadIdx.x;
   const int le = tid / N2, p = tid - le * N2;
   const int p0 = p % N, p1 = p / N;
-  const long long nfine = 8 * lv.ncoarse;
-  const long long f = (long long)xcd_remap(blockIdx.x, gridDim.x) * E + le;
-  const bool active = f < nfine;
+  const long long e = (long long)xcd_remap(blockIdx.x, gridDim.x) * E + le;
+  const bool active = e < lv.ncoarse;
   const int comp = blockIdx.y;
+  const long long nfine = 8 * lv.ncoarse;
   const int nxf = 2 * lv.nxc, nyf = 2 * lv.nyc;
-  int cx = 0, cy = 0, cz = 0;
-  long long parent = 0;
+  int ex = 0, ey = 0, ez = 0;
+  T xp[N], x[N], y[N];
   if (active) {
-    const long long fz = f / ((long long)nxf * nyf);
-    const long long r = f - fz * nxf * nyf;
-    const int fy = (int)(r / nxf), fx = (int)(r - (long long)fy * nxf);
-    cx = fx & 1;
-    cy = fy & 1;
-    cz = (int)(fz & 1);
-    parent = (fx >> 1) + (long long)lv.nxc * ((fy >> 1) + (long long)lv.nyc * (fz >> 1));
+    ez = (int)(e / ((long long)lv.nxc * lv.nyc));
+    const long long r = e - (long long)ez * lv.nxc * lv.nyc;
+    ey = (int)(r / lv.nxc);
+    ex = (int)(r - (long long)ey * lv.nxc);
+    // the parent's column (a, b) = (p0, p1), read once for all eight children
+    const T* g = uc + (size_t)comp * lv.ncoarse * N3 + (size_t)e * N3 + p0 + N * p1;
+#pragma unroll
+    for (int c = 0; c < N; ++c) xp[c] = g[N2 * c];
   }
   T* Ue = U + le * ES;
-  T x[N], y[N];
-  // z: parent column (a, b) = (p0, p1) in registers, P_cz
-  if (active) {
-    const T* g = uc + (size_t)comp * lv.ncoarse * N3 + (size_t)parent * N3 + p0 + N * p1;
+  for (int ch = 0; ch < 8; ++ch) {
+    const int cx = ch & 1, cy = (ch >> 1) & 1, cz = ch >> 2;
+    // z: P_cz on the parent column in registers.  The previous child's store
+    // read only this thread's own column, so no barrier is needed before it.
+    if (active) {
+      const int base = p0 + PX * p1;
 #pragma unroll
-    for (int c = 0; c < N; ++c) x[c] = g[N2 * c];
+      for (int l = 0; l < N; ++l) {
+        T s = tab->P[cz][l][0] * xp[0];
 #pragma unroll
-    for (int l = 0; l < N; ++l) {
-      T s = tab->P[cz][l][0] * x[0];
-#pragma unroll
-      for (int c = 1; c < N; ++c) s = fmadd(tab->P[cz][l][c], x[c], s);
-      y[l] = s;
+        for (int c = 1; c < N; ++c) s = fmadd(tab->P[cz][l][c], xp[c], s);
+        Ue[base + PY * l] = s;
+      }
     }
-    const int base = p0 + PX * p1;
+    __syncthreads();
+    // y: pencil (a, l) = (p0, p1), P_cy, in place
+    if (active) {
+      const int base = p0 + PY * p1;
 #pragma unroll
-    for (int l = 0; l < N; ++l) Ue[base + PY * l] = y[l];
-  }
-  __syncthreads();
-  // y: pencil (a, l) = (p0, p1), P_cy, in place
-  if (active) {
-    const int base = p0 + PY * p1;
+      for (int b = 0; b < N; ++b) x[b] = Ue[base + PX * b];
 #pragma unroll
-    for (int b = 0; b < N; ++b) x[b] = Ue[base + PX * b];
+      for (int j = 0; j < N; ++j) {
+        T s = tab->P[cy][j][0] * x[0];
 #pragma unroll
-    for (int j = 0; j < N; ++j) {
-      T s = tab->P[cy][j][0] * x[0];
+        for (int b = 1; b < N; ++b) s = fmadd(tab->P[cy][j][b], x[b], s);
+        y[j] = s;
+      }
 #pragma unroll
-      for (int b = 1; b < N; ++b) s = fmadd(tab->P[cy][j][b], x[b], s);
-      y[j] = s;
+      for (int j = 0; j < N; ++j) Ue[base + PX * j] = y[j];
     }
+    __syncthreads();
+    // x: pencil (j, l) = (p0, p1), P_cx, in place
+    if (active) {
+      const int base = PX * p0 + PY * p1;
 #pragma unroll
-    for (int j = 0; j < N; ++j) Ue[base + PX * j] = y[j];
-  }
-  __syncthreads();
-  // x: pencil (j, l) = (p0, p1), P_cx, in place
-  if (active) {
-    const int base = PX * p0 + PY * p1;
+      for (int a = 0; a < N; ++a) x[a] = Ue[base + a];
 #pragma unroll
-    for (int a = 0; a < N; ++a) x[a] = Ue[base + a];
+      for (int i = 0; i < N; ++i) {
+        T s = tab->P[cx][i][0] * x[0];
 #pragma unroll
-    for (int i = 0; i < N; ++i) {
-      T s = tab->P[cx][i][0] * x[0];
+        for (int a = 1; a < N; ++a) s = fmadd(tab->P[cx][i][a], x[a], s);
+        y[i] = s;
+      }
 #pragma unroll
-      for (int a = 1; a < N; ++a) s = fmadd(tab->P[cx][i][a], x[a], s);
-      y[i] = s;
+      for (int i = 0; i < N; ++i) Ue[base + i] = y[i];
     }
+    __syncthreads();
+    // store the child's z column (i, j) = (p0, p1)
+    if (active) {
+      const long long f = (2 * ex + cx) + (long long)nxf * ((2 * ey + cy) + (long long)nyf * (2 * ez + cz));
+      T* g = uf + (size_t)comp * nfine * N3 + (size_t)f * N3 + p0 + N * p1;
+      const int base = p0 + PX * p1;
 #pragma unroll
-    for (int i = 0; i < N; ++i) Ue[base + i] = y[i];
-  }
-  __syncthreads();
-  // store the fine z column (i, j) = (p0, p1)
-  if (active) {
-    T* g = uf + (size_t)comp * nfine * N3 + (size_t)f * N3 + p0 + N * p1;
-    const int base = p0 + PX * p1;
-#pragma unroll
-    for (int l = 0; l < N; ++l) g[N2 * l] = Ue[base + PY * l];
+      for (int l = 0; l < N; ++l) g[N2 * l] = Ue[base + PY * l];
+    }
   }
 }
 
@@ -217,8 +219,7 @@ hipError_t launch_n(const TransferPlan& P, bool prolong, const void* src, void* 
   if (!dt) return err;
   LevelArgs lv{P.nxc, P.nyc, P.nzc, (long long)P.nxc * P.nyc * P.nzc};
   using C = LapCfgB<N>;
-  const long long items = prolong ? 8 * lv.ncoarse : lv.ncoarse;
-  const long long grid = (items + C::E - 1) / C::E;
+  const long long grid = (lv.ncoarse + C::E - 1) / C::E;
   if (grid > 0x7fffffffLL) return hipErrorInvalidConfiguration;
   if (grid == 0) return hipSuccess;
   const dim3 g((unsigned)grid, (unsigned)P.n_comp);
