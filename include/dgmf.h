@@ -5,7 +5,8 @@
  * periodic Cartesian hexahedral meshes with tensor-product Lagrange bases on
  * Legendre-Gauss-Lobatto (LGL) nodes of degree k and Gauss quadrature, and
  * the preconditioned CG solver, the inverse mass matrix, the Helmholtz
- * operator and the projection-step operator of Sec. 3.3.  All compute runs
+ * operator, the projection-step operator and its inverse-mass-preconditioned
+ * solve, and the h-multigrid level transfers of Sec. 3.3.  All compute runs
  * in HIP kernels for gfx950.
  *
  * Mesh and layout (every entry point)
@@ -23,10 +24,10 @@
  *     parameter says "host".  The library owns only its own small caches
  *     (1D tables, solver work vectors).
  *   - apply / vjp / divergence / gradient / inverse mass / Helmholtz /
- *     projection calls are
+ *     projection / transfer calls are
  *     asynchronous on `hip_stream`
  *     (a hipStream_t; NULL = the default stream).  dg_cg_solve blocks until
- *     it returns.
+ *     it returns, and so does dg_mass_pcg_solve.
  *   - outputs are overwritten, never accumulated.  Inputs and outputs must
  *     not overlap (DG_ERR_ALIAS); dg_apply_inverse_mass alone also accepts
  *     dst == src (in place).
