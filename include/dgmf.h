@@ -264,6 +264,24 @@ int dg_mass_pcg_solve(const dg_op_desc* desc, int32_t op, double mass_factor, co
                       dg_cg_report* report, void* hip_stream);
 
 /*
+ * One V-cycle of geometric multigrid for the SIPG form of dg_apply_laplace
+ * (Sec. 3.3: the pressure Poisson preconditioner; Chebyshev smoothing of
+ * D^-1 A on [lambda_max/smoothing_range, lambda_max], the same degree before
+ * and after the coarse-grid correction, a Chebyshev method with
+ * coarse_degree steps on the coarsest level, matrix-free transfers of
+ * dg_prolongate / dg_restrict), in double precision:
+ *   z = V r,  level l = the mesh coarsened l times by two per direction
+ *   (re-discretised SIPG operator and diagonal), l = 0..levels-1.
+ * Post-smoothing smooths the residual equation from zero.
+ *   desc: the finest mesh, n_comp = 1, element counts divisible by
+ *   2^(levels-1); lambda_max: host array of `levels` eigenvalue bounds of
+ *   D_l^-1 A_l; r, z: [N_el][n^3] doubles (device), must not overlap.
+ * Allocates its level vectors, blocks until the cycle has run.
+ */
+int dg_gmg_vcycle(const dg_op_desc* desc, int32_t levels, int32_t degree, double smoothing_range,
+                  int32_t coarse_degree, const double* lambda_max, const double* r, double* z, void* hip_stream);
+
+/*
  * diag(A) of the SIPG form on one element (identical on every element of a
  * uniform periodic mesh with at least 2 elements per direction): host array of
  * n^3 doubles.  Setup for the Jacobi and Chebyshev preconditioners (Sec. 3.3:

@@ -63,4 +63,12 @@ hipError_t mpcg_start(const double* partial, double* st, hipStream_t s);
 hipError_t mpcg_beta(const double* rr_partial, const double* rz_partial, int nblocks, double* st, hipStream_t s);
 hipError_t mpcg_xpby(double* p, const double* z, const double* st, long long n, hipStream_t s);
 
+// multigrid V-cycle: Chebyshev smoother steps and vector updates (FP64)
+hipError_t mg_cheb_first(const double* b, const double* dinv, int n3, double s, double* d, double* x, long long n,
+                         hipStream_t st);
+hipError_t mg_cheb_next(const double* b, const double* t, const double* dinv, int n3, double c1, double c2, double* d,
+                        double* x, long long n, hipStream_t st);
+hipError_t mg_sub(const double* b, const double* t, double* y, long long n, hipStream_t st);
+hipError_t mg_add(double* x, const double* t, long long n, hipStream_t st);
+
 }  // namespace dgmf

@@ -1,0 +1,166 @@
+// One V-cycle of geometric multigrid for the SIPG Laplacian (Sec. 3.3: the
+// pressure Poisson preconditioner, Chebyshev smoothing of D^-1 A with
+// smoothing range 20, a Chebyshev method with a fixed number of steps on the
+// coarsest level, matrix-free level transfers), in FP64.
+//
+// Level l is the periodic mesh coarsened l times by two per direction, with
+// its own SIPG operator (the Laplace kernels with the level's plan) and
+// diagonal.  cycle(l, b):
+//   x = Cheb_l(b)                                   pre-smoothing from zero
+//   x += P cycle(l+1, R (b - A_l x))                coarse-grid correction
+//   x += Cheb_l(b - A_l x)                          post-smoothing
+// and on the coarsest level x = Cheb(b) of the coarse degree.  Cheb is the
+// zero-start Chebyshev iteration of D^-1 A on [lambda_max/range, lambda_max]
+// in its three-term form; its scalars are formed on the host.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <vector>
+
+#include "api_internal.h"
+#include "cg_kernels.h"
+#include "dgmf.h"
+#include "ops.h"
+
+namespace dgmf {
+
+namespace {
+
+struct MgLevel {
+  dg_op_desc desc{};
+  LaplacePlan plan;
+  long long n = 0;
+  double lmax = 0;
+  double *dinv = nullptr, *b = nullptr, *x = nullptr, *t = nullptr, *d = nullptr, *res = nullptr, *e = nullptr;
+};
+
+struct MgRun {
+  std::vector<MgLevel> lv;
+  std::vector<void*> owned;
+  int degree = 5, coarse_degree = 10, n3 = 0, k = 0;
+  double range = 20.0;
+  hipStream_t s = nullptr;
+  std::vector<double> P0, P1;
+
+  ~MgRun() {
+    for (void* p : owned) (void)hipFree(p);
+  }
+  hipError_t alloc(double** p, long long n) {
+    hipError_t e = hipMalloc((void**)p, (size_t)n * sizeof(double));
+    if (e == hipSuccess) owned.push_back(*p);
+    return e;
+  }
+
+  // x = Cheb(b) on level l (deg steps, deg - 1 operator applications)
+  hipError_t cheb(MgLevel& L, const double* b, double* x, int deg) {
+    const double lmin = L.lmax / range;
+    const double theta = 0.5 * (L.lmax + lmin), delta = 0.5 * (L.lmax - lmin);
+    hipError_t e;
+    if ((e = mg_cheb_first(b, L.dinv, n3, 1.0 / theta, L.d, x, L.n, s)) != hipSuccess) return e;
+    double rho_prev = delta / theta;
+    for (int step = 1; step < deg; ++step) {
+      if ((e = launch_laplace(L.plan, false, x, L.t, s)) != hipSuccess) return e;
+      const double rho = 1.0 / (2.0 * theta / delta - rho_prev);
+      if ((e = mg_cheb_next(b, L.t, L.dinv, n3, rho * rho_prev, 2.0 * rho / delta, L.d, x, L.n, s)) != hipSuccess)
+        return e;
+      rho_prev = rho;
+    }
+    return hipSuccess;
+  }
+
+  TransferPlan transfer_plan(int coarse) const {
+    TransferPlan T;
+    T.k = k;
+    T.nxc = lv[coarse].desc.n_el[0];
+    T.nyc = lv[coarse].desc.n_el[1];
+    T.nzc = lv[coarse].desc.n_el[2];
+    T.n_comp = 1;
+    T.P[0] = P0;
+    T.P[1] = P1;
+    return T;
+  }
+
+  // lv[l].x = cycle(l, lv[l].b)
+  hipError_t cycle(int l) {
+    MgLevel& L = lv[l];
+    hipError_t e;
+    const bool last = l + 1 == (int)lv.size();
+    if ((e = cheb(L, L.b, L.x, last ? coarse_degree : degree)) != hipSuccess) return e;
+    if (last) return hipSuccess;
+    if ((e = launch_laplace(L.plan, false, L.x, L.t, s)) != hipSuccess) return e;
+    if ((e = mg_sub(L.b, L.t, L.res, L.n, s)) != hipSuccess) return e;
+    const TransferPlan T = transfer_plan(l + 1);
+    if ((e = launch_transfer(T, false, false, L.res, lv[l + 1].b, s)) != hipSuccess) return e;
+    if ((e = cycle(l + 1)) != hipSuccess) return e;
+    if ((e = launch_transfer(T, true, false, lv[l + 1].x, L.t, s)) != hipSuccess) return e;
+    if ((e = mg_add(L.x, L.t, L.n, s)) != hipSuccess) return e;
+    if ((e = launch_laplace(L.plan, false, L.x, L.t, s)) != hipSuccess) return e;
+    if ((e = mg_sub(L.b, L.t, L.res, L.n, s)) != hipSuccess) return e;
+    if ((e = cheb(L, L.res, L.e, degree)) != hipSuccess) return e;
+    return mg_add(L.x, L.e, L.n, s);
+  }
+};
+
+}  // namespace
+
+}  // namespace dgmf
+
+using namespace dgmf;
+
+extern "C" int dg_gmg_vcycle(const dg_op_desc* desc, int32_t levels, int32_t degree, double smoothing_range,
+                             int32_t coarse_degree, const double* lambda_max, const double* r, double* z,
+                             void* hip_stream) {
+  int rc = validate_desc(desc);
+  if (rc) return rc;
+  if (desc->n_comp != 1) return fail(DG_ERR_INVALID_ARG, "the V-cycle needs n_comp = 1");
+  if (levels < 1 || levels > 10) return fail(DG_ERR_INVALID_ARG, "levels must be 1..10");
+  if (degree < 1 || coarse_degree < 1) return fail(DG_ERR_INVALID_ARG, "smoother degrees must be >= 1");
+  if (!(smoothing_range > 1.0) || !std::isfinite(smoothing_range))
+    return fail(DG_ERR_INVALID_ARG, "smoothing_range must be finite and > 1");
+  if (!lambda_max || !r || !z) return fail(DG_ERR_INVALID_ARG, "lambda_max/r/z is NULL");
+  if (desc->n_q != 0 && desc->n_q < desc->degree + 1)
+    return fail(DG_ERR_UNSUPPORTED, "the Laplace form needs n_q >= k+1 (exact Gauss integration)");
+  for (int l = 0; l < levels; ++l)
+    if (!(lambda_max[l] > 0.0) || !std::isfinite(lambda_max[l]))
+      return fail(DG_ERR_INVALID_ARG, "lambda_max must be finite and > 0 on every level");
+  for (int d = 0; d < 3; ++d)
+    if (desc->n_el[d] % (1 << (levels - 1)) != 0)
+      return fail(DG_ERR_INVALID_ARG, "element counts must be divisible by 2^(levels-1)");
+  const long long n0 = num_elements(desc) * dofs_per_element(desc);
+  if (overlaps(r, (size_t)n0 * 8, z, (size_t)n0 * 8)) return fail(DG_ERR_ALIAS, "z overlaps r");
+  MgRun M;
+  M.k = desc->degree;
+  M.n3 = (int)dofs_per_element(desc);
+  M.degree = degree;
+  M.coarse_degree = coarse_degree;
+  M.range = smoothing_range;
+  M.s = (hipStream_t)hip_stream;
+  M.P0 = child_interp(M.k, 0);
+  M.P1 = child_interp(M.k, 1);
+  M.lv.resize(levels);
+  hipError_t e;
+  std::vector<double> diag(M.n3);
+  for (int l = 0; l < levels; ++l) {
+    MgLevel& L = M.lv[l];
+    L.desc = *desc;
+    for (int d = 0; d < 3; ++d) L.desc.n_el[d] = desc->n_el[d] >> l;
+    L.plan = make_laplace_plan(&L.desc, 1);
+    L.n = num_elements(&L.desc) * M.n3;
+    L.lmax = lambda_max[l];
+    if ((rc = dg_laplace_diagonal(&L.desc, diag.data())) != DG_OK) return rc;
+    for (double& v : diag) v = 1.0 / v;
+    if ((e = M.alloc(&L.dinv, M.n3)) != hipSuccess) return hip_fail(e, "V-cycle tables");
+    if ((e = hipMemcpyAsync(L.dinv, diag.data(), M.n3 * sizeof(double), hipMemcpyHostToDevice, M.s)) != hipSuccess)
+      return hip_fail(e, "V-cycle tables");
+    if ((e = hipStreamSynchronize(M.s)) != hipSuccess) return hip_fail(e, "V-cycle tables");
+    double** bufs[5] = {&L.t, &L.d, &L.res, &L.e, &L.b};
+    for (int i = 0; i < (l == 0 ? 4 : 5); ++i)
+      if ((e = M.alloc(bufs[i], L.n)) != hipSuccess) return hip_fail(e, "V-cycle work vectors");
+    if (l > 0 && (e = M.alloc(&L.x, L.n)) != hipSuccess) return hip_fail(e, "V-cycle work vectors");
+  }
+  M.lv[0].b = const_cast<double*>(r);   // read only
+  M.lv[0].x = z;
+  if ((e = M.cycle(0)) != hipSuccess) return hip_fail(e, "V-cycle launch");
+  if ((e = hipStreamSynchronize(M.s)) != hipSuccess) return hip_fail(e, "V-cycle");
+  return ok();
+}

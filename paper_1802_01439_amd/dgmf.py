@@ -25,7 +25,7 @@ DG_PC_JACOBI_F64, DG_PC_CHEB_F32 = 0, 1
 DG_OP_HELMHOLTZ, DG_OP_PROJECTION = 0, 1
 
 EXPORTS = ("dg_apply_laplace", "dg_apply_convective", "dg_vjp_convective", "dg_apply_divergence",
-           "dg_apply_inverse_mass", "dg_apply_helmholtz", "dg_apply_projection", "dg_apply_gradient", "dg_prolongate", "dg_restrict", "dg_cg_solve", "dg_mass_pcg_solve", "dg_laplace_diagonal", "dg_lgl_nodes", "dg_error_string", "dg_last_error")
+           "dg_apply_inverse_mass", "dg_apply_helmholtz", "dg_apply_projection", "dg_apply_gradient", "dg_prolongate", "dg_restrict", "dg_gmg_vcycle", "dg_cg_solve", "dg_mass_pcg_solve", "dg_laplace_diagonal", "dg_lgl_nodes", "dg_error_string", "dg_last_error")
 
 
 class OpDesc(ctypes.Structure):
@@ -77,6 +77,8 @@ def lib():
         L.dg_apply_projection.argtypes = [pd, ctypes.c_int, vp, vp, vp, vp, vp]
         L.dg_apply_gradient.argtypes = [pd, ctypes.c_int, vp, vp, vp]
         L.dg_prolongate.argtypes = [pd, ctypes.c_int, vp, vp, vp]
+        L.dg_gmg_vcycle.argtypes = [pd, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
+                                     ctypes.POINTER(ctypes.c_double), vp, vp, vp]
         L.dg_restrict.argtypes = [pd, ctypes.c_int, vp, vp, vp]
         L.dg_cg_solve.argtypes = [pd, ctypes.POINTER(CgOpts), vp, vp, ctypes.POINTER(CgReport), vp]
         L.dg_mass_pcg_solve.argtypes = [pd, ctypes.c_int32, ctypes.c_double, vp, vp, vp, vp, ctypes.c_double,
@@ -88,7 +90,7 @@ def lib():
         L.dg_last_error.argtypes = []
         L.dg_last_error.restype = ctypes.c_char_p
         for name in ("dg_apply_laplace", "dg_apply_convective", "dg_vjp_convective", "dg_apply_divergence",
-                     "dg_apply_inverse_mass", "dg_apply_helmholtz", "dg_apply_projection", "dg_apply_gradient", "dg_prolongate", "dg_restrict", "dg_cg_solve", "dg_mass_pcg_solve", "dg_laplace_diagonal", "dg_lgl_nodes"):
+                     "dg_apply_inverse_mass", "dg_apply_helmholtz", "dg_apply_projection", "dg_apply_gradient", "dg_prolongate", "dg_restrict", "dg_gmg_vcycle", "dg_cg_solve", "dg_mass_pcg_solve", "dg_laplace_diagonal", "dg_lgl_nodes"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -259,6 +261,23 @@ def restrict(coarse, rf, out=None):
         raise TypeError("out must have the dtype of rf")
     _check(lib().dg_restrict(ctypes.byref(coarse), _dtype_code(rf), ctypes.c_void_p(rf.data_ptr()),
                              ctypes.c_void_p(out.data_ptr()), _stream(rf)))
+    return out
+
+
+def gmg_vcycle(desc, r, lambda_max, degree=5, smoothing_range=20.0, coarse_degree=10, out=None):
+    """z = V r, one FP64 V-cycle; lambda_max: one bound of D^-1 A per level (finest first)."""
+    torch = _torch()
+    shape = (_nel(desc), (desc.degree + 1) ** 3)
+    _check_tensor(r, "r", shape)
+    if r.dtype != torch.float64:
+        raise TypeError("r must be float64")
+    if out is None:
+        out = torch.empty_like(r)
+    _check_tensor(out, "out", shape)
+    lam = np.ascontiguousarray(lambda_max, dtype=np.float64)
+    _check(lib().dg_gmg_vcycle(ctypes.byref(desc), int(len(lam)), int(degree), float(smoothing_range),
+                               int(coarse_degree), lam.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                               ctypes.c_void_p(r.data_ptr()), ctypes.c_void_p(out.data_ptr()), _stream(r)))
     return out
 
 
