@@ -237,7 +237,7 @@ def oracle_rows(args, budget=0.15):
     return out
 
 
-def extras(torch, dgmf, inputs, dev, args, which=("vjp", "cg", "mass", "proj", "mpcg", "grad", "xfer")):
+def extras(torch, dgmf, inputs, dev, args, which=("vjp", "cg", "mass", "proj", "mpcg", "grad", "xfer", "vcycle")):
     out = {}
     # inverse mass (element-local, memory bound) and the projection-step
     # operator (M + A_D + A_C, three components, seeded per-element penalty
@@ -245,6 +245,8 @@ def extras(torch, dgmf, inputs, dev, args, which=("vjp", "cg", "mass", "proj", "
     if "mass" in which:
         out["inverse_mass_sweep"] = _sweep_extra(torch, dgmf, dev, args, 1, 102, lambda d, x, y, tau:
                                                  dgmf.apply_inverse_mass(d, x, y))
+    if "vcycle" in which:
+        out["vcycle_k7_24cubed"] = _vcycle_extra(torch, dgmf, inputs, dev)
     if "xfer" in which:
         out["transfer_sweep"] = _xfer_sweep(torch, dgmf, dev, args)
     if "grad" in which:
@@ -362,6 +364,37 @@ def mass_pcg_extra(torch, dgmf, inputs, dev, k=5, N=16):
                                           "true_rel_res": rep["true_rel_res"],
                                           "hbm_frac_per_iteration": 112 * dofs / per_it / (HBM_PEAK_GBS * 1e9)}
     return res
+
+
+def _vcycle_extra(torch, dgmf, inputs, dev, k=7, N=24, levels=4, reps=5):
+    """One FP64 V-cycle on the pressure Poisson size (k=7, 24^3 -> 12^3 ->
+    6^3 -> 3^3), Chebyshev degree 5, coarse degree 10.  The per-level bounds
+    of D^-1 A come from the library's own Lanczos estimate (the setup of
+    dg_cg_solve with the Chebyshev preconditioner, one iteration, on each
+    level).  Wall time per cycle includes the cycle's set-up (level
+    diagonals, work vectors) and its final synchronisation."""
+    lam = []
+    for l in range(levels):
+        dl = dgmf.make_desc(k, N >> l)
+        g = torch.Generator(device=dev)
+        g.manual_seed(107 + l)
+        b = torch.rand(((N >> l) ** 3, (k + 1) ** 3), generator=g, dtype=torch.float64, device=dev) - 0.5
+        b -= b.mean()
+        _, rep, _ = dgmf.cg_solve(dl, b, precond=dgmf.DG_PC_CHEB_F32, max_iter=1)
+        lam.append(rep["lambda_max"])
+    d = dgmf.make_desc(k, N)
+    g = torch.Generator(device=dev)
+    g.manual_seed(108)
+    r = torch.rand((N ** 3, (k + 1) ** 3), generator=g, dtype=torch.float64, device=dev) - 0.5
+    r -= r.mean()
+    z = dgmf.gmg_vcycle(d, r, lam)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        dgmf.gmg_vcycle(d, r, lam, out=z)
+    t = (time.perf_counter() - t0) / reps
+    return {"levels": levels, "lambda_max": lam, "ms_per_cycle": t * 1e3,
+            "fine_operator_applications": 2 * (5 - 1) + 2}
 
 
 def _xfer_sweep(torch, dgmf, dev, args):
@@ -501,7 +534,7 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--sweep-out", default="")
     ap.add_argument("--extras-only", default="",
-                    help="diagnostic: run only these extras (vjp,cg,mass,proj,mpcg,grad,xfer), print them as one JSON line, no sweep")
+                    help="diagnostic: run only these extras (vjp,cg,mass,proj,mpcg,grad,xfer,vcycle), print them as one JSON line, no sweep")
     ap.add_argument("--calib-copy", type=int, default=0,
                     help="also run one plain device copy of this many bytes (counter calibration)")
     args = ap.parse_args()

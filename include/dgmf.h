@@ -6,7 +6,7 @@
  * Legendre-Gauss-Lobatto (LGL) nodes of degree k and Gauss quadrature, and
  * the preconditioned CG solver, the inverse mass matrix, the Helmholtz
  * operator, the projection-step operator and its inverse-mass-preconditioned
- * solve, and the h-multigrid level transfers of Sec. 3.3.  All compute runs
+ * solve, and the h-multigrid level transfers and V-cycle of Sec. 3.3.  All compute runs
  * in HIP kernels for gfx950.
  *
  * Mesh and layout (every entry point)
