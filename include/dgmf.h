@@ -282,6 +282,20 @@ int dg_gmg_vcycle(const dg_op_desc* desc, int32_t levels, int32_t degree, double
                   int32_t coarse_degree, const double* lambda_max, const double* r, double* z, void* hip_stream);
 
 /*
+ * Solve A x = b with the SIPG form (n_comp = 1, periodic: b and the
+ * iterates are taken at zero coefficient mean) by FP64 CG preconditioned with
+ * one dg_gmg_vcycle per iteration (Sec. 3.3: Chebyshev degree 5, smoothing
+ * range 20, coarse Chebyshev of degree 10), flexible beta.
+ *   lambda_max: host array of `levels` bounds as for dg_gmg_vcycle; b, x:
+ *   [N_el][n^3] doubles (device), x: initial guess in, solution out; stops
+ *   when |r| <= rtol |b - mean(b)|; report: host pointer, may be NULL.
+ * Returns DG_OK, DG_NOT_CONVERGED or DG_ERR_BREAKDOWN, or a negative error.
+ * Blocks the calling thread.
+ */
+int dg_gmg_cg_solve(const dg_op_desc* desc, int32_t levels, const double* lambda_max, const double* b, double* x,
+                    double rtol, int32_t max_iter, dg_cg_report* report, void* hip_stream);
+
+/*
  * diag(A) of the SIPG form on one element (identical on every element of a
  * uniform periodic mesh with at least 2 elements per direction): host array of
  * n^3 doubles.  Setup for the Jacobi and Chebyshev preconditioners (Sec. 3.3:

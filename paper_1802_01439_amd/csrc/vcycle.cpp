@@ -14,6 +14,8 @@
 // in its three-term form; its scalars are formed on the host.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <vector>
 
@@ -107,9 +109,12 @@ struct MgRun {
 
 using namespace dgmf;
 
-extern "C" int dg_gmg_vcycle(const dg_op_desc* desc, int32_t levels, int32_t degree, double smoothing_range,
-                             int32_t coarse_degree, const double* lambda_max, const double* r, double* z,
-                             void* hip_stream) {
+namespace dgmf {
+namespace {
+
+// validation and level set-up shared by the cycle and the solver
+int mg_setup(MgRun& M, const dg_op_desc* desc, int levels, int degree, double smoothing_range, int coarse_degree,
+             const double* lambda_max, hipStream_t s) {
   int rc = validate_desc(desc);
   if (rc) return rc;
   if (desc->n_comp != 1) return fail(DG_ERR_INVALID_ARG, "the V-cycle needs n_comp = 1");
@@ -117,7 +122,7 @@ extern "C" int dg_gmg_vcycle(const dg_op_desc* desc, int32_t levels, int32_t deg
   if (degree < 1 || coarse_degree < 1) return fail(DG_ERR_INVALID_ARG, "smoother degrees must be >= 1");
   if (!(smoothing_range > 1.0) || !std::isfinite(smoothing_range))
     return fail(DG_ERR_INVALID_ARG, "smoothing_range must be finite and > 1");
-  if (!lambda_max || !r || !z) return fail(DG_ERR_INVALID_ARG, "lambda_max/r/z is NULL");
+  if (!lambda_max) return fail(DG_ERR_INVALID_ARG, "lambda_max is NULL");
   if (desc->n_q != 0 && desc->n_q < desc->degree + 1)
     return fail(DG_ERR_UNSUPPORTED, "the Laplace form needs n_q >= k+1 (exact Gauss integration)");
   for (int l = 0; l < levels; ++l)
@@ -126,15 +131,12 @@ extern "C" int dg_gmg_vcycle(const dg_op_desc* desc, int32_t levels, int32_t deg
   for (int d = 0; d < 3; ++d)
     if (desc->n_el[d] % (1 << (levels - 1)) != 0)
       return fail(DG_ERR_INVALID_ARG, "element counts must be divisible by 2^(levels-1)");
-  const long long n0 = num_elements(desc) * dofs_per_element(desc);
-  if (overlaps(r, (size_t)n0 * 8, z, (size_t)n0 * 8)) return fail(DG_ERR_ALIAS, "z overlaps r");
-  MgRun M;
   M.k = desc->degree;
   M.n3 = (int)dofs_per_element(desc);
   M.degree = degree;
   M.coarse_degree = coarse_degree;
   M.range = smoothing_range;
-  M.s = (hipStream_t)hip_stream;
+  M.s = s;
   M.P0 = child_interp(M.k, 0);
   M.P1 = child_interp(M.k, 1);
   M.lv.resize(levels);
@@ -158,9 +160,154 @@ extern "C" int dg_gmg_vcycle(const dg_op_desc* desc, int32_t levels, int32_t deg
       if ((e = M.alloc(bufs[i], L.n)) != hipSuccess) return hip_fail(e, "V-cycle work vectors");
     if (l > 0 && (e = M.alloc(&L.x, L.n)) != hipSuccess) return hip_fail(e, "V-cycle work vectors");
   }
+  return DG_OK;
+}
+
+}  // namespace
+}  // namespace dgmf
+
+extern "C" int dg_gmg_vcycle(const dg_op_desc* desc, int32_t levels, int32_t degree, double smoothing_range,
+                             int32_t coarse_degree, const double* lambda_max, const double* r, double* z,
+                             void* hip_stream) {
+  if (!r || !z) return fail(DG_ERR_INVALID_ARG, "r/z is NULL");
+  MgRun M;
+  int rc = mg_setup(M, desc, levels, degree, smoothing_range, coarse_degree, lambda_max, (hipStream_t)hip_stream);
+  if (rc) return rc;
+  const long long n0 = M.lv[0].n;
+  if (overlaps(r, (size_t)n0 * 8, z, (size_t)n0 * 8)) return fail(DG_ERR_ALIAS, "z overlaps r");
   M.lv[0].b = const_cast<double*>(r);   // read only
   M.lv[0].x = z;
+  hipError_t e;
   if ((e = M.cycle(0)) != hipSuccess) return hip_fail(e, "V-cycle launch");
   if ((e = hipStreamSynchronize(M.s)) != hipSuccess) return hip_fail(e, "V-cycle");
+  return ok();
+}
+
+// FP64 CG preconditioned by one V-cycle per iteration, for the periodic
+// pressure Poisson equation (Sec. 3.3): residual and preconditioned residual
+// kept at zero coefficient mean, flexible (Polak-Ribiere) beta as in the
+// Chebyshev-preconditioned CG.  Scalars go through the host (a few reads per
+// iteration); the level vectors are set up once per solve.
+extern "C" int dg_gmg_cg_solve(const dg_op_desc* desc, int32_t levels, const double* lambda_max, const double* b,
+                               double* x, double rtol, int32_t max_iter, dg_cg_report* report, void* hip_stream) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (!b || !x) return fail(DG_ERR_INVALID_ARG, "b/x is NULL");
+  if (!(rtol > 0.0) || !std::isfinite(rtol)) return fail(DG_ERR_INVALID_ARG, "rtol must be finite and > 0");
+  if (max_iter < 0) return fail(DG_ERR_INVALID_ARG, "max_iter must be >= 0");
+  MgRun M;
+  int rc = mg_setup(M, desc, levels, 5, 20.0, 10, lambda_max, (hipStream_t)hip_stream);
+  if (rc) return rc;
+  const long long n = M.lv[0].n;
+  if (overlaps(b, (size_t)n * 8, x, (size_t)n * 8)) return fail(DG_ERR_ALIAS, "x overlaps b");
+  hipStream_t s = M.s;
+  hipError_t e;
+  double *r, *z, *zold, *p, *q, *ones, *partial, *res, *host;
+#define GMG_CHECK(call, what)                                 \
+  do {                                                        \
+    if ((e = (call)) != hipSuccess) return hip_fail(e, what); \
+  } while (0)
+  GMG_CHECK(M.alloc(&r, n), "work vectors");
+  GMG_CHECK(M.alloc(&z, n), "work vectors");
+  GMG_CHECK(M.alloc(&zold, n), "work vectors");
+  GMG_CHECK(M.alloc(&p, n), "work vectors");
+  GMG_CHECK(M.alloc(&q, n), "work vectors");
+  GMG_CHECK(M.alloc(&ones, n), "work vectors");
+  GMG_CHECK(M.alloc(&partial, 4LL * kCgBlocks), "work vectors");
+  GMG_CHECK(M.alloc(&res, 4), "work vectors");
+  GMG_CHECK(hipHostMalloc((void**)&host, 4 * sizeof(double), 0), "pinned results");
+  struct HostFree {
+    double* h;
+    ~HostFree() { (void)hipHostFree(h); }
+  } host_free{host};
+  auto sums = [&](int nq) -> hipError_t {
+    hipError_t er;
+    if ((er = cg_finalize(partial, nq, res, s)) != hipSuccess) return er;
+    if ((er = hipMemcpyAsync(host, res, nq * sizeof(double), hipMemcpyDeviceToHost, s)) != hipSuccess) return er;
+    return hipStreamSynchronize(s);
+  };
+  const LaplacePlan& A = M.lv[0].plan;
+  const double dn = (double)n;
+  // z = V r, projected on zero mean
+  auto precond = [&]() -> hipError_t {
+    hipError_t er;
+    M.lv[0].b = r;
+    M.lv[0].x = z;
+    if ((er = M.cycle(0)) != hipSuccess) return er;
+    if ((er = cg_dot(z, ones, n, partial, s)) != hipSuccess) return er;
+    if ((er = sums(1)) != hipSuccess) return er;
+    return cg_axpb(z, z, 1.0, -host[0] / dn, n, s);
+  };
+  const auto t1 = std::chrono::steady_clock::now();
+  GMG_CHECK(cg_fill(ones, 1.0, n, s), "fill");
+  int matvec = 0, it = 0, status = DG_OK;
+  GMG_CHECK(launch_laplace(A, false, x, q, s), "operator launch");
+  ++matvec;
+  GMG_CHECK(cg_residual(b, q, r, n, partial, s), "residual");
+  GMG_CHECK(sums(4), "sums");
+  const double bb = host[3] - host[2] * host[2] / dn;   // |b - mean(b)|^2
+  double rr = host[1] - host[0] * host[0] / dn;
+  GMG_CHECK(cg_axpb(r, r, 1.0, -host[0] / dn, n, s), "projection");
+  const double tol2 = rtol * rtol * bb;
+  if (bb > 0.0 && rr > tol2) {
+    GMG_CHECK(precond(), "V-cycle");
+    GMG_CHECK(cg_dot(r, z, n, partial, s), "dot");
+    GMG_CHECK(sums(1), "sums");
+    double rz = host[0];
+    GMG_CHECK(cg_axpb(p, z, 1.0, 0.0, n, s), "copy");
+    for (;;) {
+      if (it >= max_iter) {
+        status = DG_NOT_CONVERGED;
+        break;
+      }
+      GMG_CHECK(launch_laplace(A, false, p, q, s), "operator launch");
+      ++matvec;
+      GMG_CHECK(cg_dot(p, q, n, partial, s), "dot");
+      GMG_CHECK(sums(1), "sums");
+      const double pq = host[0];
+      if (!(pq > 0.0) || !(rz > 0.0)) {
+        status = DG_ERR_BREAKDOWN;
+        break;
+      }
+      GMG_CHECK(cg_update_xr(x, r, p, q, rz / pq, n, partial, s), "update");
+      GMG_CHECK(sums(1), "sums");
+      GMG_CHECK(cg_axpb(r, r, 1.0, -host[0] / dn, n, s), "projection");
+      GMG_CHECK(cg_dot(r, r, n, partial, s), "dot");
+      GMG_CHECK(sums(1), "sums");
+      rr = host[0];
+      ++it;
+      if (rr <= tol2) break;
+      GMG_CHECK(cg_axpb(zold, z, 1.0, 0.0, n, s), "copy");
+      GMG_CHECK(precond(), "V-cycle");
+      GMG_CHECK(cg_dot(r, z, n, partial, s), "dot");
+      GMG_CHECK(cg_dot(r, zold, n, partial + kCgBlocks, s), "dot");
+      GMG_CHECK(sums(2), "sums");
+      const double rz_new = host[0];
+      GMG_CHECK(cg_xpby(p, z, (rz_new - host[1]) / rz, n, s), "direction update");
+      rz = rz_new;
+    }
+  } else if (bb == 0.0) {
+    GMG_CHECK(cg_fill(x, 0.0, n, s), "fill");
+    rr = 0.0;
+  }
+  const auto t2 = std::chrono::steady_clock::now();
+  if (report) {
+    GMG_CHECK(launch_laplace(A, false, x, q, s), "operator launch");
+    ++matvec;
+    GMG_CHECK(cg_residual(b, q, z, n, partial, s), "residual");
+    GMG_CHECK(sums(4), "sums");
+    const double true_rr = host[1] - host[0] * host[0] / dn;
+    const double bn = std::sqrt(bb);
+    report->iterations = it;
+    report->matvec_f64 = matvec;
+    report->matvec_f32 = 0;
+    report->rel_res = bn > 0 ? std::sqrt(std::max(rr, 0.0)) / bn : 0.0;
+    report->true_rel_res = bn > 0 ? std::sqrt(std::max(true_rr, 0.0)) / bn : 0.0;
+    report->lambda_max = lambda_max[0];
+    report->seconds_solve = std::chrono::duration<double>(t2 - t1).count();
+    report->seconds_setup = std::chrono::duration<double>(t1 - t0).count();
+  }
+#undef GMG_CHECK
+  if (status == DG_ERR_BREAKDOWN) return fail(DG_ERR_BREAKDOWN, "p.Ap <= 0");
+  if (status == DG_NOT_CONVERGED) return fail(DG_NOT_CONVERGED, "max_iter reached");
   return ok();
 }

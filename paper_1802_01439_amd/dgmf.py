@@ -25,7 +25,7 @@ DG_PC_JACOBI_F64, DG_PC_CHEB_F32 = 0, 1
 DG_OP_HELMHOLTZ, DG_OP_PROJECTION = 0, 1
 
 EXPORTS = ("dg_apply_laplace", "dg_apply_convective", "dg_vjp_convective", "dg_apply_divergence",
-           "dg_apply_inverse_mass", "dg_apply_helmholtz", "dg_apply_projection", "dg_apply_gradient", "dg_prolongate", "dg_restrict", "dg_gmg_vcycle", "dg_cg_solve", "dg_mass_pcg_solve", "dg_laplace_diagonal", "dg_lgl_nodes", "dg_error_string", "dg_last_error")
+           "dg_apply_inverse_mass", "dg_apply_helmholtz", "dg_apply_projection", "dg_apply_gradient", "dg_prolongate", "dg_restrict", "dg_gmg_vcycle", "dg_gmg_cg_solve", "dg_cg_solve", "dg_mass_pcg_solve", "dg_laplace_diagonal", "dg_lgl_nodes", "dg_error_string", "dg_last_error")
 
 
 class OpDesc(ctypes.Structure):
@@ -79,6 +79,8 @@ def lib():
         L.dg_prolongate.argtypes = [pd, ctypes.c_int, vp, vp, vp]
         L.dg_gmg_vcycle.argtypes = [pd, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
                                      ctypes.POINTER(ctypes.c_double), vp, vp, vp]
+        L.dg_gmg_cg_solve.argtypes = [pd, ctypes.c_int32, ctypes.POINTER(ctypes.c_double), vp, vp, ctypes.c_double,
+                                       ctypes.c_int32, ctypes.POINTER(CgReport), vp]
         L.dg_restrict.argtypes = [pd, ctypes.c_int, vp, vp, vp]
         L.dg_cg_solve.argtypes = [pd, ctypes.POINTER(CgOpts), vp, vp, ctypes.POINTER(CgReport), vp]
         L.dg_mass_pcg_solve.argtypes = [pd, ctypes.c_int32, ctypes.c_double, vp, vp, vp, vp, ctypes.c_double,
@@ -90,7 +92,7 @@ def lib():
         L.dg_last_error.argtypes = []
         L.dg_last_error.restype = ctypes.c_char_p
         for name in ("dg_apply_laplace", "dg_apply_convective", "dg_vjp_convective", "dg_apply_divergence",
-                     "dg_apply_inverse_mass", "dg_apply_helmholtz", "dg_apply_projection", "dg_apply_gradient", "dg_prolongate", "dg_restrict", "dg_gmg_vcycle", "dg_cg_solve", "dg_mass_pcg_solve", "dg_laplace_diagonal", "dg_lgl_nodes"):
+                     "dg_apply_inverse_mass", "dg_apply_helmholtz", "dg_apply_projection", "dg_apply_gradient", "dg_prolongate", "dg_restrict", "dg_gmg_vcycle", "dg_gmg_cg_solve", "dg_cg_solve", "dg_mass_pcg_solve", "dg_laplace_diagonal", "dg_lgl_nodes"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -279,6 +281,26 @@ def gmg_vcycle(desc, r, lambda_max, degree=5, smoothing_range=20.0, coarse_degre
                                int(coarse_degree), lam.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                ctypes.c_void_p(r.data_ptr()), ctypes.c_void_p(out.data_ptr()), _stream(r)))
     return out
+
+
+def gmg_cg_solve(desc, b, lambda_max, x=None, rtol=1e-10, max_iter=200):
+    """FP64 CG with one V-cycle per iteration (periodic: zero-mean iterates);
+    returns (x, report dict, return code)."""
+    torch = _torch()
+    shape = (_nel(desc), (desc.degree + 1) ** 3)
+    _check_tensor(b, "b", shape)
+    if b.dtype != torch.float64:
+        raise TypeError("b must be float64")
+    if x is None:
+        x = torch.zeros_like(b)
+    _check_tensor(x, "x", shape)
+    lam = np.ascontiguousarray(lambda_max, dtype=np.float64)
+    rep = CgReport()
+    rc = _check(lib().dg_gmg_cg_solve(ctypes.byref(desc), int(len(lam)),
+                                      lam.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                      ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(x.data_ptr()), float(rtol),
+                                      int(max_iter), ctypes.byref(rep), _stream(b)), soft_ok=True)
+    return x, rep.as_dict(), rc
 
 
 def apply_helmholtz(desc, u, mass_factor, out=None):

@@ -56,3 +56,55 @@ def test_vcycle_rejects_bad_arguments():
         dgmf.gmg_vcycle(d, r, [1.0, -1.0])
     with pytest.raises(dgmf.DgError):      # z aliases r
         dgmf.gmg_vcycle(d, r, [1.0, 1.0], out=r)
+
+
+def test_vcycle_pcg_matches_the_oracle():
+    # CG with one V-cycle per iteration on 8^3, k = 3, three levels: the same
+    # iteration count (within one) and solution as the oracle's flexible PCG
+    from oracle.solvers import pcg
+    k, fine, levels = 3, M.cube(8), 3
+    lam = _lams(k, fine, levels, 1.0, 1.0)
+    b = inputs.uniform((fine.N, (k + 1) ** 3), seed=1120)
+    b -= b.mean()
+    announce("V-cycle PCG k=3 8^3 levels=3")
+    x, rep, rc = dgmf.gmg_cg_solve(dgmf.make_desc(k, 8), to_dev(b), lam, rtol=1e-10)
+    assert rc == dgmf.DG_OK, rep
+    xr, info = pcg(lambda v: laplace_apply(v, k, fine), b, precond=lambda r: vcycle(r, k, fine, levels, lam),
+                   rtol=1e-10, project=True)
+    xs = x.cpu().numpy()
+    xs -= xs.mean()
+    xr -= xr.mean()
+    assert abs(rep["iterations"] - info["iterations"]) <= 1, (rep["iterations"], info["iterations"])
+    assert rel_err(xs, xr) < 1e-8
+    assert rep["true_rel_res"] < 1e-9
+
+
+def test_vcycle_pcg_config5_against_fdm():
+    # the pressure Poisson problem at k = 7 on 24^3 (four levels down to 3^3),
+    # rhs = d_h(TGV + noise) with zero mean, 1e-10: the paper's GMG-preconditioned
+    # CG needs 6-12 iterations; bounds of D^-1 A from the library's own
+    # estimate (dg_cg_solve's set-up)
+    from oracle import basis
+    from oracle.divergence import poisson_rhs
+    from oracle.solvers import fdm_solve
+    k, N, levels = 7, 24, 4
+    msh = M.cube(N)
+    u = inputs.tgv_plus_noise(basis.lgl_nodes(k), msh.n_el, msh.length, seed=inputs.FIELD_SEED_BASE + 4)
+    b = poisson_rhs(u, k, msh)
+    x_ref = fdm_solve(b, k, msh)
+    x_ref -= x_ref.mean()
+    lam = []
+    for l in range(levels):
+        dl = dgmf.make_desc(k, N >> l)
+        bl = to_dev(inputs.uniform(((N >> l) ** 3, (k + 1) ** 3), seed=1130 + l))
+        bl -= bl.mean()
+        _, rl, _ = dgmf.cg_solve(dl, bl, precond=dgmf.DG_PC_CHEB_F32, max_iter=1)
+        lam.append(rl["lambda_max"])
+    announce(f"V-cycle PCG config 5, lambda_max {lam}")
+    x, rep, rc = dgmf.gmg_cg_solve(dgmf.make_desc(k, N), to_dev(b), lam, rtol=1e-10)
+    assert rc == dgmf.DG_OK, rep
+    xs = x.cpu().numpy()
+    xs -= xs.mean()
+    assert np.linalg.norm(xs - x_ref) / np.linalg.norm(x_ref) < 1e-7
+    assert rep["true_rel_res"] < 1e-9 and rep["iterations"] <= 20, rep
+    announce(f"V-cycle PCG config 5 report {rep}")
