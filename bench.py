@@ -313,6 +313,24 @@ def extras(torch, dgmf, inputs, dev, args, which=("vjp", "cg", "mass", "proj", "
             rep["rc"] = rc
             res[name] = rep
         res["speedup_solve"] = res["jacobi_f64"]["seconds_solve"] / res["chebyshev5_f32"]["seconds_solve"]
+        # CG with one FP64 V-cycle per iteration (24^3 -> 3^3, four levels);
+        # level bounds of D^-1 A from dg_cg_solve's own set-up on each level
+        lam = []
+        for l in range(4):
+            dl = dgmf.make_desc(k, N >> l)
+            g = torch.Generator(device=dev)
+            g.manual_seed(109 + l)
+            bl = torch.rand(((N >> l) ** 3, (k + 1) ** 3), generator=g, dtype=torch.float64, device=dev) - 0.5
+            bl -= bl.mean()
+            _, rl, _ = dgmf.cg_solve(dl, bl, precond=dgmf.DG_PC_CHEB_F32, max_iter=1)
+            lam.append(rl["lambda_max"])
+        for rtol in (1e-10, 1e-6):
+            dgmf.gmg_cg_solve(d, b, lam, rtol=rtol)       # warm-up
+            x, rep, rc = dgmf.gmg_cg_solve(d, b, lam, rtol=rtol)
+            rep["rc"] = rc
+            res[f"gmg_vcycle_f64_rtol{rtol:g}"] = rep
+        res["speedup_gmg_vs_jacobi"] = (res["jacobi_f64"]["seconds_solve"]
+                                        / res["gmg_vcycle_f64_rtol1e-10"]["seconds_solve"])
         out["cg_k7_24cubed"] = res
     except _Skip:
         pass
