@@ -111,7 +111,7 @@ __global__ void __launch_bounds__(kThreads) k_update_p(double* __restrict__ z, d
   for (long long i = blockIdx.x * (long long)kThreads + threadIdx.x; i < n; i += (long long)gridDim.x * kThreads) {
     const double zi = z[i] - mu_z;
     zold[i] = zi;
-    p[i] = zi + beta * p[i];
+    p[i] = beta != 0.0 ? zi + beta * p[i] : zi;   // a zero beta never reads the old direction
   }
 }
 
@@ -138,7 +138,7 @@ __global__ void __launch_bounds__(kThreads) k_hash_fill(double* __restrict__ v, 
 __global__ void __launch_bounds__(kThreads) k_xpby(double* __restrict__ y, const double* __restrict__ x, double b,
                                                    long long n) {
   for (long long i = blockIdx.x * (long long)kThreads + threadIdx.x; i < n; i += (long long)gridDim.x * kThreads)
-    y[i] = x[i] + b * y[i];
+    y[i] = b != 0.0 ? x[i] + b * y[i] : x[i];
 }
 
 __global__ void __launch_bounds__(kThreads) k_axpb(double* __restrict__ y, const double* __restrict__ x, double a,
@@ -307,16 +307,20 @@ __global__ void __launch_bounds__(kThreads) k_update_p_jacobi(const double* __re
                                                               const double* __restrict__ dinv, int n3,
                                                               const double* __restrict__ st, long long n) {
   const double mu = st[kMuR], muz = st[kMuZ], beta = st[kBeta];
-  for (long long i = blockIdx.x * (long long)kThreads + threadIdx.x; i < n; i += (long long)gridDim.x * kThreads)
-    p[i] = fma(dinv[i % n3], r[i] - mu, -muz) + beta * p[i];
+  for (long long i = blockIdx.x * (long long)kThreads + threadIdx.x; i < n; i += (long long)gridDim.x * kThreads) {
+    const double zi = fma(dinv[i % n3], r[i] - mu, -muz);
+    p[i] = beta != 0.0 ? zi + beta * p[i] : zi;   // a zero beta never reads the old direction
+  }
 }
 
 // p = (z - mu_z) + beta p, z the FP32 smoother output
 __global__ void __launch_bounds__(kThreads) k_update_p_cheb(const float* __restrict__ z, double* __restrict__ p,
                                                             const double* __restrict__ st, long long n) {
   const double muz = st[kMuZ], beta = st[kBeta];
-  for (long long i = blockIdx.x * (long long)kThreads + threadIdx.x; i < n; i += (long long)gridDim.x * kThreads)
-    p[i] = ((double)z[i] - muz) + beta * p[i];
+  for (long long i = blockIdx.x * (long long)kThreads + threadIdx.x; i < n; i += (long long)gridDim.x * kThreads) {
+    const double zi = (double)z[i] - muz;
+    p[i] = beta != 0.0 ? zi + beta * p[i] : zi;
+  }
 }
 
 // Chebyshev degree 1 (no operator apply): z = D^-1 r' / theta and the

@@ -78,7 +78,7 @@ __global__ void __launch_bounds__(kThreads) k_mp_xpby(double* __restrict__ p, co
                                                       const double* __restrict__ st, long long n) {
   const double beta = st[kBeta];
   for (long long i = blockIdx.x * (long long)kThreads + threadIdx.x; i < n; i += (long long)gridDim.x * kThreads)
-    p[i] = z[i] + beta * p[i];
+    p[i] = beta != 0.0 ? z[i] + beta * p[i] : z[i];
 }
 
 }  // namespace

@@ -128,6 +128,12 @@ def test_cg_error_paths():
     bn[0, 0] = float("nan")
     x, rep, rc = dgmf.cg_solve(d, bn, precond=dgmf.DG_PC_JACOBI_F64)
     assert rc == dgmf.DG_ERR_BREAKDOWN
+    # the breakdown leaves non-finite values in the solver's work vectors; the
+    # next solves (which start from p = z, beta = 0) must not read them
+    for pc in (dgmf.DG_PC_JACOBI_F64, dgmf.DG_PC_CHEB_F32):
+        announce(f"cg after a breakdown, preconditioner {pc}")
+        x, rep, rc = dgmf.cg_solve(d, b, precond=pc, rtol=1e-10)
+        assert rc == dgmf.DG_OK and rep["true_rel_res"] < 1e-9, rep
     announce("cg negative penalty")
     dneg = dgmf.make_desc(k, N, penalty_factor=-1.0)
     x, rep, rc = dgmf.cg_solve(dneg, b, precond=dgmf.DG_PC_JACOBI_F64)
