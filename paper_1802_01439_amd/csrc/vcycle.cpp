@@ -113,8 +113,9 @@ namespace dgmf {
 namespace {
 
 // validation and level set-up shared by the cycle and the solver
+// in, out: the finest-level input and output, which must not overlap
 int mg_setup(MgRun& M, const dg_op_desc* desc, int levels, int degree, double smoothing_range, int coarse_degree,
-             const double* lambda_max, hipStream_t s) {
+             const double* lambda_max, hipStream_t s, const double* in, const double* out) {
   int rc = validate_desc(desc);
   if (rc) return rc;
   if (desc->n_comp != 1) return fail(DG_ERR_INVALID_ARG, "the V-cycle needs n_comp = 1");
@@ -131,6 +132,8 @@ int mg_setup(MgRun& M, const dg_op_desc* desc, int levels, int degree, double sm
   for (int d = 0; d < 3; ++d)
     if (desc->n_el[d] % (1 << (levels - 1)) != 0)
       return fail(DG_ERR_INVALID_ARG, "element counts must be divisible by 2^(levels-1)");
+  const size_t bytes = (size_t)num_elements(desc) * dofs_per_element(desc) * 8;
+  if (overlaps(in, bytes, out, bytes)) return fail(DG_ERR_ALIAS, "the output overlaps the input");
   M.k = desc->degree;
   M.n3 = (int)dofs_per_element(desc);
   M.degree = degree;
@@ -170,11 +173,12 @@ extern "C" int dg_gmg_vcycle(const dg_op_desc* desc, int32_t levels, int32_t deg
                              int32_t coarse_degree, const double* lambda_max, const double* r, double* z,
                              void* hip_stream) {
   if (!r || !z) return fail(DG_ERR_INVALID_ARG, "r/z is NULL");
-  MgRun M;
-  int rc = mg_setup(M, desc, levels, degree, smoothing_range, coarse_degree, lambda_max, (hipStream_t)hip_stream);
+  int rc = validate_desc(desc);
   if (rc) return rc;
-  const long long n0 = M.lv[0].n;
-  if (overlaps(r, (size_t)n0 * 8, z, (size_t)n0 * 8)) return fail(DG_ERR_ALIAS, "z overlaps r");
+  // every argument is checked before the set-up allocates anything
+  MgRun M;
+  rc = mg_setup(M, desc, levels, degree, smoothing_range, coarse_degree, lambda_max, (hipStream_t)hip_stream, r, z);
+  if (rc) return rc;
   M.lv[0].b = const_cast<double*>(r);   // read only
   M.lv[0].x = z;
   hipError_t e;
@@ -195,10 +199,9 @@ extern "C" int dg_gmg_cg_solve(const dg_op_desc* desc, int32_t levels, const dou
   if (!(rtol > 0.0) || !std::isfinite(rtol)) return fail(DG_ERR_INVALID_ARG, "rtol must be finite and > 0");
   if (max_iter < 0) return fail(DG_ERR_INVALID_ARG, "max_iter must be >= 0");
   MgRun M;
-  int rc = mg_setup(M, desc, levels, 5, 20.0, 10, lambda_max, (hipStream_t)hip_stream);
+  int rc = mg_setup(M, desc, levels, 5, 20.0, 10, lambda_max, (hipStream_t)hip_stream, b, x);
   if (rc) return rc;
   const long long n = M.lv[0].n;
-  if (overlaps(b, (size_t)n * 8, x, (size_t)n * 8)) return fail(DG_ERR_ALIAS, "x overlaps b");
   hipStream_t s = M.s;
   hipError_t e;
   double *r, *z, *zold, *p, *q, *ones, *partial, *res, *host;

@@ -109,3 +109,31 @@ def test_validation_errors_of_the_widening_entry_points_without_gpu():
     assert solve(d3, dgmf.DG_OP_PROJECTION, 0.0, None, vp(fd), fa, fb) == dgmf.DG_ERR_INVALID_ARG
     assert solve(d3, dgmf.DG_OP_PROJECTION, 0.0, vp(fc), vp(fd), fa, fa + 8) == dgmf.DG_ERR_ALIAS
     assert solve(d1, dgmf.DG_OP_HELMHOLTZ, 1.0, None, None, fa, fa) == dgmf.DG_ERR_ALIAS
+
+
+def test_validation_errors_of_the_multigrid_entry_points_without_gpu():
+    L = dgmf.lib()
+    vp = ctypes.c_void_p
+    fa, fb = 0x10000000, 0x20000000      # never dereferenced
+    lam2 = (ctypes.c_double * 2)(2.5, 2.5)
+    bad = (ctypes.c_double * 2)(2.5, float("nan"))
+    d = dgmf.make_desc(2, (8, 4, 4))
+    d6 = dgmf.make_desc(2, (6, 4, 4))
+    d3 = dgmf.make_desc(2, 4, n_comp=3)
+
+    def vc(desc, levels, lam, r, z, degree=5, rng=20.0, coarse=10):
+        return L.dg_gmg_vcycle(ctypes.byref(desc), levels, degree, rng, coarse, lam, vp(r), vp(z), None)
+    assert vc(d3, 2, lam2, fa, fb) == dgmf.DG_ERR_INVALID_ARG            # n_comp must be 1
+    assert vc(d6, 3, (ctypes.c_double * 3)(1, 1, 1), fa, fb) == dgmf.DG_ERR_INVALID_ARG   # 6 not divisible by 4
+    assert vc(d, 2, bad, fa, fb) == dgmf.DG_ERR_INVALID_ARG              # non-finite bound
+    assert vc(d, 0, lam2, fa, fb) == dgmf.DG_ERR_INVALID_ARG             # no level
+    assert vc(d, 2, lam2, fa, fb, rng=1.0) == dgmf.DG_ERR_INVALID_ARG    # smoothing range must exceed 1
+    assert vc(d, 2, lam2, fa, fa + 8) == dgmf.DG_ERR_ALIAS
+    rep = dgmf.CgReport()
+
+    def cg(desc, levels, lam, b, x, rtol=1e-10, it=10):
+        return L.dg_gmg_cg_solve(ctypes.byref(desc), levels, lam, vp(b), vp(x), rtol, it, ctypes.byref(rep), None)
+    assert cg(d, 2, lam2, fa, fb, rtol=0.0) == dgmf.DG_ERR_INVALID_ARG
+    assert cg(d, 2, lam2, fa, fb, it=-1) == dgmf.DG_ERR_INVALID_ARG
+    assert cg(d, 2, bad, fa, fb) == dgmf.DG_ERR_INVALID_ARG
+    assert cg(d, 2, lam2, fa, fa + 8) == dgmf.DG_ERR_ALIAS
