@@ -324,13 +324,16 @@ def extras(torch, dgmf, inputs, dev, args, which=("vjp", "cg", "mass", "proj", "
             bl -= bl.mean()
             _, rl, _ = dgmf.cg_solve(dl, bl, precond=dgmf.DG_PC_CHEB_F32, max_iter=1)
             lam.append(rl["lambda_max"])
-        for rtol in (1e-10, 1e-6):
-            dgmf.gmg_cg_solve(d, b, lam, rtol=rtol)       # warm-up
-            x, rep, rc = dgmf.gmg_cg_solve(d, b, lam, rtol=rtol)
-            rep["rc"] = rc
-            res[f"gmg_vcycle_f64_rtol{rtol:g}"] = rep
+        for cyc, cdt in (("f64", dgmf.DG_F64), ("f32", dgmf.DG_F32)):
+            for rtol in (1e-10, 1e-6):
+                dgmf.gmg_cg_solve(d, b, lam, rtol=rtol, cycle_dtype=cdt)       # warm-up
+                x, rep, rc = dgmf.gmg_cg_solve(d, b, lam, rtol=rtol, cycle_dtype=cdt)
+                rep["rc"] = rc
+                res[f"gmg_vcycle_{cyc}_rtol{rtol:g}"] = rep
         res["speedup_gmg_vs_jacobi"] = (res["jacobi_f64"]["seconds_solve"]
                                         / res["gmg_vcycle_f64_rtol1e-10"]["seconds_solve"])
+        res["speedup_gmg_f32_vs_jacobi"] = (res["jacobi_f64"]["seconds_solve"]
+                                            / res["gmg_vcycle_f32_rtol1e-10"]["seconds_solve"])
         out["cg_k7_24cubed"] = res
     except _Skip:
         pass

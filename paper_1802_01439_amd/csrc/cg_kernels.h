@@ -63,12 +63,20 @@ hipError_t mpcg_start(const double* partial, double* st, hipStream_t s);
 hipError_t mpcg_beta(const double* rr_partial, const double* rz_partial, int nblocks, double* st, hipStream_t s);
 hipError_t mpcg_xpby(double* p, const double* z, const double* st, long long n, hipStream_t s);
 
-// multigrid V-cycle: Chebyshev smoother steps and vector updates (FP64)
+// multigrid V-cycle: Chebyshev smoother steps and vector updates (FP64, FP32)
 hipError_t mg_cheb_first(const double* b, const double* dinv, int n3, double s, double* d, double* x, long long n,
                          hipStream_t st);
-hipError_t mg_cheb_next(const double* b, const double* t, const double* dinv, int n3, double c1, double c2, double* d,
-                        double* x, long long n, hipStream_t st);
+hipError_t mg_cheb_next(const double* b, const double* t, const double* dinv, int n3, double c1, double c2, double* d, double* x,
+                        long long n, hipStream_t st);
 hipError_t mg_sub(const double* b, const double* t, double* y, long long n, hipStream_t st);
 hipError_t mg_add(double* x, const double* t, long long n, hipStream_t st);
+hipError_t mg_cheb_first(const float* b, const float* dinv, int n3, float s, float* d, float* x, long long n,
+                         hipStream_t st);
+hipError_t mg_cheb_next(const float* b, const float* t, const float* dinv, int n3, float c1, float c2, float* d, float* x,
+                        long long n, hipStream_t st);
+hipError_t mg_sub(const float* b, const float* t, float* y, long long n, hipStream_t st);
+hipError_t mg_add(float* x, const float* t, long long n, hipStream_t st);
+hipError_t mg_convert(const double* a, float* b, long long n, hipStream_t st);
+hipError_t mg_convert(const float* a, double* b, long long n, hipStream_t st);
 
 }  // namespace dgmf

@@ -28,16 +28,20 @@ namespace dgmf {
 
 namespace {
 
+template <typename T>
 struct MgLevel {
   dg_op_desc desc{};
   LaplacePlan plan;
   long long n = 0;
   double lmax = 0;
-  double *dinv = nullptr, *b = nullptr, *x = nullptr, *t = nullptr, *d = nullptr, *res = nullptr, *e = nullptr;
+  T *dinv = nullptr, *b = nullptr, *x = nullptr, *t = nullptr, *d = nullptr, *res = nullptr, *e = nullptr;
 };
 
+// the cycle's vectors and arithmetic in T (double or float)
+template <typename T>
 struct MgRun {
-  std::vector<MgLevel> lv;
+  static constexpr bool F32 = sizeof(T) == 4;
+  std::vector<MgLevel<T>> lv;
   std::vector<void*> owned;
   int degree = 5, coarse_degree = 10, n3 = 0, k = 0;
   double range = 20.0;
@@ -47,23 +51,25 @@ struct MgRun {
   ~MgRun() {
     for (void* p : owned) (void)hipFree(p);
   }
-  hipError_t alloc(double** p, long long n) {
-    hipError_t e = hipMalloc((void**)p, (size_t)n * sizeof(double));
+  template <typename U>
+  hipError_t alloc(U** p, long long n) {
+    hipError_t e = hipMalloc((void**)p, (size_t)n * sizeof(U));
     if (e == hipSuccess) owned.push_back(*p);
     return e;
   }
 
   // x = Cheb(b) on level l (deg steps, deg - 1 operator applications)
-  hipError_t cheb(MgLevel& L, const double* b, double* x, int deg) {
+  hipError_t cheb(MgLevel<T>& L, const T* b, T* x, int deg) {
     const double lmin = L.lmax / range;
     const double theta = 0.5 * (L.lmax + lmin), delta = 0.5 * (L.lmax - lmin);
     hipError_t e;
-    if ((e = mg_cheb_first(b, L.dinv, n3, 1.0 / theta, L.d, x, L.n, s)) != hipSuccess) return e;
+    if ((e = mg_cheb_first(b, L.dinv, n3, (T)(1.0 / theta), L.d, x, L.n, s)) != hipSuccess) return e;
     double rho_prev = delta / theta;
     for (int step = 1; step < deg; ++step) {
-      if ((e = launch_laplace(L.plan, false, x, L.t, s)) != hipSuccess) return e;
+      if ((e = launch_laplace(L.plan, F32, x, L.t, s)) != hipSuccess) return e;
       const double rho = 1.0 / (2.0 * theta / delta - rho_prev);
-      if ((e = mg_cheb_next(b, L.t, L.dinv, n3, rho * rho_prev, 2.0 * rho / delta, L.d, x, L.n, s)) != hipSuccess)
+      if ((e = mg_cheb_next(b, L.t, L.dinv, n3, (T)(rho * rho_prev), (T)(2.0 * rho / delta), L.d, x, L.n, s)) !=
+          hipSuccess)
         return e;
       rho_prev = rho;
     }
@@ -71,32 +77,32 @@ struct MgRun {
   }
 
   TransferPlan transfer_plan(int coarse) const {
-    TransferPlan T;
-    T.k = k;
-    T.nxc = lv[coarse].desc.n_el[0];
-    T.nyc = lv[coarse].desc.n_el[1];
-    T.nzc = lv[coarse].desc.n_el[2];
-    T.n_comp = 1;
-    T.P[0] = P0;
-    T.P[1] = P1;
-    return T;
+    TransferPlan TP;
+    TP.k = k;
+    TP.nxc = lv[coarse].desc.n_el[0];
+    TP.nyc = lv[coarse].desc.n_el[1];
+    TP.nzc = lv[coarse].desc.n_el[2];
+    TP.n_comp = 1;
+    TP.P[0] = P0;
+    TP.P[1] = P1;
+    return TP;
   }
 
   // lv[l].x = cycle(l, lv[l].b)
   hipError_t cycle(int l) {
-    MgLevel& L = lv[l];
+    MgLevel<T>& L = lv[l];
     hipError_t e;
     const bool last = l + 1 == (int)lv.size();
     if ((e = cheb(L, L.b, L.x, last ? coarse_degree : degree)) != hipSuccess) return e;
     if (last) return hipSuccess;
-    if ((e = launch_laplace(L.plan, false, L.x, L.t, s)) != hipSuccess) return e;
+    if ((e = launch_laplace(L.plan, F32, L.x, L.t, s)) != hipSuccess) return e;
     if ((e = mg_sub(L.b, L.t, L.res, L.n, s)) != hipSuccess) return e;
-    const TransferPlan T = transfer_plan(l + 1);
-    if ((e = launch_transfer(T, false, false, L.res, lv[l + 1].b, s)) != hipSuccess) return e;
+    const TransferPlan TP = transfer_plan(l + 1);
+    if ((e = launch_transfer(TP, false, F32, L.res, lv[l + 1].b, s)) != hipSuccess) return e;
     if ((e = cycle(l + 1)) != hipSuccess) return e;
-    if ((e = launch_transfer(T, true, false, lv[l + 1].x, L.t, s)) != hipSuccess) return e;
+    if ((e = launch_transfer(TP, true, F32, lv[l + 1].x, L.t, s)) != hipSuccess) return e;
     if ((e = mg_add(L.x, L.t, L.n, s)) != hipSuccess) return e;
-    if ((e = launch_laplace(L.plan, false, L.x, L.t, s)) != hipSuccess) return e;
+    if ((e = launch_laplace(L.plan, F32, L.x, L.t, s)) != hipSuccess) return e;
     if ((e = mg_sub(L.b, L.t, L.res, L.n, s)) != hipSuccess) return e;
     if ((e = cheb(L, L.res, L.e, degree)) != hipSuccess) return e;
     return mg_add(L.x, L.e, L.n, s);
@@ -113,9 +119,11 @@ namespace dgmf {
 namespace {
 
 // validation and level set-up shared by the cycle and the solver
-// in, out: the finest-level input and output, which must not overlap
-int mg_setup(MgRun& M, const dg_op_desc* desc, int levels, int degree, double smoothing_range, int coarse_degree,
-             const double* lambda_max, hipStream_t s, const double* in, const double* out) {
+// in, out: the caller's finest-level input and output (FP64), which must not
+// overlap; own_top: the cycle allocates its own finest-level b and x (FP32)
+template <typename T>
+int mg_setup(MgRun<T>& M, const dg_op_desc* desc, int levels, int degree, double smoothing_range, int coarse_degree,
+             const double* lambda_max, hipStream_t s, const void* in, const void* out, bool own_top) {
   int rc = validate_desc(desc);
   if (rc) return rc;
   if (desc->n_comp != 1) return fail(DG_ERR_INVALID_ARG, "the V-cycle needs n_comp = 1");
@@ -145,23 +153,25 @@ int mg_setup(MgRun& M, const dg_op_desc* desc, int levels, int degree, double sm
   M.lv.resize(levels);
   hipError_t e;
   std::vector<double> diag(M.n3);
+  std::vector<T> dinv(M.n3);
   for (int l = 0; l < levels; ++l) {
-    MgLevel& L = M.lv[l];
+    MgLevel<T>& L = M.lv[l];
     L.desc = *desc;
     for (int d = 0; d < 3; ++d) L.desc.n_el[d] = desc->n_el[d] >> l;
     L.plan = make_laplace_plan(&L.desc, 1);
     L.n = num_elements(&L.desc) * M.n3;
     L.lmax = lambda_max[l];
     if ((rc = dg_laplace_diagonal(&L.desc, diag.data())) != DG_OK) return rc;
-    for (double& v : diag) v = 1.0 / v;
+    for (int i = 0; i < M.n3; ++i) dinv[i] = (T)(1.0 / diag[i]);
     if ((e = M.alloc(&L.dinv, M.n3)) != hipSuccess) return hip_fail(e, "V-cycle tables");
-    if ((e = hipMemcpyAsync(L.dinv, diag.data(), M.n3 * sizeof(double), hipMemcpyHostToDevice, M.s)) != hipSuccess)
+    if ((e = hipMemcpyAsync(L.dinv, dinv.data(), M.n3 * sizeof(T), hipMemcpyHostToDevice, M.s)) != hipSuccess)
       return hip_fail(e, "V-cycle tables");
     if ((e = hipStreamSynchronize(M.s)) != hipSuccess) return hip_fail(e, "V-cycle tables");
-    double** bufs[5] = {&L.t, &L.d, &L.res, &L.e, &L.b};
-    for (int i = 0; i < (l == 0 ? 4 : 5); ++i)
+    T** bufs[5] = {&L.t, &L.d, &L.res, &L.e, &L.b};
+    const bool top = l > 0 || own_top;
+    for (int i = 0; i < (top ? 5 : 4); ++i)
       if ((e = M.alloc(bufs[i], L.n)) != hipSuccess) return hip_fail(e, "V-cycle work vectors");
-    if (l > 0 && (e = M.alloc(&L.x, L.n)) != hipSuccess) return hip_fail(e, "V-cycle work vectors");
+    if (top && (e = M.alloc(&L.x, L.n)) != hipSuccess) return hip_fail(e, "V-cycle work vectors");
   }
   return DG_OK;
 }
@@ -176,8 +186,9 @@ extern "C" int dg_gmg_vcycle(const dg_op_desc* desc, int32_t levels, int32_t deg
   int rc = validate_desc(desc);
   if (rc) return rc;
   // every argument is checked before the set-up allocates anything
-  MgRun M;
-  rc = mg_setup(M, desc, levels, degree, smoothing_range, coarse_degree, lambda_max, (hipStream_t)hip_stream, r, z);
+  MgRun<double> M;
+  rc = mg_setup(M, desc, levels, degree, smoothing_range, coarse_degree, lambda_max, (hipStream_t)hip_stream, r, z,
+                false);
   if (rc) return rc;
   M.lv[0].b = const_cast<double*>(r);   // read only
   M.lv[0].x = z;
@@ -187,19 +198,23 @@ extern "C" int dg_gmg_vcycle(const dg_op_desc* desc, int32_t levels, int32_t deg
   return ok();
 }
 
+namespace dgmf {
+namespace {
+
 // FP64 CG preconditioned by one V-cycle per iteration, for the periodic
 // pressure Poisson equation (Sec. 3.3): residual and preconditioned residual
 // kept at zero coefficient mean, flexible (Polak-Ribiere) beta as in the
-// Chebyshev-preconditioned CG.  Scalars go through the host (a few reads per
-// iteration); the level vectors are set up once per solve.
-extern "C" int dg_gmg_cg_solve(const dg_op_desc* desc, int32_t levels, const double* lambda_max, const double* b,
-                               double* x, double rtol, int32_t max_iter, dg_cg_report* report, void* hip_stream) {
+// Chebyshev-preconditioned CG.  The cycle runs in T: with T = float the
+// residual is rounded to FP32 on the way in and the correction widened on the
+// way out, the outer iteration staying FP64 (the mixed-precision split of
+// Sec. 3.3).  Scalars go through the host (a few reads per iteration); the
+// level vectors are set up once per solve.
+template <typename T>
+int gmg_cg(const dg_op_desc* desc, int32_t levels, const double* lambda_max, const double* b, double* x, double rtol,
+           int32_t max_iter, dg_cg_report* report, void* hip_stream) {
   const auto t0 = std::chrono::steady_clock::now();
-  if (!b || !x) return fail(DG_ERR_INVALID_ARG, "b/x is NULL");
-  if (!(rtol > 0.0) || !std::isfinite(rtol)) return fail(DG_ERR_INVALID_ARG, "rtol must be finite and > 0");
-  if (max_iter < 0) return fail(DG_ERR_INVALID_ARG, "max_iter must be >= 0");
-  MgRun M;
-  int rc = mg_setup(M, desc, levels, 5, 20.0, 10, lambda_max, (hipStream_t)hip_stream, b, x);
+  MgRun<T> M;
+  int rc = mg_setup(M, desc, levels, 5, 20.0, 10, lambda_max, (hipStream_t)hip_stream, b, x, MgRun<T>::F32);
   if (rc) return rc;
   const long long n = M.lv[0].n;
   hipStream_t s = M.s;
@@ -233,9 +248,15 @@ extern "C" int dg_gmg_cg_solve(const dg_op_desc* desc, int32_t levels, const dou
   // z = V r, projected on zero mean
   auto precond = [&]() -> hipError_t {
     hipError_t er;
-    M.lv[0].b = r;
-    M.lv[0].x = z;
-    if ((er = M.cycle(0)) != hipSuccess) return er;
+    if constexpr (MgRun<T>::F32) {
+      if ((er = mg_convert(r, M.lv[0].b, n, s)) != hipSuccess) return er;
+      if ((er = M.cycle(0)) != hipSuccess) return er;
+      if ((er = mg_convert(M.lv[0].x, z, n, s)) != hipSuccess) return er;
+    } else {
+      M.lv[0].b = r;
+      M.lv[0].x = z;
+      if ((er = M.cycle(0)) != hipSuccess) return er;
+    }
     if ((er = cg_dot(z, ones, n, partial, s)) != hipSuccess) return er;
     if ((er = sums(1)) != hipSuccess) return er;
     return cg_axpb(z, z, 1.0, -host[0] / dn, n, s);
@@ -313,4 +334,18 @@ extern "C" int dg_gmg_cg_solve(const dg_op_desc* desc, int32_t levels, const dou
   if (status == DG_ERR_BREAKDOWN) return fail(DG_ERR_BREAKDOWN, "p.Ap <= 0");
   if (status == DG_NOT_CONVERGED) return fail(DG_NOT_CONVERGED, "max_iter reached");
   return ok();
+}
+
+}  // namespace
+}  // namespace dgmf
+
+extern "C" int dg_gmg_cg_solve(const dg_op_desc* desc, int32_t levels, const double* lambda_max, int32_t cycle_dtype,
+                               const double* b, double* x, double rtol, int32_t max_iter, dg_cg_report* report,
+                               void* hip_stream) {
+  if (!b || !x) return fail(DG_ERR_INVALID_ARG, "b/x is NULL");
+  if (!(rtol > 0.0) || !std::isfinite(rtol)) return fail(DG_ERR_INVALID_ARG, "rtol must be finite and > 0");
+  if (max_iter < 0) return fail(DG_ERR_INVALID_ARG, "max_iter must be >= 0");
+  if (cycle_dtype == DG_F64) return gmg_cg<double>(desc, levels, lambda_max, b, x, rtol, max_iter, report, hip_stream);
+  if (cycle_dtype == DG_F32) return gmg_cg<float>(desc, levels, lambda_max, b, x, rtol, max_iter, report, hip_stream);
+  return fail(DG_ERR_INVALID_ARG, "cycle_dtype must be DG_F64 or DG_F32");
 }

@@ -79,8 +79,8 @@ def lib():
         L.dg_prolongate.argtypes = [pd, ctypes.c_int, vp, vp, vp]
         L.dg_gmg_vcycle.argtypes = [pd, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
                                      ctypes.POINTER(ctypes.c_double), vp, vp, vp]
-        L.dg_gmg_cg_solve.argtypes = [pd, ctypes.c_int32, ctypes.POINTER(ctypes.c_double), vp, vp, ctypes.c_double,
-                                       ctypes.c_int32, ctypes.POINTER(CgReport), vp]
+        L.dg_gmg_cg_solve.argtypes = [pd, ctypes.c_int32, ctypes.POINTER(ctypes.c_double), ctypes.c_int32, vp, vp,
+                                       ctypes.c_double, ctypes.c_int32, ctypes.POINTER(CgReport), vp]
         L.dg_restrict.argtypes = [pd, ctypes.c_int, vp, vp, vp]
         L.dg_cg_solve.argtypes = [pd, ctypes.POINTER(CgOpts), vp, vp, ctypes.POINTER(CgReport), vp]
         L.dg_mass_pcg_solve.argtypes = [pd, ctypes.c_int32, ctypes.c_double, vp, vp, vp, vp, ctypes.c_double,
@@ -283,9 +283,10 @@ def gmg_vcycle(desc, r, lambda_max, degree=5, smoothing_range=20.0, coarse_degre
     return out
 
 
-def gmg_cg_solve(desc, b, lambda_max, x=None, rtol=1e-10, max_iter=200):
-    """FP64 CG with one V-cycle per iteration (periodic: zero-mean iterates);
-    returns (x, report dict, return code)."""
+def gmg_cg_solve(desc, b, lambda_max, x=None, rtol=1e-10, max_iter=200, cycle_dtype=DG_F64):
+    """FP64 CG with one V-cycle per iteration (periodic: zero-mean iterates),
+    the cycle in FP64 (DG_F64) or FP32 (DG_F32); returns (x, report dict,
+    return code)."""
     torch = _torch()
     shape = (_nel(desc), (desc.degree + 1) ** 3)
     _check_tensor(b, "b", shape)
@@ -297,7 +298,7 @@ def gmg_cg_solve(desc, b, lambda_max, x=None, rtol=1e-10, max_iter=200):
     lam = np.ascontiguousarray(lambda_max, dtype=np.float64)
     rep = CgReport()
     rc = _check(lib().dg_gmg_cg_solve(ctypes.byref(desc), int(len(lam)),
-                                      lam.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                      lam.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(cycle_dtype),
                                       ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(x.data_ptr()), float(rtol),
                                       int(max_iter), ctypes.byref(rep), _stream(b)), soft_ok=True)
     return x, rep.as_dict(), rc
