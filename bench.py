@@ -388,8 +388,8 @@ def mass_pcg_extra(torch, dgmf, inputs, dev, k=5, N=16):
 
 
 def _vcycle_extra(torch, dgmf, inputs, dev, k=7, N=24, levels=4, reps=5):
-    """One FP64 V-cycle on the pressure Poisson size (k=7, 24^3 -> 12^3 ->
-    6^3 -> 3^3), Chebyshev degree 5, coarse degree 10.  The per-level bounds
+    """One V-cycle, FP64 and FP32, on the pressure Poisson size (k=7, 24^3 ->
+    12^3 -> 6^3 -> 3^3), Chebyshev degree 5, coarse degree 10.  The per-level bounds
     of D^-1 A come from the library's own Lanczos estimate (the setup of
     dg_cg_solve with the Chebyshev preconditioner, one iteration, on each
     level).  Wall time per cycle includes the cycle's set-up (level
@@ -408,14 +408,16 @@ def _vcycle_extra(torch, dgmf, inputs, dev, k=7, N=24, levels=4, reps=5):
     g.manual_seed(108)
     r = torch.rand((N ** 3, (k + 1) ** 3), generator=g, dtype=torch.float64, device=dev) - 0.5
     r -= r.mean()
-    z = dgmf.gmg_vcycle(d, r, lam)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        dgmf.gmg_vcycle(d, r, lam, out=z)
-    t = (time.perf_counter() - t0) / reps
-    return {"levels": levels, "lambda_max": lam, "ms_per_cycle": t * 1e3,
-            "fine_operator_applications": 2 * (5 - 1) + 2}
+    res = {"levels": levels, "lambda_max": lam, "fine_operator_applications": 2 * (5 - 1) + 2}
+    for name, rr in (("f64", r), ("f32", r.float())):
+        z = dgmf.gmg_vcycle(d, rr, lam)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            dgmf.gmg_vcycle(d, rr, lam, out=z)
+        t = (time.perf_counter() - t0) / reps
+        res["ms_per_cycle" if name == "f64" else "ms_per_cycle_f32"] = t * 1e3
+    return res
 
 
 def _xfer_sweep(torch, dgmf, dev, args):

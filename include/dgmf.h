@@ -269,17 +269,20 @@ int dg_mass_pcg_solve(const dg_op_desc* desc, int32_t op, double mass_factor, co
  * D^-1 A on [lambda_max/smoothing_range, lambda_max], the same degree before
  * and after the coarse-grid correction, a Chebyshev method with
  * coarse_degree steps on the coarsest level, matrix-free transfers of
- * dg_prolongate / dg_restrict), in double precision:
+ * dg_prolongate / dg_restrict), all in the precision `dtype`:
  *   z = V r,  level l = the mesh coarsened l times by two per direction
  *   (re-discretised SIPG operator and diagonal), l = 0..levels-1.
  * Post-smoothing smooths the residual equation from zero.
  *   desc: the finest mesh, n_comp = 1, element counts divisible by
  *   2^(levels-1); lambda_max: host array of `levels` eigenvalue bounds of
- *   D_l^-1 A_l; r, z: [N_el][n^3] doubles (device), must not overlap.
+ *   D_l^-1 A_l (level diagonals and Chebyshev coefficients are rounded to
+ *   FP32 for DG_F32); dtype: DG_F64 or DG_F32; r, z: [N_el][n^3] values of
+ *   that type (device), must not overlap.
  * Allocates its level vectors, blocks until the cycle has run.
  */
 int dg_gmg_vcycle(const dg_op_desc* desc, int32_t levels, int32_t degree, double smoothing_range,
-                  int32_t coarse_degree, const double* lambda_max, const double* r, double* z, void* hip_stream);
+                  int32_t coarse_degree, const double* lambda_max, int32_t dtype, const void* r, void* z,
+                  void* hip_stream);
 
 /*
  * Solve A x = b with the SIPG form (n_comp = 1, periodic: b and the

@@ -119,8 +119,9 @@ namespace dgmf {
 namespace {
 
 // validation and level set-up shared by the cycle and the solver
-// in, out: the caller's finest-level input and output (FP64), which must not
-// overlap; own_top: the cycle allocates its own finest-level b and x (FP32)
+// in, out: the caller's finest-level input and output, which must not
+// overlap; own_top: the cycle allocates its own finest-level b and x (the
+// FP32 cycle inside the FP64 solver, whose in and out are then FP64)
 template <typename T>
 int mg_setup(MgRun<T>& M, const dg_op_desc* desc, int levels, int degree, double smoothing_range, int coarse_degree,
              const double* lambda_max, hipStream_t s, const void* in, const void* out, bool own_top) {
@@ -140,7 +141,7 @@ int mg_setup(MgRun<T>& M, const dg_op_desc* desc, int levels, int degree, double
   for (int d = 0; d < 3; ++d)
     if (desc->n_el[d] % (1 << (levels - 1)) != 0)
       return fail(DG_ERR_INVALID_ARG, "element counts must be divisible by 2^(levels-1)");
-  const size_t bytes = (size_t)num_elements(desc) * dofs_per_element(desc) * 8;
+  const size_t bytes = (size_t)num_elements(desc) * dofs_per_element(desc) * (own_top ? sizeof(double) : sizeof(T));
   if (overlaps(in, bytes, out, bytes)) return fail(DG_ERR_ALIAS, "the output overlaps the input");
   M.k = desc->degree;
   M.n3 = (int)dofs_per_element(desc);
@@ -179,23 +180,37 @@ int mg_setup(MgRun<T>& M, const dg_op_desc* desc, int levels, int degree, double
 }  // namespace
 }  // namespace dgmf
 
-extern "C" int dg_gmg_vcycle(const dg_op_desc* desc, int32_t levels, int32_t degree, double smoothing_range,
-                             int32_t coarse_degree, const double* lambda_max, const double* r, double* z,
-                             void* hip_stream) {
-  if (!r || !z) return fail(DG_ERR_INVALID_ARG, "r/z is NULL");
-  int rc = validate_desc(desc);
-  if (rc) return rc;
+namespace {
+
+template <typename T>
+int vcycle_once(const dg_op_desc* desc, int levels, int degree, double smoothing_range, int coarse_degree,
+                const double* lambda_max, const void* r, void* z, void* hip_stream) {
   // every argument is checked before the set-up allocates anything
-  MgRun<double> M;
-  rc = mg_setup(M, desc, levels, degree, smoothing_range, coarse_degree, lambda_max, (hipStream_t)hip_stream, r, z,
-                false);
+  MgRun<T> M;
+  int rc = mg_setup(M, desc, levels, degree, smoothing_range, coarse_degree, lambda_max, (hipStream_t)hip_stream, r,
+                    z, false);
   if (rc) return rc;
-  M.lv[0].b = const_cast<double*>(r);   // read only
-  M.lv[0].x = z;
+  M.lv[0].b = const_cast<T*>(static_cast<const T*>(r));   // read only
+  M.lv[0].x = static_cast<T*>(z);
   hipError_t e;
   if ((e = M.cycle(0)) != hipSuccess) return hip_fail(e, "V-cycle launch");
   if ((e = hipStreamSynchronize(M.s)) != hipSuccess) return hip_fail(e, "V-cycle");
   return ok();
+}
+
+}  // namespace
+
+extern "C" int dg_gmg_vcycle(const dg_op_desc* desc, int32_t levels, int32_t degree, double smoothing_range,
+                             int32_t coarse_degree, const double* lambda_max, int32_t dtype, const void* r, void* z,
+                             void* hip_stream) {
+  if (!r || !z) return fail(DG_ERR_INVALID_ARG, "r/z is NULL");
+  int rc = validate_desc(desc);
+  if (rc) return rc;
+  if (dtype == DG_F64)
+    return vcycle_once<double>(desc, levels, degree, smoothing_range, coarse_degree, lambda_max, r, z, hip_stream);
+  if (dtype == DG_F32)
+    return vcycle_once<float>(desc, levels, degree, smoothing_range, coarse_degree, lambda_max, r, z, hip_stream);
+  return fail(DG_ERR_INVALID_ARG, "dtype must be DG_F64 or DG_F32");
 }
 
 namespace dgmf {

@@ -78,7 +78,7 @@ def lib():
         L.dg_apply_gradient.argtypes = [pd, ctypes.c_int, vp, vp, vp]
         L.dg_prolongate.argtypes = [pd, ctypes.c_int, vp, vp, vp]
         L.dg_gmg_vcycle.argtypes = [pd, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
-                                     ctypes.POINTER(ctypes.c_double), vp, vp, vp]
+                                     ctypes.POINTER(ctypes.c_double), ctypes.c_int32, vp, vp, vp]
         L.dg_gmg_cg_solve.argtypes = [pd, ctypes.c_int32, ctypes.POINTER(ctypes.c_double), ctypes.c_int32, vp, vp,
                                        ctypes.c_double, ctypes.c_int32, ctypes.POINTER(CgReport), vp]
         L.dg_restrict.argtypes = [pd, ctypes.c_int, vp, vp, vp]
@@ -267,19 +267,22 @@ def restrict(coarse, rf, out=None):
 
 
 def gmg_vcycle(desc, r, lambda_max, degree=5, smoothing_range=20.0, coarse_degree=10, out=None):
-    """z = V r, one FP64 V-cycle; lambda_max: one bound of D^-1 A per level (finest first)."""
+    """z = V r, one V-cycle in r's precision (float64 or float32);
+    lambda_max: one bound of D^-1 A per level (finest first)."""
     torch = _torch()
     shape = (_nel(desc), (desc.degree + 1) ** 3)
     _check_tensor(r, "r", shape)
-    if r.dtype != torch.float64:
-        raise TypeError("r must be float64")
+    if r.dtype not in (torch.float64, torch.float32):
+        raise TypeError("r must be float64 or float32")
     if out is None:
         out = torch.empty_like(r)
     _check_tensor(out, "out", shape)
+    if out.dtype != r.dtype:
+        raise TypeError("out must have r's dtype")
     lam = np.ascontiguousarray(lambda_max, dtype=np.float64)
     _check(lib().dg_gmg_vcycle(ctypes.byref(desc), int(len(lam)), int(degree), float(smoothing_range),
                                int(coarse_degree), lam.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-                               ctypes.c_void_p(r.data_ptr()), ctypes.c_void_p(out.data_ptr()), _stream(r)))
+                               DG_F32 if r.dtype == torch.float32 else DG_F64, ctypes.c_void_p(r.data_ptr()), ctypes.c_void_p(out.data_ptr()), _stream(r)))
     return out
 
 

@@ -122,13 +122,17 @@ def test_validation_errors_of_the_multigrid_entry_points_without_gpu():
     d3 = dgmf.make_desc(2, 4, n_comp=3)
 
     def vc(desc, levels, lam, r, z, degree=5, rng=20.0, coarse=10):
-        return L.dg_gmg_vcycle(ctypes.byref(desc), levels, degree, rng, coarse, lam, vp(r), vp(z), None)
+        return L.dg_gmg_vcycle(ctypes.byref(desc), levels, degree, rng, coarse, lam, dgmf.DG_F64, vp(r), vp(z), None)
     assert vc(d3, 2, lam2, fa, fb) == dgmf.DG_ERR_INVALID_ARG            # n_comp must be 1
     assert vc(d6, 3, (ctypes.c_double * 3)(1, 1, 1), fa, fb) == dgmf.DG_ERR_INVALID_ARG   # 6 not divisible by 4
     assert vc(d, 2, bad, fa, fb) == dgmf.DG_ERR_INVALID_ARG              # non-finite bound
     assert vc(d, 0, lam2, fa, fb) == dgmf.DG_ERR_INVALID_ARG             # no level
     assert vc(d, 2, lam2, fa, fb, rng=1.0) == dgmf.DG_ERR_INVALID_ARG    # smoothing range must exceed 1
     assert vc(d, 2, lam2, fa, fa + 8) == dgmf.DG_ERR_ALIAS
+    assert L.dg_gmg_vcycle(ctypes.byref(d), 2, 5, 20.0, 10, lam2, 7, vp(fa), vp(fb), None) == dgmf.DG_ERR_INVALID_ARG
+    # FP32: 4-byte values, so an offset of 4 bytes still overlaps
+    assert L.dg_gmg_vcycle(ctypes.byref(d), 2, 5, 20.0, 10, lam2, dgmf.DG_F32, vp(fa), vp(fa + 4),
+                           None) == dgmf.DG_ERR_ALIAS
     rep = dgmf.CgReport()
 
     def cg(desc, levels, lam, b, x, rtol=1e-10, it=10, cycle=dgmf.DG_F64):

@@ -4,13 +4,16 @@ Laplacian) against the oracle's V-cycle, through the C ABI.
 Both sides take the same per-level eigenvalue bounds (from the oracle's
 Lanczos estimate), so the two cycles are the same linear operator; FP64
 within 1e-11 relative (2-norm).  Two and three levels, a single level (the
-coarse Chebyshev alone), anisotropic meshes, penalty and scale factors.
+coarse Chebyshev alone), anisotropic meshes, penalty and scale factors.  The
+FP32 cycle within 1e-5 of the oracle applied to the FP32-rounded input.  CG
+with one cycle per iteration (FP64 and FP32 cycles) against the oracle's
+flexible PCG and, at k = 7 on 24^3, against the direct FDM solve.
 """
 import numpy as np
 import pytest
 import torch
 
-from gpu_common import announce, rel_err, to_dev
+from gpu_common import announce, rel_err, round_f32, to_dev
 from oracle import mesh as M
 from oracle.laplace import laplace_apply, laplace_diagonal
 from oracle.multigrid import level_meshes, vcycle
@@ -45,6 +48,20 @@ def test_vcycle_parity(k, n_el, length, levels, pen, scale):
     z = dgmf.gmg_vcycle(d, to_dev(r), lam).cpu().numpy()
     ref = vcycle(r, k, fine, levels, lam, penalty_factor=pen, scale=scale)
     assert rel_err(z, ref) < 1e-11
+
+
+@pytest.mark.parametrize("k,n_el,levels", [(3, (8, 8, 8), 3), (6, (4, 4, 2), 2)])
+def test_vcycle_parity_f32(k, n_el, levels):
+    # the cycle in single precision against the FP64 oracle cycle of the
+    # FP32-rounded input: within 1e-5 relative
+    fine = M.Mesh(n_el, (2 * np.pi,) * 3)
+    lam = _lams(k, fine, levels, 1.0, 1.0)
+    r = inputs.uniform((fine.N, (k + 1) ** 3), seed=1120 + k)
+    r = round_f32(r - r.mean())
+    announce(f"V-cycle FP32 k={k} n_el={n_el} levels={levels}")
+    d = dgmf.make_desc(k, n_el, (2 * np.pi,) * 3)
+    z = dgmf.gmg_vcycle(d, to_dev(r, torch.float32), lam).double().cpu().numpy()
+    assert rel_err(z, vcycle(r, k, fine, levels, lam)) < 1e-5
 
 
 def test_vcycle_rejects_bad_arguments():
