@@ -27,6 +27,15 @@ struct LaplacePlan {
 hipError_t launch_laplace(const LaplacePlan& P, bool f32, const void* src, void* dst,
                           hipStream_t stream);
 
+// Multigrid smoother steps fused into the Laplace apply (T = double, float):
+// d <- c1 d + c2 D^-1 (b - A x), xout = x + d (xout must not be x: x is read
+// for neighbour DoFs); res = b - A x.  dinv: one element's n^3 values.
+template <typename T>
+hipError_t mg_apply_cheb(const LaplacePlan& P, const T* x, const T* b, const T* dinv, T c1, T c2, T* d, T* xout,
+                         hipStream_t s);
+template <typename T>
+hipError_t mg_apply_residual(const LaplacePlan& P, const T* x, const T* b, T* res, hipStream_t s);
+
 // Convective form and its VJP: 1D tables on [0,1] and the cell/face scalings.
 struct ConvPlan {
   int k = 0;

@@ -65,12 +65,26 @@ struct MgRun {
     hipError_t e;
     if ((e = mg_cheb_first(b, L.dinv, n3, (T)(1.0 / theta), L.d, x, L.n, s)) != hipSuccess) return e;
     double rho_prev = delta / theta;
-    for (int step = 1; step < deg; ++step) {
+    int step = 1;
+    if ((deg - 1) % 2 == 1) {
+      // an odd number of steps: the first one apart (apply, then the update
+      // in place), so that the fused steps, which alternate between x and
+      // L.t, end in x
       if ((e = launch_laplace(L.plan, F32, x, L.t, s)) != hipSuccess) return e;
       const double rho = 1.0 / (2.0 * theta / delta - rho_prev);
       if ((e = mg_cheb_next(b, L.t, L.dinv, n3, (T)(rho * rho_prev), (T)(2.0 * rho / delta), L.d, x, L.n, s)) !=
           hipSuccess)
         return e;
+      rho_prev = rho;
+      step = 2;
+    }
+    T *cur = x, *nxt = L.t;
+    for (; step < deg; ++step) {
+      const double rho = 1.0 / (2.0 * theta / delta - rho_prev);
+      if ((e = mg_apply_cheb<T>(L.plan, cur, b, L.dinv, (T)(rho * rho_prev), (T)(2.0 * rho / delta), L.d, nxt, s)) !=
+          hipSuccess)
+        return e;
+      std::swap(cur, nxt);
       rho_prev = rho;
     }
     return hipSuccess;
@@ -95,15 +109,13 @@ struct MgRun {
     const bool last = l + 1 == (int)lv.size();
     if ((e = cheb(L, L.b, L.x, last ? coarse_degree : degree)) != hipSuccess) return e;
     if (last) return hipSuccess;
-    if ((e = launch_laplace(L.plan, F32, L.x, L.t, s)) != hipSuccess) return e;
-    if ((e = mg_sub(L.b, L.t, L.res, L.n, s)) != hipSuccess) return e;
+    if ((e = mg_apply_residual<T>(L.plan, L.x, L.b, L.res, s)) != hipSuccess) return e;
     const TransferPlan TP = transfer_plan(l + 1);
     if ((e = launch_transfer(TP, false, F32, L.res, lv[l + 1].b, s)) != hipSuccess) return e;
     if ((e = cycle(l + 1)) != hipSuccess) return e;
     if ((e = launch_transfer(TP, true, F32, lv[l + 1].x, L.t, s)) != hipSuccess) return e;
     if ((e = mg_add(L.x, L.t, L.n, s)) != hipSuccess) return e;
-    if ((e = launch_laplace(L.plan, F32, L.x, L.t, s)) != hipSuccess) return e;
-    if ((e = mg_sub(L.b, L.t, L.res, L.n, s)) != hipSuccess) return e;
+    if ((e = mg_apply_residual<T>(L.plan, L.x, L.b, L.res, s)) != hipSuccess) return e;
     if ((e = cheb(L, L.res, L.e, degree)) != hipSuccess) return e;
     return mg_add(L.x, L.e, L.n, s);
   }
