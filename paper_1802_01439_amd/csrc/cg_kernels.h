@@ -68,13 +68,11 @@ hipError_t mg_cheb_first(const double* b, const double* dinv, int n3, double s, 
                          hipStream_t st);
 hipError_t mg_cheb_next(const double* b, const double* t, const double* dinv, int n3, double c1, double c2, double* d, double* x,
                         long long n, hipStream_t st);
-hipError_t mg_sub(const double* b, const double* t, double* y, long long n, hipStream_t st);
 hipError_t mg_add(double* x, const double* t, long long n, hipStream_t st);
 hipError_t mg_cheb_first(const float* b, const float* dinv, int n3, float s, float* d, float* x, long long n,
                          hipStream_t st);
 hipError_t mg_cheb_next(const float* b, const float* t, const float* dinv, int n3, float c1, float c2, float* d, float* x,
                         long long n, hipStream_t st);
-hipError_t mg_sub(const float* b, const float* t, float* y, long long n, hipStream_t st);
 hipError_t mg_add(float* x, const float* t, long long n, hipStream_t st);
 hipError_t mg_convert(const double* a, float* b, long long n, hipStream_t st);
 hipError_t mg_convert(const float* a, double* b, long long n, hipStream_t st);

@@ -1,7 +1,7 @@
 // One V-cycle of geometric multigrid for the SIPG Laplacian (Sec. 3.3: the
 // pressure Poisson preconditioner, Chebyshev smoothing of D^-1 A with
 // smoothing range 20, a Chebyshev method with a fixed number of steps on the
-// coarsest level, matrix-free level transfers), in FP64.
+// coarsest level, matrix-free level transfers), in FP64 or FP32.
 //
 // Level l is the periodic mesh coarsened l times by two per direction, with
 // its own SIPG operator (the Laplace kernels with the level's plan) and
@@ -11,7 +11,9 @@
 //   x += Cheb_l(b - A_l x)                          post-smoothing
 // and on the coarsest level x = Cheb(b) of the coarse degree.  Cheb is the
 // zero-start Chebyshev iteration of D^-1 A on [lambda_max/range, lambda_max]
-// in its three-term form; its scalars are formed on the host.
+// in its three-term form; its scalars are formed on the host, and its steps
+// after the first, like the residuals b - A_l x, run in the epilogue of the
+// Laplace apply.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

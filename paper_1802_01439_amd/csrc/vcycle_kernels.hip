@@ -35,14 +35,6 @@ __global__ void __launch_bounds__(kThreads) k_cheb_next(const T* __restrict__ b,
   }
 }
 
-// y = b - t
-template <typename T>
-__global__ void __launch_bounds__(kThreads) k_sub(const T* __restrict__ b, const T* __restrict__ t, T* __restrict__ y,
-                                                  long long n) {
-  for (long long i = blockIdx.x * (long long)kThreads + threadIdx.x; i < n; i += (long long)gridDim.x * kThreads)
-    y[i] = b[i] - t[i];
-}
-
 // x += t
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_add(T* __restrict__ x, const T* __restrict__ t, long long n) {
@@ -68,10 +60,6 @@ hipError_t mg_cheb_next(const double* b, const double* t, const double* dinv, in
   hipLaunchKernelGGL(k_cheb_next<double>, dim3(kCgBlocks), dim3(kThreads), 0, st, b, t, dinv, n3, c1, c2, d, x, n);
   return hipGetLastError();
 }
-hipError_t mg_sub(const double* b, const double* t, double* y, long long n, hipStream_t st) {
-  hipLaunchKernelGGL(k_sub<double>, dim3(kCgBlocks), dim3(kThreads), 0, st, b, t, y, n);
-  return hipGetLastError();
-}
 hipError_t mg_add(double* x, const double* t, long long n, hipStream_t st) {
   hipLaunchKernelGGL(k_add<double>, dim3(kCgBlocks), dim3(kThreads), 0, st, x, t, n);
   return hipGetLastError();
@@ -85,10 +73,6 @@ hipError_t mg_cheb_first(const float* b, const float* dinv, int n3, float s, flo
 hipError_t mg_cheb_next(const float* b, const float* t, const float* dinv, int n3, float c1, float c2, float* d, float* x,
                         long long n, hipStream_t st) {
   hipLaunchKernelGGL(k_cheb_next<float>, dim3(kCgBlocks), dim3(kThreads), 0, st, b, t, dinv, n3, c1, c2, d, x, n);
-  return hipGetLastError();
-}
-hipError_t mg_sub(const float* b, const float* t, float* y, long long n, hipStream_t st) {
-  hipLaunchKernelGGL(k_sub<float>, dim3(kCgBlocks), dim3(kThreads), 0, st, b, t, y, n);
   return hipGetLastError();
 }
 hipError_t mg_add(float* x, const float* t, long long n, hipStream_t st) {
