@@ -50,6 +50,23 @@ def test_vcycle_parity(k, n_el, length, levels, pen, scale):
     assert rel_err(z, ref) < 1e-11
 
 
+@pytest.mark.parametrize("degree,coarse", [(4, 7), (2, 1)])
+def test_vcycle_parity_other_degrees(degree, coarse):
+    # smoother degrees other than 5 and 10: an odd number of operator steps on
+    # the smoothing levels, an even one on the coarsest (and a single step,
+    # and a coarse solve that is the first step alone)
+    k, n_el, levels = 3, (8, 4, 4), 3
+    fine = M.Mesh(n_el, (2.0, 1.0, 1.0))
+    lam = _lams(k, fine, levels, 1.0, 1.0)
+    r = inputs.uniform((fine.N, (k + 1) ** 3), seed=1140 + degree)
+    r -= r.mean()
+    announce(f"V-cycle degree={degree} coarse={coarse}")
+    d = dgmf.make_desc(k, n_el, (2.0, 1.0, 1.0))
+    z = dgmf.gmg_vcycle(d, to_dev(r), lam, degree=degree, coarse_degree=coarse).cpu().numpy()
+    ref = vcycle(r, k, fine, levels, lam, degree=degree, coarse_degree=coarse)
+    assert rel_err(z, ref) < 1e-11
+
+
 @pytest.mark.parametrize("k,n_el,levels", [(3, (8, 8, 8), 3), (6, (4, 4, 2), 2)])
 def test_vcycle_parity_f32(k, n_el, levels):
     # the cycle in single precision against the FP64 oracle cycle of the
