@@ -139,13 +139,29 @@ def _dtype_code(t):
     raise TypeError(f"unsupported dtype {t.dtype}; use float64 or float32")
 
 
-def _check_tensor(t, name, shape):
-    if not t.is_cuda:
-        raise ValueError(f"{name} must be a GPU tensor")
-    if not t.is_contiguous():
-        raise ValueError(f"{name} must be contiguous")
+def _check_tensor(t, name, shape, like=None, dtype=None):
+    """Shape and dtype of one argument.  The C ABI takes one dtype per call
+    and raw pointers, so an output of another dtype would be written past its
+    end: every argument is checked before any launch.  like: a tensor whose
+    dtype t must share; dtype: the dtype t must have.  Device and layout are
+    checked by _placed, after every shape and dtype."""
     if tuple(t.shape) != tuple(shape):
         raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    if dtype is None and like is not None:
+        dtype = like.dtype
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} has dtype {t.dtype}, expected {dtype}")
+
+
+def _placed(first, *others):
+    """Every tensor is a contiguous GPU tensor on first's device."""
+    for t in (first,) + others:
+        if not t.is_cuda:
+            raise ValueError("every tensor argument must be a GPU tensor")
+        if t.device != first.device:
+            raise ValueError(f"tensor arguments on {first.device} and {t.device}: use one device")
+        if not t.is_contiguous():
+            raise ValueError("every tensor argument must be contiguous")
 
 
 def _stream(t):
@@ -165,7 +181,8 @@ def apply_laplace(desc, u, out=None):
     _check_tensor(u, "u", shape)
     if out is None:
         out = torch.empty_like(u)
-    _check_tensor(out, "out", shape)
+    _check_tensor(out, "out", shape, like=u)
+    _placed(u, out)
     _check(lib().dg_apply_laplace(ctypes.byref(desc), _dtype_code(u), ctypes.c_void_p(u.data_ptr()),
                                   ctypes.c_void_p(out.data_ptr()), _stream(u)))
     return out
@@ -178,7 +195,8 @@ def apply_convective(desc, u, out=None):
     _check_tensor(u, "u", shape)
     if out is None:
         out = torch.empty_like(u)
-    _check_tensor(out, "out", shape)
+    _check_tensor(out, "out", shape, like=u)
+    _placed(u, out)
     _check(lib().dg_apply_convective(ctypes.byref(desc), _dtype_code(u), ctypes.c_void_p(u.data_ptr()),
                                      ctypes.c_void_p(out.data_ptr()), _stream(u)))
     return out
@@ -189,12 +207,11 @@ def vjp_convective(desc, u, w, out=None):
     torch = _torch()
     shape = (3, _nel(desc), (desc.degree + 1) ** 3)
     _check_tensor(u, "u", shape)
-    _check_tensor(w, "w", shape)
-    if w.dtype != u.dtype:
-        raise TypeError("u and w must have the same dtype")
+    _check_tensor(w, "w", shape, like=u)
     if out is None:
         out = torch.empty_like(u)
-    _check_tensor(out, "out", shape)
+    _check_tensor(out, "out", shape, like=u)
+    _placed(u, w, out)
     _check(lib().dg_vjp_convective(ctypes.byref(desc), _dtype_code(u), ctypes.c_void_p(u.data_ptr()),
                                    ctypes.c_void_p(w.data_ptr()), ctypes.c_void_p(out.data_ptr()), _stream(u)))
     return out
@@ -207,7 +224,8 @@ def apply_divergence(desc, u, out=None):
     _check_tensor(u, "u", (3, _nel(desc), n3))
     if out is None:
         out = torch.empty((_nel(desc), n3), dtype=u.dtype, device=u.device)
-    _check_tensor(out, "out", (_nel(desc), n3))
+    _check_tensor(out, "out", (_nel(desc), n3), like=u)
+    _placed(u, out)
     _check(lib().dg_apply_divergence(ctypes.byref(desc), _dtype_code(u), ctypes.c_void_p(u.data_ptr()),
                                      ctypes.c_void_p(out.data_ptr()), _stream(u)))
     return out
@@ -220,9 +238,8 @@ def apply_gradient(desc, p, out=None):
     _check_tensor(p, "p", (_nel(desc), n3))
     if out is None:
         out = torch.empty((3, _nel(desc), n3), dtype=p.dtype, device=p.device)
-    _check_tensor(out, "out", (3, _nel(desc), n3))
-    if out.dtype != p.dtype:
-        raise TypeError("out must have the dtype of p")
+    _check_tensor(out, "out", (3, _nel(desc), n3), like=p)
+    _placed(p, out)
     _check(lib().dg_apply_gradient(ctypes.byref(desc), _dtype_code(p), ctypes.c_void_p(p.data_ptr()),
                                    ctypes.c_void_p(out.data_ptr()), _stream(p)))
     return out
@@ -243,9 +260,8 @@ def prolongate(coarse, uc, out=None):
     _check_tensor(uc, "uc", sc)
     if out is None:
         out = torch.empty(sf, dtype=uc.dtype, device=uc.device)
-    _check_tensor(out, "out", sf)
-    if out.dtype != uc.dtype:
-        raise TypeError("out must have the dtype of uc")
+    _check_tensor(out, "out", sf, like=uc)
+    _placed(uc, out)
     _check(lib().dg_prolongate(ctypes.byref(coarse), _dtype_code(uc), ctypes.c_void_p(uc.data_ptr()),
                                ctypes.c_void_p(out.data_ptr()), _stream(uc)))
     return out
@@ -258,9 +274,8 @@ def restrict(coarse, rf, out=None):
     _check_tensor(rf, "rf", sf)
     if out is None:
         out = torch.empty(sc, dtype=rf.dtype, device=rf.device)
-    _check_tensor(out, "out", sc)
-    if out.dtype != rf.dtype:
-        raise TypeError("out must have the dtype of rf")
+    _check_tensor(out, "out", sc, like=rf)
+    _placed(rf, out)
     _check(lib().dg_restrict(ctypes.byref(coarse), _dtype_code(rf), ctypes.c_void_p(rf.data_ptr()),
                              ctypes.c_void_p(out.data_ptr()), _stream(rf)))
     return out
@@ -276,10 +291,9 @@ def gmg_vcycle(desc, r, lambda_max, degree=5, smoothing_range=20.0, coarse_degre
         raise TypeError("r must be float64 or float32")
     if out is None:
         out = torch.empty_like(r)
-    _check_tensor(out, "out", shape)
-    if out.dtype != r.dtype:
-        raise TypeError("out must have r's dtype")
+    _check_tensor(out, "out", shape, like=r)
     lam = np.ascontiguousarray(lambda_max, dtype=np.float64)
+    _placed(r, out)
     _check(lib().dg_gmg_vcycle(ctypes.byref(desc), int(len(lam)), int(degree), float(smoothing_range),
                                int(coarse_degree), lam.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                DG_F32 if r.dtype == torch.float32 else DG_F64, ctypes.c_void_p(r.data_ptr()), ctypes.c_void_p(out.data_ptr()), _stream(r)))
@@ -292,14 +306,13 @@ def gmg_cg_solve(desc, b, lambda_max, x=None, rtol=1e-10, max_iter=200, cycle_dt
     return code)."""
     torch = _torch()
     shape = (_nel(desc), (desc.degree + 1) ** 3)
-    _check_tensor(b, "b", shape)
-    if b.dtype != torch.float64:
-        raise TypeError("b must be float64")
+    _check_tensor(b, "b", shape, dtype=torch.float64)
     if x is None:
         x = torch.zeros_like(b)
-    _check_tensor(x, "x", shape)
+    _check_tensor(x, "x", shape, like=b)
     lam = np.ascontiguousarray(lambda_max, dtype=np.float64)
     rep = CgReport()
+    _placed(b, x)
     rc = _check(lib().dg_gmg_cg_solve(ctypes.byref(desc), int(len(lam)),
                                       lam.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(cycle_dtype),
                                       ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(x.data_ptr()), float(rtol),
@@ -315,7 +328,8 @@ def apply_helmholtz(desc, u, mass_factor, out=None):
     _check_tensor(u, "u", shape)
     if out is None:
         out = torch.empty_like(u)
-    _check_tensor(out, "out", shape)
+    _check_tensor(out, "out", shape, like=u)
+    _placed(u, out)
     _check(lib().dg_apply_helmholtz(ctypes.byref(desc), _dtype_code(u), float(mass_factor),
                                     ctypes.c_void_p(u.data_ptr()), ctypes.c_void_p(out.data_ptr()), _stream(u)))
     return out
@@ -326,13 +340,12 @@ def apply_projection(desc, u, tau_d, tau_c, out=None):
     torch = _torch()
     shape = (3, _nel(desc), (desc.degree + 1) ** 3)
     _check_tensor(u, "u", shape)
-    _check_tensor(tau_d, "tau_d", (_nel(desc),))
-    _check_tensor(tau_c, "tau_c", (_nel(desc),))
-    if tau_d.dtype != u.dtype or tau_c.dtype != u.dtype:
-        raise TypeError("tau_d and tau_c must have the dtype of u")
+    _check_tensor(tau_d, "tau_d", (_nel(desc),), like=u)
+    _check_tensor(tau_c, "tau_c", (_nel(desc),), like=u)
     if out is None:
         out = torch.empty_like(u)
-    _check_tensor(out, "out", shape)
+    _check_tensor(out, "out", shape, like=u)
+    _placed(u, tau_d, tau_c, out)
     _check(lib().dg_apply_projection(ctypes.byref(desc), _dtype_code(u), ctypes.c_void_p(u.data_ptr()),
                                      ctypes.c_void_p(tau_d.data_ptr()), ctypes.c_void_p(tau_c.data_ptr()),
                                      ctypes.c_void_p(out.data_ptr()), _stream(u)))
@@ -348,9 +361,8 @@ def apply_inverse_mass(desc, u, out=None):
     _check_tensor(u, "u", shape)
     if out is None:
         out = torch.empty_like(u)
-    _check_tensor(out, "out", shape)
-    if out.dtype != u.dtype:
-        raise TypeError("out must have the dtype of u")
+    _check_tensor(out, "out", shape, like=u)
+    _placed(u, out)
     _check(lib().dg_apply_inverse_mass(ctypes.byref(desc), _dtype_code(u), ctypes.c_void_p(u.data_ptr()),
                                        ctypes.c_void_p(out.data_ptr()), _stream(u)))
     return out
@@ -361,16 +373,15 @@ def cg_solve(desc, b, x=None, precond=DG_PC_CHEB_F32, cheb_degree=5, cheb_range=
     """FP64 CG on the SIPG Laplacian; returns (x, report dict, return code)."""
     torch = _torch()
     n3 = (desc.degree + 1) ** 3
-    _check_tensor(b, "b", (_nel(desc), n3))
-    if b.dtype != torch.float64:
-        raise TypeError("b must be float64")
+    _check_tensor(b, "b", (_nel(desc), n3), dtype=torch.float64)
     if x is None:
         x = torch.zeros_like(b)
-    _check_tensor(x, "x", (_nel(desc), n3))
+    _check_tensor(x, "x", (_nel(desc), n3), like=b)
     o = CgOpts()
     o.precond, o.cheb_degree, o.cheb_range = int(precond), int(cheb_degree), float(cheb_range)
     o.rtol, o.atol, o.max_iter, o.project_mean = float(rtol), float(atol), int(max_iter), int(project_mean)
     rep = CgReport()
+    _placed(b, x)
     rc = _check(lib().dg_cg_solve(ctypes.byref(desc), ctypes.byref(o), ctypes.c_void_p(b.data_ptr()),
                                   ctypes.c_void_p(x.data_ptr()), ctypes.byref(rep), _stream(b)), soft_ok=True)
     return x, rep.as_dict(), rc
@@ -382,20 +393,17 @@ def mass_pcg_solve(desc, op, b, x=None, mass_factor=0.0, tau_d=None, tau_c=None,
     (x, report dict, return code)."""
     torch = _torch()
     shape = (desc.n_comp, _nel(desc), (desc.degree + 1) ** 3) if desc.n_comp > 1 else (_nel(desc), (desc.degree + 1) ** 3)
-    _check_tensor(b, "b", shape)
-    if b.dtype != torch.float64:
-        raise TypeError("b must be float64")
+    _check_tensor(b, "b", shape, dtype=torch.float64)
     if x is None:
         x = torch.zeros_like(b)
-    _check_tensor(x, "x", shape)
+    _check_tensor(x, "x", shape, like=b)
     ptr = [None, None]
     if op == DG_OP_PROJECTION:
         for i, t in enumerate((tau_d, tau_c)):
-            _check_tensor(t, "tau", (_nel(desc),))
-            if t.dtype != torch.float64:
-                raise TypeError("tau_d and tau_c must be float64")
+            _check_tensor(t, "tau", (_nel(desc),), like=b)
             ptr[i] = ctypes.c_void_p(t.data_ptr())
     rep = CgReport()
+    _placed(b, x, *[t for t in (tau_d, tau_c) if op == DG_OP_PROJECTION])
     rc = _check(lib().dg_mass_pcg_solve(ctypes.byref(desc), int(op), float(mass_factor), ptr[0], ptr[1],
                                         ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(x.data_ptr()), float(rtol),
                                         int(max_iter), ctypes.byref(rep), _stream(b)), soft_ok=True)

@@ -144,3 +144,41 @@ def test_validation_errors_of_the_multigrid_entry_points_without_gpu():
     assert cg(d, 2, lam2, fa, fb, it=-1) == dgmf.DG_ERR_INVALID_ARG
     assert cg(d, 2, bad, fa, fb) == dgmf.DG_ERR_INVALID_ARG
     assert cg(d, 2, lam2, fa, fa + 8) == dgmf.DG_ERR_ALIAS
+
+
+def test_binding_checks_dtype_before_any_launch():
+    """An output or solution tensor of another dtype than the call's would be
+    written past its end by the kernel (the C ABI takes one dtype per call):
+    the binding raises TypeError before calling the library.  Shapes match
+    here, so the dtype check is the one that fires (host tensors: nothing
+    reaches a GPU)."""
+    import torch
+    k, N = 2, 2
+    n3 = (k + 1) ** 3
+    d1, d3 = dgmf.make_desc(k, N), dgmf.make_desc(k, N, n_comp=3)
+    s64 = torch.zeros((N ** 3, n3), dtype=torch.float64)
+    v64 = torch.zeros((3, N ** 3, n3), dtype=torch.float64)
+    s32, v32 = s64.float(), v64.float()
+    tau32 = torch.zeros(N ** 3, dtype=torch.float32)
+    cases = [
+        lambda: dgmf.apply_laplace(d1, s64, out=s32),
+        lambda: dgmf.apply_convective(d1, v64, out=v32),
+        lambda: dgmf.vjp_convective(d1, v64, v32),
+        lambda: dgmf.vjp_convective(d1, v64, v64, out=v32),
+        lambda: dgmf.apply_divergence(d1, v64, out=s32),
+        lambda: dgmf.apply_gradient(d1, s64, out=v32),
+        lambda: dgmf.apply_helmholtz(d1, s64, 1.0, out=s32),
+        lambda: dgmf.apply_projection(d3, v64, tau32, tau32),
+        lambda: dgmf.apply_inverse_mass(d1, s32, out=s64),
+        lambda: dgmf.prolongate(dgmf.make_desc(k, 1), s64[:1], out=s32),
+        lambda: dgmf.restrict(dgmf.make_desc(k, 1), s64, out=s32[:1]),
+        lambda: dgmf.gmg_vcycle(d1, s32, [1.0], out=s64),
+        lambda: dgmf.cg_solve(d1, s32),
+        lambda: dgmf.cg_solve(d1, s64, x=s32),
+        lambda: dgmf.gmg_cg_solve(d1, s64, [1.0], x=s32),
+        lambda: dgmf.mass_pcg_solve(d3, dgmf.DG_OP_HELMHOLTZ, v64, x=v32, mass_factor=1.0),
+        lambda: dgmf.mass_pcg_solve(d3, dgmf.DG_OP_PROJECTION, v64, tau_d=tau32, tau_c=tau32),
+    ]
+    for i, call in enumerate(cases):
+        with pytest.raises(TypeError):
+            call()
