@@ -15,7 +15,12 @@ FP32 Chebyshev preconditioner against FP64 Jacobi-CG.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--kmin 2 --kmax 11]
                     [--ops laplace,convective] [--no-cpu-baseline] [--no-extras]
-                    [--sweep-out FILE] [--only OP:K:DTYPE]
+                    [--sweep-out FILE] [--full-out FILE] [--only OP:K:DTYPE]
+
+stdout gets one compact JSON line (under SUMMARY_MAX_CHARS): the headline,
+the roofline of the dominant kernel, the oracle baseline and one GDoF/s and
+HBM fraction per operator, dtype and degree; --full-out writes the full
+record (every case, every extra) to a file.
 """
 import argparse
 import hashlib
@@ -32,9 +37,12 @@ if ROOT not in sys.path:
 
 METRIC = "DoFs/sec per operator apply vs degree k (FP64, FP32); % HBM roofline"
 HBM_PEAK_GBS = 8000.0
-# vector ALU peaks of MI355X (256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz for
-# FP64; the published FP32 vector figure counts packed FP32, twice that)
-ALU_PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}
+# vector ALU peak of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz =
+# 78.6 TFLOP/s, for FP64 and for unpacked FP32 alike (the published FP32
+# figure, 157.3, counts packed FP32 instructions, which this code never uses)
+ALU_PEAK_TFLOPS = {"f64": 78.6, "f32": 78.6}
+# the final stdout line stays under this many characters (a log tail holds it)
+SUMMARY_MAX_CHARS = 4096
 # algorithmic bytes per DoF of one apply: read the input once, write the output once
 BYTES_PER_DOF = {("laplace", "f64"): 16, ("laplace", "f32"): 8,
                  ("convective", "f64"): 16, ("convective", "f32"): 8,
@@ -128,9 +136,29 @@ def build_cases(args, torch, dgmf, inputs, dev):
     return cases
 
 
-def cpu_baseline(args):
+def config5_against_oracle(solutions, k=7, N=24):
+    """Final error of each GPU pressure-Poisson solve (k=7, 24^3, tolerance
+    1e-10) against the oracle's FP64 direct solve (fast diagonalisation of the
+    Kronecker-sum operator, exact on this mesh) of the same right-hand side:
+    relative 2-norm of the difference after removing the constant."""
+    from oracle import mesh as M
+    from oracle.solvers import fdm_solve
+    b = solutions["b"]
+    t0 = time.perf_counter()
+    x_ref = fdm_solve(b, k, M.cube(N))
+    t_fdm = time.perf_counter() - t0
+    x_ref = x_ref - x_ref.mean()
+    nrm = np.linalg.norm(x_ref)
+    err = {name: float(np.linalg.norm((x - x.mean()) - x_ref) / nrm)
+           for name, x in solutions.items() if name != "b"}
+    return {"rel_err_vs_oracle_fdm": err, "oracle_fdm_seconds": t_fdm}
+
+
+def cpu_baseline(args, solutions=None):
     """The oracle (plain NumPy, explicit 3D tables) on a bounded sample of the
-    sweep: every degree, both operators, a fixed number of elements each."""
+    sweep: every degree, both operators, a fixed number of elements each.
+    With solutions (from the CG extras): also the final errors of the GPU
+    solves against the oracle's direct solve."""
     from oracle import mesh as M
     from oracle.convective import convective_apply
     from oracle.laplace import laplace_apply
@@ -172,7 +200,8 @@ def cpu_baseline(args):
                        f"degree-sweep mesh, k={args.kmin}..{args.kmax}, Laplace and convective, at least "
                        f"{budget} s of oracle work each ({tot_dofs} DoFs in {tot_t:.1f} s; "
                        + ", ".join(parts) + ")"),
-            "rows": oracle_rows(args)}
+            "rows": oracle_rows(args),
+            "config5": config5_against_oracle(solutions) if solutions and "b" in solutions else None}
 
 
 def oracle_rows(args, budget=0.15):
@@ -237,7 +266,11 @@ def oracle_rows(args, budget=0.15):
     return out
 
 
-def extras(torch, dgmf, inputs, dev, args, which=("vjp", "cg", "mass", "proj", "mpcg", "grad", "xfer", "vcycle")):
+def extras(torch, dgmf, inputs, dev, args, which=("vjp", "cg", "mass", "proj", "mpcg", "grad", "xfer", "vcycle"),
+           keep=None):
+    """Rows measured once per run, outside the timed steps.  keep: a dict that
+    receives the pressure-Poisson right-hand side and each solver's solution
+    (host arrays), for the comparison with the oracle's direct solve."""
     out = {}
     # inverse mass (element-local, memory bound) and the projection-step
     # operator (M + A_D + A_C, three components, seeded per-element penalty
@@ -308,10 +341,14 @@ def extras(torch, dgmf, inputs, dev, args, which=("vjp", "cg", "mass", "proj", "
         b = dgmf.apply_divergence(d, torch.from_numpy(u).to(dev))
         b -= b.mean()
         res = {}
+        if keep is not None:
+            keep["b"] = b.cpu().numpy()
         for name, pc in (("jacobi_f64", dgmf.DG_PC_JACOBI_F64), ("chebyshev5_f32", dgmf.DG_PC_CHEB_F32)):
             x, rep, rc = dgmf.cg_solve(d, b, precond=pc, rtol=1e-10, max_iter=20000)
             rep["rc"] = rc
             res[name] = rep
+            if keep is not None:
+                keep[name] = x.cpu().numpy()
         res["speedup_solve"] = res["jacobi_f64"]["seconds_solve"] / res["chebyshev5_f32"]["seconds_solve"]
         # CG with one FP64 V-cycle per iteration (24^3 -> 3^3, four levels);
         # level bounds of D^-1 A from dg_cg_solve's own set-up on each level
@@ -330,6 +367,8 @@ def extras(torch, dgmf, inputs, dev, args, which=("vjp", "cg", "mass", "proj", "
                 x, rep, rc = dgmf.gmg_cg_solve(d, b, lam, rtol=rtol, cycle_dtype=cdt)
                 rep["rc"] = rc
                 res[f"gmg_vcycle_{cyc}_rtol{rtol:g}"] = rep
+                if keep is not None and rtol == 1e-10:
+                    keep[f"gmg_vcycle_{cyc}"] = x.cpu().numpy()
         res["speedup_gmg_vs_jacobi"] = (res["jacobi_f64"]["seconds_solve"]
                                         / res["gmg_vcycle_f64_rtol1e-10"]["seconds_solve"])
         res["speedup_gmg_f32_vs_jacobi"] = (res["jacobi_f64"]["seconds_solve"]
@@ -556,6 +595,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--sweep-out", default="")
+    ap.add_argument("--full-out", default="", help="write the full record (every case, all extras) to this file")
     ap.add_argument("--extras-only", default="",
                     help="diagnostic: run only these extras (vjp,cg,mass,proj,mpcg,grad,xfer,vcycle), print them as one JSON line, no sweep")
     ap.add_argument("--calib-copy", type=int, default=0,
@@ -627,17 +667,14 @@ def main():
     dom = max(cases, key=lambda c: np.mean(c.times))
     tdom = float(np.mean(dom.times))
     traffic = load_traffic(dom.op, dom.k, dom.dtype)
-    if dom.flops:   # the convective apply is bound by vector arithmetic, not HBM
-        roofline = {"bound": "alu", "achieved": dom.flops / tdom / 1e12, "peak": ALU_PEAK_TFLOPS[dom.dtype],
-                    "unit": "TFLOP/s", "frac": dom.flops / tdom / 1e12 / ALU_PEAK_TFLOPS[dom.dtype],
-                    "traffic": traffic, "kernel": f"{KERNEL_NAME[dom.op]} k={dom.k} {dom.dtype} N={dom.N}",
-                    "algorithmic_flops_per_launch": dom.flops, "algorithmic_bytes_per_launch": dom.bytes,
-                    "hbm_frac": dom.bytes / tdom / 1e9 / HBM_PEAK_GBS, "avg_launch_us": tdom * 1e6}
-    else:
-        roofline = {"bound": "hbm", "achieved": dom.bytes / tdom / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": dom.bytes / tdom / 1e9 / HBM_PEAK_GBS, "traffic": traffic,
-                    "kernel": f"{KERNEL_NAME[dom.op]} k={dom.k} {dom.dtype} N={dom.N}",
-                    "algorithmic_bytes_per_launch": dom.bytes, "avg_launch_us": tdom * 1e6}
+    roofline = {"bound": "hbm", "achieved": dom.bytes / tdom / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": dom.bytes / tdom / 1e9 / HBM_PEAK_GBS, "traffic": traffic,
+                "kernel": f"{KERNEL_NAME[dom.op]} k={dom.k} {dom.dtype} N={dom.N}",
+                "algorithmic_bytes_per_launch": dom.bytes, "avg_launch_us": tdom * 1e6}
+    if dom.flops:   # the convective apply also has a vector-ALU roofline
+        roofline["alu_frac"] = dom.flops / tdom / 1e12 / ALU_PEAK_TFLOPS[dom.dtype]
+        roofline["alu_peak_tflops"] = ALU_PEAK_TFLOPS[dom.dtype]
+        roofline["algorithmic_flops_per_launch"] = dom.flops
     res = {"metric": METRIC, "value": dofs_step / (ms_step / 1e3), "unit": "DoFs/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32", "data": "synthetic",
@@ -652,15 +689,79 @@ def main():
     res["sweep"] = [{k_: (round(v, 4) if isinstance(v, float) else v) for k_, v in r.items()} for r in sweep]
     del cases
     torch.cuda.empty_cache()
+    solutions = {}
     if not args.no_extras:
         print("[bench] extras: inverse mass, gradient, projection, mass-preconditioned solves, VJP, CG",
               file=sys.stderr, flush=True)
-        res["extras"] = extras(torch, dgmf, inputs, dev, args)
+        res["extras"] = extras(torch, dgmf, inputs, dev, args, keep=solutions)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
-        res["cpu_baseline"] = cpu_baseline(args)
-    print(json.dumps(res), flush=True)
+        res["cpu_baseline"] = cpu_baseline(args, solutions)
+    if args.full_out:
+        with open(args.full_out, "w") as f:
+            json.dump(res, f, indent=1)
+    sys.stderr.flush()
+    print(json.dumps(summary(res)), flush=True)
 
+
+def _r(x, nd=3):
+    return None if x is None else float(f"{x:.{nd}g}")
+
+
+def summary(res):
+    """The one stdout line: the contract's fields, the roofline of the
+    dominant kernel, the oracle baseline, one GDoF/s and one HBM fraction per
+    (operator, dtype) and degree, and a few figures of the extras.  The full
+    record (every per-case number, all extras) goes to --full-out."""
+    out = {k: res[k] for k in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step",
+                               "higher_is_better", "scaling", "vs_baseline", "dtype", "data")}
+    out["config"] = {"workload": res["config"]["workload"], "applies_per_step": res["config"]["applies_per_step"],
+                     "dofs_per_step": res["config"]["dofs_per_step"]}
+    rf = res["roofline"]
+    out["roofline"] = {k: (_r(v, 4) if isinstance(v, float) else v) for k, v in rf.items()
+                       if k not in ("algorithmic_flops_per_launch",)}
+    gd, hf, ks = {}, {}, {}
+    for r in res.get("sweep", []):
+        key = f"{r['op']}_{r['dtype']}"
+        gd.setdefault(key, []).append(round(r["dofs_per_s"] / 1e9, 1))
+        hf.setdefault(key, []).append(round(r["hbm_frac"], 3))
+        ks.setdefault(key, []).append(r["k"])
+    ks_all = sorted({k for v in ks.values() for k in v})
+    out["sweep"] = {"k": ks_all, "gdofs_per_s": gd, "hbm_frac": hf}
+    ex = res.get("extras") or {}
+    xs = {}
+    v = ex.get("vjp_k4_32cubed") or {}
+    for dt in ("f64", "f32"):
+        if dt in v:
+            xs[f"vjp_k4_32cubed_{dt}"] = {"us": _r(v[dt]["us"]), "hbm_frac": _r(v[dt]["hbm_frac"])}
+    cg = ex.get("cg_k7_24cubed") or {}
+    if "jacobi_f64" in cg:
+        xs["cg_k7_24cubed_seconds_to_1e-10"] = {
+            n: _r(cg[key]["seconds_solve"]) for n, key in (("jacobi_f64", "jacobi_f64"),
+                                                           ("chebyshev5_f32", "chebyshev5_f32"),
+                                                           ("gmg_f64", "gmg_vcycle_f64_rtol1e-10"),
+                                                           ("gmg_f32", "gmg_vcycle_f32_rtol1e-10")) if key in cg}
+        xs["cg_k7_24cubed_iterations"] = {n: cg[n]["iterations"] for n in
+                                          ("jacobi_f64", "chebyshev5_f32", "gmg_vcycle_f64_rtol1e-10",
+                                           "gmg_vcycle_f32_rtol1e-10") if n in cg}
+    for name in ("inverse_mass_sweep", "projection_sweep", "gradient_sweep", "divergence_sweep"):
+        v = ex.get(name)
+        if isinstance(v, dict) and v:
+            fr = [e["hbm_frac"] for e in v.values() if isinstance(e, dict) and "hbm_frac" in e]
+            if fr:
+                xs[name + "_hbm_frac_range"] = [_r(min(fr), 2), _r(max(fr), 2)]
+    if xs:
+        out["extras"] = xs
+    cb = res.get("cpu_baseline")
+    if cb:
+        out["cpu_baseline"] = {"value": _r(cb["value"]), "unit": cb["unit"], "cores": cb["cores"], "kind": cb["kind"],
+                               "sample": ("oracle FP64 applies on the first elements of each degree-sweep mesh, "
+                                          "Laplace and convective, k=2..11 (full description in the full record)")}
+        c5 = cb.get("config5")
+        if c5:
+            out["cpu_baseline"]["config5_rel_err_vs_oracle_fdm"] = {k: _r(v, 2) for k, v in
+                                                                    c5["rel_err_vs_oracle_fdm"].items()}
+    return out
 
 if __name__ == "__main__":
     main()

@@ -20,10 +20,16 @@ def to_dev(a, dtype=None):
 
 
 def rel_err(got, ref):
+    """The larger of the relative 2-norm error ||got - ref|| / ||ref|| and the
+    element-wise error max|got - ref| / max|ref|, so that one entry far off
+    cannot hide in the norm of a large array."""
     got = np.asarray(got, dtype=np.float64)
     ref = np.asarray(ref, dtype=np.float64)
     nrm = np.linalg.norm(ref)
-    return np.linalg.norm(got - ref) / (nrm if nrm > 0 else 1.0)
+    top = np.abs(ref).max() if ref.size else 0.0
+    e2 = np.linalg.norm(got - ref) / (nrm if nrm > 0 else 1.0)
+    emax = np.abs(got - ref).max() / (top if top > 0 else 1.0) if ref.size else 0.0
+    return max(e2, emax)
 
 
 def announce(msg):

@@ -61,3 +61,71 @@ def test_source_hash_covers_every_defining_file(op):
     for name in bench.SOURCES[op]:
         assert os.path.exists(os.path.join(ROOT, "paper_1802_01439_amd", "csrc", name)), name
     assert len(bench.source_hash(op)) == 16
+
+
+def _full_record():
+    """A record shaped like bench.py's full one at the default sizes: 40
+    sweep cases and every extra."""
+    sweep = []
+    for k in range(2, 12):
+        for op in ("laplace", "convective"):
+            for dt in ("f64", "f32"):
+                row = {"op": op, "k": k, "N": bench.sweep_mesh(k), "dtype": dt, "dofs": 17_000_000,
+                       "us": 123.4567, "dofs_per_s": 1.234567e11, "gbs": 1234.5678, "hbm_frac": 0.123456}
+                if op == "convective":
+                    row.update(tflops=12.3456, alu_frac=0.345678)
+                sweep.append(row)
+    per_k = {f"k{k}_{dt}": {"us": 100.123, "dofs_per_s": 1.5e11, "hbm_frac": 0.412345}
+             for k in range(2, 12) for dt in ("f64", "f32")}
+    rep = {"iterations": 203, "matvec_f64": 204, "matvec_f32": 816, "rel_res": 9.9e-11, "true_rel_res": 9.9e-11,
+           "lambda_max": 2.345, "seconds_solve": 0.0567, "seconds_setup": 0.01, "rc": 0}
+    cg = {"jacobi_f64": rep, "chebyshev5_f32": rep, "speedup_solve": 1.8}
+    for cyc in ("f64", "f32"):
+        for rt in ("1e-10", "1e-06"):
+            cg[f"gmg_vcycle_{cyc}_rtol{rt}"] = rep
+    extras = {"inverse_mass_sweep": per_k, "projection_sweep": per_k, "gradient_sweep": per_k,
+              "divergence_sweep": per_k, "transfer_sweep": per_k, "cg_k7_24cubed": cg,
+              "vjp_k4_32cubed": {"f64": {"dofs_per_s": 2e10, "us": 608.5, "hbm_frac": 0.061},
+                                 "f32": {"dofs_per_s": 4e10, "us": 266.0, "hbm_frac": 0.069}}}
+    return {"metric": bench.METRIC, "value": 8.3e10, "unit": "DoFs/s", "n_gpus": 1, "steps": 20, "warmup": 5,
+            "ms_per_step": 16.1, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f64+f32", "data": "synthetic",
+            "config": {"workload": "degree sweep k=2..11: " + "x" * 150, "ops": ["laplace", "convective"],
+                       "applies_per_step": 40, "dofs_per_step": 1_360_000_000},
+            "roofline": {"bound": "hbm", "achieved": 569.123456, "peak": 8000.0, "unit": "GB/s",
+                         "frac": 0.0711234, "traffic": 1.234e9, "kernel": "convective_kernel k=9 f64 N=26",
+                         "algorithmic_bytes_per_launch": 843_648_000, "avg_launch_us": 1481.12345,
+                         "alu_frac": 0.27712, "alu_peak_tflops": 78.6, "algorithmic_flops_per_launch": 3.2e10},
+            "sweep": sweep, "extras": extras,
+            "cpu_baseline": {"value": 4.5e6, "unit": "DoFs/s", "cores": 16, "kind": "oracle", "sample": "s" * 2000,
+                             "rows": {"inverse_mass": {"dofs_per_s": 1e6, "sample": "x" * 100}},
+                             "config5": {"rel_err_vs_oracle_fdm": {"jacobi_f64": 1.23e-11,
+                                                                   "chebyshev5_f32": 2.34e-11,
+                                                                   "gmg_vcycle_f64": 3.4e-11,
+                                                                   "gmg_vcycle_f32": 4.5e-11},
+                                         "oracle_fdm_seconds": 1.5}}}
+
+
+def test_summary_line_is_compact_and_complete():
+    full = _full_record()
+    line = json.dumps(bench.summary(full))
+    assert len(line) < bench.SUMMARY_MAX_CHARS, len(line)
+    assert "\n" not in line
+    s = json.loads(line)
+    for key in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better",
+                "scaling", "vs_baseline", "dtype", "data", "config", "roofline", "cpu_baseline"):
+        assert key in s, key
+    assert s["config"]["workload"].startswith("degree sweep")
+    rf = s["roofline"]
+    assert rf["bound"] == "hbm" and rf["unit"] == "GB/s" and rf["peak"] == 8000.0
+    assert abs(rf["frac"] - rf["achieved"] / rf["peak"]) < 1e-3
+    assert {"value", "unit", "cores", "kind", "sample"} <= set(s["cpu_baseline"])
+    assert set(s["sweep"]["hbm_frac"]) == {"laplace_f64", "laplace_f32", "convective_f64", "convective_f32"}
+    assert all(len(v) == 10 for v in s["sweep"]["gdofs_per_s"].values())
+    assert s["sweep"]["k"] == list(range(2, 12))
+    assert s["cpu_baseline"]["config5_rel_err_vs_oracle_fdm"]["chebyshev5_f32"] == 2.3e-11
+
+
+def test_alu_peak_is_the_unpacked_vector_rate():
+    # no packed FP32 instruction is ever generated, so FP32 and FP64 share it
+    assert bench.ALU_PEAK_TFLOPS["f32"] == bench.ALU_PEAK_TFLOPS["f64"] == 78.6

@@ -4,7 +4,10 @@ Divergence: against the oracle d_h (FP64 1e-12, FP32 1e-5).  CG: the
 Jacobi-FP64 and Chebyshev(5)-FP32 preconditioned solves of the SIPG Poisson
 problem with rhs = d_h(Taylor-Green + noise) against the oracle's
 fast-diagonalisation direct solve (modulo the constant), on a small mesh and
-at the full k=7, 24^3 size; the true FP64 residual; error paths.
+at the full k=7, 24^3 size; the true FP64 residual; error paths.  The FP32
+Chebyshev preconditioner itself: the first CG iterate against the oracle's
+PCG with the oracle's Chebyshev iteration, the iteration count to 1e-10, and
+the library's lambda_max against dense eigenvalues of D^-1 A.
 """
 import numpy as np
 import pytest
@@ -13,7 +16,8 @@ import torch
 from gpu_common import announce, rel_err, round_f32, to_dev
 from oracle import basis, mesh as M
 from oracle.divergence import divergence_apply, poisson_rhs
-from oracle.solvers import fdm_solve
+from oracle.laplace import laplace_apply, laplace_diagonal
+from oracle.solvers import chebyshev, fdm_solve, pcg
 from paper_1802_01439_amd import dgmf, inputs
 
 pytestmark = pytest.mark.gpu
@@ -141,3 +145,83 @@ def test_cg_error_paths():
     with pytest.raises(dgmf.DgError) as ei:
         dgmf.cg_solve(d, b, x=b)
     assert ei.value.code == dgmf.DG_ERR_ALIAS
+
+
+def _oracle_operator(k, msh):
+    n3 = (k + 1) ** 3
+    A = lambda v: laplace_apply(v.reshape(msh.N, n3), k, msh).ravel()
+    dinv = 1.0 / np.tile(laplace_diagonal(k, msh), msh.N)
+    return A, dinv
+
+
+@pytest.mark.parametrize("k,N,degree", [
+    (2, 4, 5),   # FP32 march kernel, n = 3
+    (4, 3, 5),   # FP32 march kernel, n = 5
+    (3, 4, 5),   # FP32 batch kernel, n = 4: first, two middle and the last step
+    (5, 3, 5),   # FP32 batch kernel, n = 6
+    (3, 4, 2),   # one apply: first and last step in one kernel
+    (3, 4, 3),   # first and last step, no middle one
+    (3, 4, 1),   # no apply: x1 = D^-1 r / theta
+])
+def test_cheb_preconditioner_one_iterate_against_oracle(k, N, degree):
+    """x1 of dg_cg_solve with the FP32 Chebyshev preconditioner from x0 = 0
+    equals alpha P(r0) of the oracle's PCG, P = the oracle's Chebyshev
+    iteration of D^-1 A on [lambda/20, lambda] (Sec. 3.3: degree 5, smoothing
+    range 20) applied to the FP32-rounded residual, with the library's own
+    lambda: every Chebyshev coefficient, the interval and the recurrence of
+    each fused step are checked, not only the converged solution."""
+    msh = M.cube(N)
+    u = inputs.tgv_plus_noise(basis.lgl_nodes(k), msh.n_el, msh.length, seed=inputs.FIELD_SEED_BASE + 4)
+    b = poisson_rhs(u, k, msh)
+    announce(f"cheb one iterate k={k} N={N} degree={degree}")
+    x, rep, rc = dgmf.cg_solve(dgmf.make_desc(k, N), to_dev(b), precond=dgmf.DG_PC_CHEB_F32,
+                               cheb_degree=degree, rtol=1e-14, max_iter=1)
+    assert rc == dgmf.DG_NOT_CONVERGED and rep["iterations"] == 1, rep
+    lam = rep["lambda_max"]
+    A, dinv = _oracle_operator(k, msh)
+    P = lambda r: chebyshev(A, dinv, round_f32(r), degree, lam / 20.0, lam)
+    x_ref, info = pcg(A, b.ravel(), precond=P, max_iter=1, project=True)
+    assert info["iterations"] == 1
+    assert rel_err(x.cpu().numpy().ravel(), x_ref) < 1e-5
+
+
+def test_cheb_pcg_iteration_count_against_oracle():
+    """Chebyshev(5)-preconditioned CG to 1e-10: the library's iteration count
+    is within one of the oracle's PCG with the oracle's Chebyshev iteration
+    at the library's lambda (a wrong coefficient or interval changes the
+    count), and the solutions agree."""
+    k, N = 3, 4
+    msh = M.cube(N)
+    u = inputs.tgv_plus_noise(basis.lgl_nodes(k), msh.n_el, msh.length, seed=inputs.FIELD_SEED_BASE + 4)
+    b = poisson_rhs(u, k, msh)
+    announce(f"cheb pcg iterations k={k} N={N}")
+    x, rep, rc = dgmf.cg_solve(dgmf.make_desc(k, N), to_dev(b), precond=dgmf.DG_PC_CHEB_F32, rtol=1e-10)
+    assert rc == dgmf.DG_OK, rep
+    lam = rep["lambda_max"]
+    A, dinv = _oracle_operator(k, msh)
+    P = lambda r: chebyshev(A, dinv, round_f32(r), 5, lam / 20.0, lam)
+    x_ref, info = pcg(A, b.ravel(), precond=P, rtol=1e-10, project=True)
+    assert abs(rep["iterations"] - info["iterations"]) <= 1, (rep["iterations"], info["iterations"])
+    xs = x.cpu().numpy().ravel()
+    assert rel_err(xs - xs.mean(), x_ref - x_ref.mean()) < 1e-8
+
+
+@pytest.mark.parametrize("k,N", [(2, 3), (3, 3), (4, 2)])
+def test_lambda_max_against_dense_eigenvalues(k, N):
+    """The library's bound of D^-1 A (1.1 x the largest Ritz value of 25
+    Lanczos steps) against the largest eigenvalue of D^-1/2 A D^-1/2 of the
+    dense oracle matrix: a Ritz value never exceeds it, and 25 steps come
+    within 2e-3 of it on these meshes."""
+    msh = M.cube(N)
+    n3 = (k + 1) ** 3
+    n = msh.N * n3
+    I = np.eye(n)
+    Ad = np.stack([laplace_apply(I[j].reshape(msh.N, n3), k, msh).ravel() for j in range(n)], axis=1)
+    dg = np.tile(laplace_diagonal(k, msh), msh.N)
+    lam_true = np.linalg.eigvalsh(Ad / np.sqrt(np.outer(dg, dg))).max()
+    b = inputs.uniform((msh.N, n3), seed=61)
+    b -= b.mean()
+    announce(f"lambda_max k={k} N={N}")
+    _, rep, _ = dgmf.cg_solve(dgmf.make_desc(k, N), to_dev(b), precond=dgmf.DG_PC_CHEB_F32, max_iter=1)
+    ratio = rep["lambda_max"] / (1.1 * lam_true)
+    assert 1.0 - 2e-3 <= ratio <= 1.0 + 1e-9, (rep["lambda_max"], lam_true)
