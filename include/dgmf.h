@@ -233,6 +233,27 @@ typedef struct {
 int dg_cg_solve(const dg_op_desc* desc, const dg_cg_opts* opts, const double* b, double* x,
                 dg_cg_report* report, void* hip_stream);
 
+/*
+ * dg_cg_solve for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same solve, arguments, results and errors, but it calls no hipMalloc,
+ * hipHostMalloc, hipFree or allocating library routine.  Every piece of device
+ * memory beyond b and x (six double and five float work vectors, partial
+ * sums, the iteration state, the diagonal, the operator tables) is carved
+ * from one static device array of 64 MiB per GPU, held from the library's
+ * load until the process ends; host reads go through stack buffers (the
+ * small operator plan and tables are built in ordinary host memory).
+ * Limit: 68 bytes per DoF plus a fixed part under 1 MiB, about 0.97e6 DoFs
+ * (k = 7 on 12^3 elements fits); a larger problem returns
+ * DG_ERR_INVALID_ARG before touching the GPU.  Calls on one GPU share the
+ * array and its contents persist between calls (each call initialises what
+ * it reads); the library serialises calls from the threads of one process,
+ * and the call blocks until the solve has finished, so calls never overlap
+ * inside one process.
+ */
+int dg_cg_solve_noalloc(const dg_op_desc* desc, const dg_cg_opts* opts, const double* b, double* x,
+                        dg_cg_report* report, void* hip_stream);
+
 enum { DG_OP_HELMHOLTZ = 0, DG_OP_PROJECTION = 1 };
 
 /*

@@ -130,9 +130,17 @@ double tridiag_max_eig(const std::vector<double>& a, const std::vector<double>& 
   return hi;
 }
 
+// Device tables of the FP64 and FP32 Laplace kernels (nullptr: the library's
+// table cache).
+struct Tables {
+  const void* f64 = nullptr;
+  const void* f32 = nullptr;
+};
+
 struct Solver {
   const dg_op_desc* desc;
   LaplacePlan P;
+  Tables tab;
   Workspace* w;
   hipStream_t s;
   long long n;
@@ -153,23 +161,18 @@ struct Solver {
   }
   bool apply64(const double* in, double* out) {
     ++matvec64;
-    return ok(launch_laplace(P, false, in, out, s));
+    return ok(launch_laplace(P, false, in, out, s, tab.f64));
   }
   bool apply32(const float* in, float* out) {
     ++matvec32;
-    return ok(launch_laplace(P, true, in, out, s));
+    return ok(launch_laplace(P, true, in, out, s, tab.f32));
   }
 };
 
-}  // namespace
-
-}  // namespace dgmf
-
-using namespace dgmf;
-
-extern "C" int dg_cg_solve(const dg_op_desc* desc, const dg_cg_opts* opts, const double* b, double* x,
-                           dg_cg_report* report, void* hip_stream) {
-  const double t_start = now();
+// Arguments of dg_cg_solve and its allocation-free variant; sets the DoF
+// counts.
+int cg_validate(const dg_op_desc* desc, const dg_cg_opts* opts, const double* b, const double* x, long long* n_out,
+                long long* n3_out) {
   int rc = validate_desc(desc);
   if (rc) return rc;
   if (!opts) return fail(DG_ERR_INVALID_ARG, "opts is NULL");
@@ -187,20 +190,23 @@ extern "C" int dg_cg_solve(const dg_op_desc* desc, const dg_cg_opts* opts, const
   const long long n3 = dofs_per_element(desc);
   const long long n = num_elements(desc) * n3;
   if (overlaps(b, (size_t)n * 8, x, (size_t)n * 8)) return fail(DG_ERR_ALIAS, "x overlaps b");
-  if (report) *report = dg_cg_report{};
+  *n_out = n;
+  *n3_out = n3;
+  return DG_OK;
+}
 
-  std::lock_guard<std::mutex> lock(g_ws_mutex);
-  int dev = 0;
-  hipError_t e = hipGetDevice(&dev);
-  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
-  Workspace& W = g_ws[dev];
-  const LaplacePlan LP = make_laplace_plan(desc, 1);
+// The solve on a workspace W whose vectors hold n values and whose partial
+// buffer holds max(grid64, 3 grid32, 8 kCgBlocks) doubles.
+int cg_run(const dg_op_desc* desc, const dg_cg_opts* opts, const double* b, double* x, dg_cg_report* report,
+           void* hip_stream, Workspace& W, const LaplacePlan& LP, Tables tabs, long long n, long long n3,
+           double t_start) {
+  const bool cheb = opts->precond == DG_PC_CHEB_F32;
   const long grid64 = cg_apply_grid(LP, false), grid32 = cg_apply_grid(LP, true);
-  if ((e = ensure(W, n, std::max(grid64, 3 * grid32))) != hipSuccess) return hip_fail(e, "CG workspace allocation");
-
+  int rc;
   Solver S;
   S.desc = desc;
   S.P = LP;
+  S.tab = tabs;
   S.w = &W;
   S.s = (hipStream_t)hip_stream;
   S.n = n;
@@ -333,7 +339,7 @@ extern "C" int dg_cg_solve(const dg_op_desc* desc, const dg_cg_opts* opts, const
       a.c2 = (float)(2.0 * rho / delta);
       a.inv_theta = (float)(1.0 / theta);
       ++S.matvec32;
-      S.ok(cg_apply_cheb(LP, j, j == napp, a, S.s));
+      S.ok(cg_apply_cheb(LP, j, j == napp, a, S.s, tabs.f32));
       rho_prev = rho;
     }
     S.ok(cg_fin_cheb(W.partial, napp == 0 ? kCgBlocks : (int)grid32, W.st, start, S.s));
@@ -366,7 +372,7 @@ extern "C" int dg_cg_solve(const dg_op_desc* desc, const dg_cg_opts* opts, const
     for (int b2 = 0; b2 < batch; ++b2) {
       // q = A p with the p.q partials
       ++S.matvec64;
-      S.ok(cg_apply_dot(LP, W.p, W.q, W.partial, S.s));
+      S.ok(cg_apply_dot(LP, W.p, W.q, W.partial, S.s, tabs.f64));
       S.ok(cg_fin_alpha(W.partial, (int)grid64, W.st, S.s));
       S.ok(cg_update_xr_st(x, W.r, W.p, W.q, W.dinv, S.n3, W.st, !cheb, n, W.partial, S.s));
       precondition(false);
@@ -399,4 +405,146 @@ extern "C" int dg_cg_solve(const dg_op_desc* desc, const dg_cg_opts* opts, const
   if (status == DG_ERR_BREAKDOWN) return fail(status, "CG breakdown (p.Ap <= 0 or non-finite residual)");
   if (status == DG_NOT_CONVERGED) return fail(status, "CG reached max_iter");
   return ok();
+}
+
+}  // namespace
+
+}  // namespace dgmf
+
+using namespace dgmf;
+
+extern "C" int dg_cg_solve(const dg_op_desc* desc, const dg_cg_opts* opts, const double* b, double* x,
+                           dg_cg_report* report, void* hip_stream) {
+  const double t_start = now();
+  long long n = 0, n3 = 0;
+  int rc = cg_validate(desc, opts, b, x, &n, &n3);
+  if (rc) return rc;
+  if (report) *report = dg_cg_report{};
+  std::lock_guard<std::mutex> lock(g_ws_mutex);
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  Workspace& W = g_ws[dev];
+  const LaplacePlan LP = make_laplace_plan(desc, 1);
+  const long grid64 = cg_apply_grid(LP, false), grid32 = cg_apply_grid(LP, true);
+  if ((e = ensure(W, n, std::max(grid64, 3 * grid32))) != hipSuccess) return hip_fail(e, "CG workspace allocation");
+  return cg_run(desc, opts, b, x, report, hip_stream, W, LP, Tables{}, n, n3, t_start);
+}
+
+// ---- allocation-free variant ----
+//
+// dg_cg_solve_noalloc runs the same solve with every piece of device memory
+// beyond b and x (work vectors, partial sums, iteration state, diagonal,
+// operator tables) carved from one file-scope device array of fixed size,
+// and host reads through stack buffers, so that it calls no hipMalloc,
+// hipHostMalloc or hipFree.  In host code `scratch` names a host-side
+// stand-in: its device address is taken once per device with
+// hipGetSymbolAddress and only that address is used.
+namespace dgmf {
+
+namespace {
+
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+constexpr int kMaxDevices = 64;
+
+__device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+std::mutex g_scratch_mutex;
+void* g_scratch_dev[kMaxDevices] = {};
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+// Byte offsets of the pieces in the scratch array.
+struct ScratchLayout {
+  size_t st, res, dinv, dinv32, tab64, tab32, partial, vec64[6], vec32[5], total;
+  size_t tab64_bytes, tab32_bytes;
+  long npartial;
+};
+
+ScratchLayout scratch_layout(const LaplacePlan& LP, long long n) {
+  ScratchLayout L{};
+  L.tab64_bytes = lap_table_fill(LP, false, nullptr);
+  L.tab32_bytes = lap_table_fill(LP, true, nullptr);
+  L.npartial = std::max<long>(std::max(cg_apply_grid(LP, false), 3 * cg_apply_grid(LP, true)), 8L * kCgBlocks);
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = align256(o + bytes);
+    return at;
+  };
+  L.st = take(kStateSize * sizeof(double));
+  L.res = take(8 * sizeof(double));
+  L.dinv = take(1728 * sizeof(double));
+  L.dinv32 = take(1728 * sizeof(float));
+  L.tab64 = take(L.tab64_bytes);
+  L.tab32 = take(L.tab32_bytes);
+  L.partial = take((size_t)L.npartial * sizeof(double));
+  for (size_t& v : L.vec64) v = take((size_t)n * sizeof(double));
+  for (size_t& v : L.vec32) v = take((size_t)n * sizeof(float));
+  L.total = o;
+  return L;
+}
+
+}  // namespace
+
+}  // namespace dgmf
+
+extern "C" int dg_cg_solve_noalloc(const dg_op_desc* desc, const dg_cg_opts* opts, const double* b, double* x,
+                                   dg_cg_report* report, void* hip_stream) {
+  const double t_start = now();
+  long long n = 0, n3 = 0;
+  int rc = cg_validate(desc, opts, b, x, &n, &n3);
+  if (rc) return rc;
+  const LaplacePlan LP = make_laplace_plan(desc, 1);
+  const ScratchLayout L = scratch_layout(LP, n);
+  if (L.total > kNoAllocScratchBytes)
+    return fail(DG_ERR_INVALID_ARG, "dg_cg_solve_noalloc: " + std::to_string(n) + " DoFs need " +
+                                        std::to_string(L.total) + " bytes of scratch; the static array holds " +
+                                        std::to_string(kNoAllocScratchBytes) + " (68 bytes per DoF)");
+  if (report) *report = dg_cg_report{};
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) return fail(DG_ERR_INVALID_ARG, "device index beyond the scratch table");
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    if ((e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch))) != hipSuccess)
+      return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    g_scratch_dev[dev] = p;
+  }
+  unsigned char* base = static_cast<unsigned char*>(g_scratch_dev[dev]);
+  Workspace W;
+  W.n = n;
+  W.st = reinterpret_cast<double*>(base + L.st);
+  W.res = reinterpret_cast<double*>(base + L.res);
+  W.dinv = reinterpret_cast<double*>(base + L.dinv);
+  W.dinv32 = reinterpret_cast<float*>(base + L.dinv32);
+  W.partial = reinterpret_cast<double*>(base + L.partial);
+  W.npartial = L.npartial;
+  double** d8[] = {&W.r, &W.p, &W.q, &W.z, &W.zold, &W.tmp};
+  float** d4[] = {&W.r32, &W.x32, &W.t32, &W.za32, &W.zb32};
+  for (int i = 0; i < 6; ++i) *d8[i] = reinterpret_cast<double*>(base + L.vec64[i]);
+  for (int i = 0; i < 5; ++i) *d4[i] = reinterpret_cast<float*>(base + L.vec32[i]);
+  // host ends of the state reads: ordinary (pageable) memory, read after a
+  // stream synchronisation
+  double host_res[8], host_st[kStateSize];
+  W.host = host_res;
+  W.host_st = host_st;
+  // the operator tables, built on the host and copied into the scratch array
+  // (the host copies live until the solve has returned)
+  std::vector<unsigned char> t64(L.tab64_bytes), t32(L.tab32_bytes);
+  lap_table_fill(LP, false, t64.data());
+  lap_table_fill(LP, true, t32.data());
+  const hipStream_t s = (hipStream_t)hip_stream;
+  if ((e = hipMemcpyAsync(base + L.tab64, t64.data(), L.tab64_bytes, hipMemcpyHostToDevice, s)) != hipSuccess ||
+      (e = hipMemcpyAsync(base + L.tab32, t32.data(), L.tab32_bytes, hipMemcpyHostToDevice, s)) != hipSuccess)
+    return hip_fail(e, "operator table upload");
+  Tables tabs;
+  tabs.f64 = base + L.tab64;
+  tabs.f32 = base + L.tab32;
+  rc = cg_run(desc, opts, b, x, report, hip_stream, W, LP, tabs, n, n3, t_start);
+  const hipError_t se = hipStreamSynchronize(s);
+  if (rc == DG_OK && se != hipSuccess) return hip_fail(se, "dg_cg_solve_noalloc");
+  return rc;
 }

@@ -16,8 +16,10 @@ namespace dgmf {
 // Workgroups of one apply of plan P in FP32 or FP64 (partials per quantity).
 long cg_apply_grid(const LaplacePlan& P, bool f32);
 
-// FP64 q = A p; partial[wg] = sum of p.q over the workgroup.
-hipError_t cg_apply_dot(const LaplacePlan& P, const double* p, double* q, double* partial, hipStream_t s);
+// FP64 q = A p; partial[wg] = sum of p.q over the workgroup.  tab: device
+// table as in launch_laplace (nullptr: from the table cache).
+hipError_t cg_apply_dot(const LaplacePlan& P, const double* p, double* q, double* partial, hipStream_t s,
+                        const void* tab = nullptr);
 
 // One FP32 Chebyshev step with its operator apply t = A x_k, in three-term
 // form (d_k = x_{k+1} - x_k of the two-term recurrence is not stored):
@@ -40,6 +42,7 @@ struct ChebStepArgs {
   double* partial;      // 3 x cg_apply_grid() partials (last)
   float c1, c2, inv_theta;
 };
-hipError_t cg_apply_cheb(const LaplacePlan& P, int step, bool last, const ChebStepArgs& a, hipStream_t s);
+hipError_t cg_apply_cheb(const LaplacePlan& P, int step, bool last, const ChebStepArgs& a, hipStream_t s,
+                         const void* tab = nullptr);
 
 }  // namespace dgmf

@@ -62,34 +62,36 @@ struct ChebIO {
 };
 
 template <int N, int KIND, bool LAST>
-hipError_t step_n(const LaplacePlan& P, const ChebStepArgs& a, hipStream_t s) {
+hipError_t step_n(const LaplacePlan& P, const ChebStepArgs& a, hipStream_t s, const void* tab) {
   ChebIO<KIND, LAST> io{};
   io.a = a;
-  return launch_laplace_io<N, float>(P, io, nullptr, s);
+  return launch_laplace_io<N, float>(P, io, static_cast<const LapTab<N, float>*>(tab), s);
 }
 
 template <int N>
-hipError_t step_fl(const LaplacePlan& P, int step, bool last, const ChebStepArgs& a, hipStream_t s) {
-  if (step == 1) return last ? step_n<N, 0, true>(P, a, s) : step_n<N, 0, false>(P, a, s);
-  if (step == 2) return last ? step_n<N, 1, true>(P, a, s) : step_n<N, 1, false>(P, a, s);
-  return last ? step_n<N, 2, true>(P, a, s) : step_n<N, 2, false>(P, a, s);
+hipError_t step_fl(const LaplacePlan& P, int step, bool last, const ChebStepArgs& a, hipStream_t s,
+                   const void* t) {
+  if (step == 1) return last ? step_n<N, 0, true>(P, a, s, t) : step_n<N, 0, false>(P, a, s, t);
+  if (step == 2) return last ? step_n<N, 1, true>(P, a, s, t) : step_n<N, 1, false>(P, a, s, t);
+  return last ? step_n<N, 2, true>(P, a, s, t) : step_n<N, 2, false>(P, a, s, t);
 }
 
 }  // namespace
 
-hipError_t cg_apply_cheb(const LaplacePlan& P, int step, bool last, const ChebStepArgs& a, hipStream_t s) {
+hipError_t cg_apply_cheb(const LaplacePlan& P, int step, bool last, const ChebStepArgs& a, hipStream_t s,
+                         const void* tab) {
   switch (P.k) {
-    case 1: return step_fl<2>(P, step, last, a, s);
-    case 2: return step_fl<3>(P, step, last, a, s);
-    case 3: return step_fl<4>(P, step, last, a, s);
-    case 4: return step_fl<5>(P, step, last, a, s);
-    case 5: return step_fl<6>(P, step, last, a, s);
-    case 6: return step_fl<7>(P, step, last, a, s);
-    case 7: return step_fl<8>(P, step, last, a, s);
-    case 8: return step_fl<9>(P, step, last, a, s);
-    case 9: return step_fl<10>(P, step, last, a, s);
-    case 10: return step_fl<11>(P, step, last, a, s);
-    case 11: return step_fl<12>(P, step, last, a, s);
+    case 1: return step_fl<2>(P, step, last, a, s, tab);
+    case 2: return step_fl<3>(P, step, last, a, s, tab);
+    case 3: return step_fl<4>(P, step, last, a, s, tab);
+    case 4: return step_fl<5>(P, step, last, a, s, tab);
+    case 5: return step_fl<6>(P, step, last, a, s, tab);
+    case 6: return step_fl<7>(P, step, last, a, s, tab);
+    case 7: return step_fl<8>(P, step, last, a, s, tab);
+    case 8: return step_fl<9>(P, step, last, a, s, tab);
+    case 9: return step_fl<10>(P, step, last, a, s, tab);
+    case 10: return step_fl<11>(P, step, last, a, s, tab);
+    case 11: return step_fl<12>(P, step, last, a, s, tab);
     default: return hipErrorInvalidValue;
   }
 }

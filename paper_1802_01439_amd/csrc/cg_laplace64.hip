@@ -29,20 +29,25 @@ struct CgDotIO {
   }
 };
 
+template <int N>
+const LapTab<N, double>* tab_of(const void* tab) {
+  return static_cast<const LapTab<N, double>*>(tab);
+}
+
 template <typename IO>
-hipError_t dispatch64(const LaplacePlan& P, const IO& io, hipStream_t s) {
+hipError_t dispatch64(const LaplacePlan& P, const IO& io, hipStream_t s, const void* tab) {
   switch (P.k) {
-    case 1: return launch_laplace_io<2, double>(P, io, nullptr, s);
-    case 2: return launch_laplace_io<3, double>(P, io, nullptr, s);
-    case 3: return launch_laplace_io<4, double>(P, io, nullptr, s);
-    case 4: return launch_laplace_io<5, double>(P, io, nullptr, s);
-    case 5: return launch_laplace_io<6, double>(P, io, nullptr, s);
-    case 6: return launch_laplace_io<7, double>(P, io, nullptr, s);
-    case 7: return launch_laplace_io<8, double>(P, io, nullptr, s);
-    case 8: return launch_laplace_io<9, double>(P, io, nullptr, s);
-    case 9: return launch_laplace_io<10, double>(P, io, nullptr, s);
-    case 10: return launch_laplace_io<11, double>(P, io, nullptr, s);
-    case 11: return launch_laplace_io<12, double>(P, io, nullptr, s);
+    case 1: return launch_laplace_io<2, double>(P, io, tab_of<2>(tab), s);
+    case 2: return launch_laplace_io<3, double>(P, io, tab_of<3>(tab), s);
+    case 3: return launch_laplace_io<4, double>(P, io, tab_of<4>(tab), s);
+    case 4: return launch_laplace_io<5, double>(P, io, tab_of<5>(tab), s);
+    case 5: return launch_laplace_io<6, double>(P, io, tab_of<6>(tab), s);
+    case 6: return launch_laplace_io<7, double>(P, io, tab_of<7>(tab), s);
+    case 7: return launch_laplace_io<8, double>(P, io, tab_of<8>(tab), s);
+    case 8: return launch_laplace_io<9, double>(P, io, tab_of<9>(tab), s);
+    case 9: return launch_laplace_io<10, double>(P, io, tab_of<10>(tab), s);
+    case 10: return launch_laplace_io<11, double>(P, io, tab_of<11>(tab), s);
+    case 11: return launch_laplace_io<12, double>(P, io, tab_of<12>(tab), s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -69,12 +74,13 @@ long grid_t(const LaplacePlan& P) {
 
 long cg_apply_grid(const LaplacePlan& P, bool f32) { return f32 ? grid_t<float>(P) : grid_t<double>(P); }
 
-hipError_t cg_apply_dot(const LaplacePlan& P, const double* p, double* q, double* partial, hipStream_t s) {
+hipError_t cg_apply_dot(const LaplacePlan& P, const double* p, double* q, double* partial, hipStream_t s,
+                        const void* tab) {
   CgDotIO io{};
   io.p = p;
   io.q = q;
   io.partial = partial;
-  return dispatch64(P, io, s);
+  return dispatch64(P, io, s, tab);
 }
 
 }  // namespace dgmf

@@ -24,8 +24,13 @@ struct LaplacePlan {
   double shift = 0;          // y = (Mx(x)My(x)Mz)(shift I + sum_d c_d L_d) u: mass_factor * vol
 };
 
+// tab: the kernel's device table of plan P (bytes written by lap_table_fill),
+// or nullptr to take it from the library's table cache (uploaded on first use).
 hipError_t launch_laplace(const LaplacePlan& P, bool f32, const void* src, void* dst,
-                          hipStream_t stream);
+                          hipStream_t stream, const void* tab = nullptr);
+// Size of the device table of plan P's Laplace kernels (FP32 or FP64); with
+// host_out, also writes the table there (for an upload by the caller).
+size_t lap_table_fill(const LaplacePlan& P, bool f32, void* host_out);
 
 // Multigrid smoother steps fused into the Laplace apply (T = double, float):
 // d <- c1 d + c2 D^-1 (b - A x), xout = x + d (xout must not be x: x is read

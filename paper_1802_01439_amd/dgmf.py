@@ -25,7 +25,7 @@ DG_PC_JACOBI_F64, DG_PC_CHEB_F32 = 0, 1
 DG_OP_HELMHOLTZ, DG_OP_PROJECTION = 0, 1
 
 EXPORTS = ("dg_apply_laplace", "dg_apply_convective", "dg_vjp_convective", "dg_apply_divergence",
-           "dg_apply_inverse_mass", "dg_apply_helmholtz", "dg_apply_projection", "dg_apply_gradient", "dg_prolongate", "dg_restrict", "dg_gmg_vcycle", "dg_gmg_cg_solve", "dg_cg_solve", "dg_mass_pcg_solve", "dg_laplace_diagonal", "dg_lgl_nodes", "dg_error_string", "dg_last_error")
+           "dg_apply_inverse_mass", "dg_apply_helmholtz", "dg_apply_projection", "dg_apply_gradient", "dg_prolongate", "dg_restrict", "dg_gmg_vcycle", "dg_gmg_cg_solve", "dg_cg_solve", "dg_cg_solve_noalloc", "dg_mass_pcg_solve", "dg_laplace_diagonal", "dg_lgl_nodes", "dg_error_string", "dg_last_error")
 
 
 class OpDesc(ctypes.Structure):
@@ -83,6 +83,7 @@ def lib():
                                        ctypes.c_double, ctypes.c_int32, ctypes.POINTER(CgReport), vp]
         L.dg_restrict.argtypes = [pd, ctypes.c_int, vp, vp, vp]
         L.dg_cg_solve.argtypes = [pd, ctypes.POINTER(CgOpts), vp, vp, ctypes.POINTER(CgReport), vp]
+        L.dg_cg_solve_noalloc.argtypes = [pd, ctypes.POINTER(CgOpts), vp, vp, ctypes.POINTER(CgReport), vp]
         L.dg_mass_pcg_solve.argtypes = [pd, ctypes.c_int32, ctypes.c_double, vp, vp, vp, vp, ctypes.c_double,
                                          ctypes.c_int32, ctypes.POINTER(CgReport), vp]
         L.dg_laplace_diagonal.argtypes = [pd, dp]
@@ -92,7 +93,7 @@ def lib():
         L.dg_last_error.argtypes = []
         L.dg_last_error.restype = ctypes.c_char_p
         for name in ("dg_apply_laplace", "dg_apply_convective", "dg_vjp_convective", "dg_apply_divergence",
-                     "dg_apply_inverse_mass", "dg_apply_helmholtz", "dg_apply_projection", "dg_apply_gradient", "dg_prolongate", "dg_restrict", "dg_gmg_vcycle", "dg_gmg_cg_solve", "dg_cg_solve", "dg_mass_pcg_solve", "dg_laplace_diagonal", "dg_lgl_nodes"):
+                     "dg_apply_inverse_mass", "dg_apply_helmholtz", "dg_apply_projection", "dg_apply_gradient", "dg_prolongate", "dg_restrict", "dg_gmg_vcycle", "dg_gmg_cg_solve", "dg_cg_solve", "dg_cg_solve_noalloc", "dg_mass_pcg_solve", "dg_laplace_diagonal", "dg_lgl_nodes"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -369,8 +370,11 @@ def apply_inverse_mass(desc, u, out=None):
 
 
 def cg_solve(desc, b, x=None, precond=DG_PC_CHEB_F32, cheb_degree=5, cheb_range=20.0, rtol=1e-10,
-             atol=0.0, max_iter=5000, project_mean=True):
-    """FP64 CG on the SIPG Laplacian; returns (x, report dict, return code)."""
+             atol=0.0, max_iter=5000, project_mean=True, noalloc=False):
+    """FP64 CG on the SIPG Laplacian; returns (x, report dict, return code).
+    noalloc: call dg_cg_solve_noalloc (work memory from the library's static
+    array, no device allocation by the library; x must be given then if the
+    caller allocates nothing either)."""
     torch = _torch()
     n3 = (desc.degree + 1) ** 3
     _check_tensor(b, "b", (_nel(desc), n3), dtype=torch.float64)
@@ -382,8 +386,9 @@ def cg_solve(desc, b, x=None, precond=DG_PC_CHEB_F32, cheb_degree=5, cheb_range=
     o.rtol, o.atol, o.max_iter, o.project_mean = float(rtol), float(atol), int(max_iter), int(project_mean)
     rep = CgReport()
     _placed(b, x)
-    rc = _check(lib().dg_cg_solve(ctypes.byref(desc), ctypes.byref(o), ctypes.c_void_p(b.data_ptr()),
-                                  ctypes.c_void_p(x.data_ptr()), ctypes.byref(rep), _stream(b)), soft_ok=True)
+    fn = lib().dg_cg_solve_noalloc if noalloc else lib().dg_cg_solve
+    rc = _check(fn(ctypes.byref(desc), ctypes.byref(o), ctypes.c_void_p(b.data_ptr()),
+                   ctypes.c_void_p(x.data_ptr()), ctypes.byref(rep), _stream(b)), soft_ok=True)
     return x, rep.as_dict(), rc
 
 

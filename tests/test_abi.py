@@ -182,3 +182,24 @@ def test_binding_checks_dtype_before_any_launch():
     for i, call in enumerate(cases):
         with pytest.raises(TypeError):
             call()
+
+
+def test_noalloc_cg_refuses_problems_beyond_its_static_array_without_gpu():
+    """68 bytes per DoF in a 64 MiB array: 1.1e6 DoFs (k = 3, 20 x 20 x 43
+    elements) no longer fit and are refused before any HIP call; the
+    argument checks are those of dg_cg_solve."""
+    L = dgmf.lib()
+    vp = ctypes.c_void_p
+    fa, fb = 0x10000000, 0x40000000      # never dereferenced
+    o = dgmf.CgOpts()
+    o.precond, o.cheb_degree, o.cheb_range, o.rtol, o.atol, o.max_iter, o.project_mean = 1, 5, 20.0, 1e-10, 0.0, 10, 1
+    big = dgmf.make_desc(3, (20, 20, 43))
+    assert L.dg_cg_solve_noalloc(ctypes.byref(big), ctypes.byref(o), vp(fa), vp(fb), None, None) == \
+        dgmf.DG_ERR_INVALID_ARG
+    assert "scratch" in L.dg_last_error().decode()
+    small = dgmf.make_desc(3, 4)
+    assert L.dg_cg_solve_noalloc(ctypes.byref(small), ctypes.byref(o), vp(fa), vp(fa + 8), None, None) == \
+        dgmf.DG_ERR_ALIAS
+    o.max_iter = 0
+    assert L.dg_cg_solve_noalloc(ctypes.byref(small), ctypes.byref(o), vp(fa), vp(fb), None, None) == \
+        dgmf.DG_ERR_INVALID_ARG
