@@ -18,4 +18,14 @@ convective  convective term c_h with local Lax-Friedrichs flux, its explicit
 divergence  velocity divergence d_h with central flux (Sec. 3.2, weak form of d_h)
 solvers     CG (Jacobi / Chebyshev preconditioned), Chebyshev iteration and
             the fast-diagonalisation direct solve (Sec. 3.3)
+gradient    pressure gradient g_h in the velocity space (Sec. 3.2)
+mass        mass matrix, its inverse and the Helmholtz operator (Sec. 3.3)
+projection  the projection-step operator M + A_D + A_C (Sec. 3.2, 3.3)
+transfer    h-multigrid level transfers (Sec. 3.3)
+multigrid   the geometric multigrid V-cycle (Sec. 3.3)
+mixed       divergence and gradient between the degree-k velocity and the
+            degree-(k-1) pressure (Sec. 3.2, mixed-order spaces)
+dual_splitting  one BDF1/BDF2 dual-splitting step composed from the operators
+            above, the penalty parameters and the Taylor-Green diagnostics
+            e_k and eps (Sec. 3.1, 3.2, 4.2)
 """
