@@ -266,7 +266,8 @@ def oracle_rows(args, budget=0.15):
     return out
 
 
-def extras(torch, dgmf, inputs, dev, args, which=("vjp", "cg", "mass", "proj", "mpcg", "grad", "xfer", "vcycle"),
+def extras(torch, dgmf, inputs, dev, args, which=("vjp", "cg", "mass", "proj", "mpcg", "grad", "xfer", "vcycle",
+                                                  "step"),
            keep=None):
     """Rows measured once per run, outside the timed steps.  keep: a dict that
     receives the pressure-Poisson right-hand side and each solver's solution
@@ -280,6 +281,11 @@ def extras(torch, dgmf, inputs, dev, args, which=("vjp", "cg", "mass", "proj", "
                                                  dgmf.apply_inverse_mass(d, x, y))
     if "vcycle" in which:
         out["vcycle_k7_24cubed"] = _vcycle_extra(torch, dgmf, inputs, dev)
+    if "step" in which:
+        try:
+            out["dual_splitting_k7_24cubed"] = step_extra(torch, dgmf, inputs, dev)
+        except dgmf.DgError as ex:
+            out["dual_splitting_k7_24cubed"] = {"error": str(ex)}
     if "xfer" in which:
         out["transfer_sweep"] = _xfer_sweep(torch, dgmf, dev, args)
     if "grad" in which:
@@ -379,6 +385,38 @@ def extras(torch, dgmf, inputs, dev, args, which=("vjp", "cg", "mass", "proj", "
     except dgmf.DgError as ex:
         out["cg_k7_24cubed"] = {"error": str(ex)}
     return out
+
+
+def step_extra(torch, dgmf, inputs, dev, k=7, N=24, steps=5):
+    """Dual-splitting time steps of the Taylor-Green vortex (Sec. 4: Re = 1600,
+    U0 = L = 1, no noise), velocity degree k = 7, pressure 6, on 24^3
+    elements; dt from the CFL condition with Cr = 0.125 and r = 1.5
+    (Sec. 4.1); the paper's solver tolerances (relative 1e-6, absolute 1e-12
+    for the pressure).  One BDF1 start-up step, then `steps` BDF2 steps, each
+    timed on the host around the blocking call (three CG solves, the
+    convective, divergence, gradient and mass applies, the penalty
+    parameters and the diagnostics)."""
+    L = 2 * np.pi
+    h = L / N
+    dt, nu = 0.125 / k ** 1.5 * h, 1.0 / 1600
+    x, y, z = inputs.node_positions(dgmf.lgl_nodes(k), (N, N, N), (L,) * 3)
+    u0 = torch.from_numpy(inputs.taylor_green(x, y, z)).to(dev)
+    d = dgmf.make_desc(k, N)
+    bufs = [u0, torch.empty_like(u0), torch.empty_like(u0)]
+    _, p, rep0, rc = dgmf.dual_splitting_step(d, bufs[0], out=bufs[1], dt=dt, nu=nu, order=1)
+    res = {"dt": dt, "dofs": N ** 3 * (3 * (k + 1) ** 3 + k ** 3), "startup": rep0, "rc": [rc], "steps": []}
+    cur, prev, nxt = 1, 0, 2
+    for _ in range(steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, p, rep, rc = dgmf.dual_splitting_step(d, bufs[cur], bufs[prev], p=p, out=bufs[nxt], dt=dt, nu=nu, order=2)
+        res["steps"].append(dict(rep, wall_s=time.perf_counter() - t0))
+        res["rc"].append(rc)
+        cur, prev, nxt = nxt, cur, prev
+    w = [r["wall_s"] for r in res["steps"]]
+    res["ms_per_step"] = 1e3 * float(np.median(w))
+    res["dofs_steps_per_s"] = res["dofs"] / float(np.median(w))
+    return res
 
 
 def mass_pcg_extra(torch, dgmf, inputs, dev, k=5, N=16):
@@ -597,7 +635,7 @@ def main():
     ap.add_argument("--sweep-out", default="")
     ap.add_argument("--full-out", default="", help="write the full record (every case, all extras) to this file")
     ap.add_argument("--extras-only", default="",
-                    help="diagnostic: run only these extras (vjp,cg,mass,proj,mpcg,grad,xfer,vcycle), print them as one JSON line, no sweep")
+                    help="diagnostic: run only these extras (vjp,cg,mass,proj,mpcg,grad,xfer,vcycle,step), print them as one JSON line, no sweep")
     ap.add_argument("--calib-copy", type=int, default=0,
                     help="also run one plain device copy of this many bytes (counter calibration)")
     args = ap.parse_args()
@@ -744,6 +782,13 @@ def summary(res):
         xs["cg_k7_24cubed_iterations"] = {n: cg[n]["iterations"] for n in
                                           ("jacobi_f64", "chebyshev5_f32", "gmg_vcycle_f64_rtol1e-10",
                                            "gmg_vcycle_f32_rtol1e-10") if n in cg}
+    st = ex.get("dual_splitting_k7_24cubed") or {}
+    if "ms_per_step" in st:
+        last = st["steps"][-1]
+        xs["dual_splitting_k7_24cubed"] = {"ms_per_step": _r(st["ms_per_step"]),
+                                           "iterations_p_proj_visc": [last["it_pressure"], last["it_projection"],
+                                                                      last["it_viscous"]],
+                                           "e_k": _r(last["kinetic_energy"], 6), "eps": _r(last["dissipation"], 4)}
     for name in ("inverse_mass_sweep", "projection_sweep", "gradient_sweep", "divergence_sweep"):
         v = ex.get(name)
         if isinstance(v, dict) and v:

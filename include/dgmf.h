@@ -254,6 +254,81 @@ int dg_cg_solve(const dg_op_desc* desc, const dg_cg_opts* opts, const double* b,
 int dg_cg_solve_noalloc(const dg_op_desc* desc, const dg_cg_opts* opts, const double* b, double* x,
                         dg_cg_report* report, void* hip_stream);
 
+/*
+ * Divergence and gradient between the mixed-order spaces of the paper's
+ * solver (Sec. 3.2: velocity of tensor degree k, pressure of degree k-1,
+ * inf-sup stable), central fluxes, k+1 Gauss points (exact on affine cells):
+ *   dg_apply_divergence_mixed: b_i = d_h(q_i, u) = -(grad q_i, u)_K +
+ *     (q_i, {{u}}.n)_dK for the degree-(k-1) basis q_i;
+ *     u: [3][N_el][(k+1)^3], b: [N_el][k^3];
+ *   dg_apply_gradient_mixed: y_j,i = g_h(phi_i e_j, p) = -(d_j phi_i, p)_K +
+ *     (phi_i n_j, {{p}})_dK for the degree-k basis phi_i;
+ *     p: [N_el][k^3], y: [3][N_el][(k+1)^3].
+ * desc: degree = k (2..11), the mesh; n_q 0 or k+1; n_comp, scale, penalty
+ * and lf_factor unused.  dtype DG_F64 or DG_F32; device pointers, the output
+ * must not overlap the input.  Asynchronous on hip_stream.  On a periodic
+ * mesh the gradient is minus the transpose of the divergence.
+ */
+int dg_apply_divergence_mixed(const dg_op_desc* desc, dg_dtype dtype, const void* u, void* b, void* hip_stream);
+int dg_apply_gradient_mixed(const dg_op_desc* desc, dg_dtype dtype, const void* p, void* y, void* hip_stream);
+
+/*
+ * Taylor-Green diagnostics of a velocity field (Sec. 4.2):
+ *   out[0] = e_k = (1/V) int 1/2 u.u,  out[1] = eps = (nu/V) int grad u : grad u
+ * (gradients element by element, k+1 Gauss points: exact), V the box volume.
+ * u: [3][N_el][(k+1)^3] doubles (device); out: 2 doubles (host).  Blocks.
+ */
+int dg_tgv_diagnostics(const dg_op_desc* desc, const double* u, double nu, double* out, void* hip_stream);
+
+typedef struct {
+  int32_t order;          /* 1: BDF1 (the start-up step, u_nm1 unused); 2: BDF2 */
+  double  dt;             /* time step */
+  double  nu;             /* kinematic viscosity */
+  double  zeta_d;         /* divergence penalty factor (the paper: 1) */
+  double  zeta_c;         /* continuity penalty factor (the paper: 1) */
+  double  rtol_pressure;  /* relative CG tolerances of the three solves (the paper: 1e-6) */
+  double  rtol_projection;
+  double  rtol_viscous;
+  double  atol_pressure;  /* absolute tolerance of the pressure solve (the paper: 1e-12) */
+  int32_t max_iter;       /* iteration limit of each solve */
+} dg_step_opts;
+
+typedef struct {
+  int32_t it_pressure, it_projection, it_viscous;   /* CG iterations of the three solves */
+  double  kinetic_energy;   /* e_k of u_np1 */
+  double  dissipation;      /* eps of u_np1 (nu from opts) */
+  double  seconds;          /* wall time of the call */
+} dg_step_report;
+
+/*
+ * One time step of the dual splitting scheme (Sec. 3.1; matrix form of
+ * Sec. 3.3) on the periodic mesh of desc, in double precision, no body force:
+ *   convective step  U^ = (sum_i alpha_i U^{n-i} - dt M^-1 sum_i beta_i C(U^{n-i})) / gamma_0
+ *   pressure step    L P = -(gamma_0/dt) D U^        (degree k-1; FP64 CG with the FP32
+ *                                                     Chebyshev(5) preconditioner)
+ *   projection step  (M + A_D + A_C) U^^ = M U^ - (dt/gamma_0) G P   (inverse-mass PCG)
+ *   viscous step     (gamma_0/dt M + nu L) U^{n+1} = (gamma_0/dt) M U^^  (inverse-mass PCG)
+ * BDF1: gamma_0 = 1, alpha = 1, beta = 1; BDF2: gamma_0 = 3/2,
+ * alpha = (2, -1/2), beta = (2, -1).  C is the convective form of
+ * dg_apply_convective (lf_factor from desc), D and G those of the mixed-order
+ * calls above, L the SIPG form (penalty_factor from desc) at degree k-1 for
+ * the pressure and k for the velocity, A_D and A_C those of
+ * dg_apply_projection with tau_D = zeta_d |u_ex|_e h/(k+1) dt and
+ * tau_C = zeta_c |u_ex|_e dt per element, u_ex = sum_i beta_i U^{n-i},
+ * |u_ex|_e its element-averaged magnitude, h = (element volume)^(1/3).
+ *   desc: velocity degree k (2..11), the mesh; n_q 0; scale and n_comp unused.
+ *   u_n, u_nm1 (order 2), u_np1: [3][N_el][(k+1)^3] doubles (device);
+ *   p: [N_el][k^3] doubles (device): in, the pressure solve's initial guess
+ *   (e.g. the previous pressure); out, P^{n+1} (zero coefficient mean).
+ *   u_np1 and p must not overlap each other or the inputs.
+ * The library keeps seven velocity-sized work vectors per GPU.  Returns
+ * DG_OK, a negative error, or DG_NOT_CONVERGED / DG_ERR_BREAKDOWN of the
+ * solve that failed (u_np1 then does not hold the step's result).  Blocks.
+ */
+int dg_dual_splitting_step(const dg_op_desc* desc, const dg_step_opts* opts, const double* u_n,
+                           const double* u_nm1, double* u_np1, double* p, dg_step_report* report,
+                           void* hip_stream);
+
 enum { DG_OP_HELMHOLTZ = 0, DG_OP_PROJECTION = 1 };
 
 /*

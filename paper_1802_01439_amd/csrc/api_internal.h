@@ -27,6 +27,7 @@ double cell_volume(const dg_op_desc* d);
 // M1^-1 of the 1D LGL mass on [0,1] (row major, n x n)
 std::vector<double> inverse_mass_1d(int k);
 ProjPlan make_proj_plan(const dg_op_desc* d);
+DivPlan make_div_plan(const dg_op_desc* d);
 int default_conv_nq(int k);
 int make_conv_plan(const dg_op_desc* d, ConvPlan& P);
 

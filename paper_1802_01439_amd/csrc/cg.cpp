@@ -27,7 +27,8 @@
 // (x_k - x_{k-1}) + (2 rho_k/delta) D^-1 (r - A x_k) with x_0 = 0, so that
 // no step vector is stored.
 // lmax is 1.1x the largest Ritz value of 25 Lanczos steps (plain Jacobi-PCG
-// on a hashed random zero-mean vector); lmin = lmax / range.
+// on a hashed random zero-mean vector), computed once per operator and kept;
+// lmin = lmax / range.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -63,6 +64,17 @@ struct Workspace {
 
 std::mutex g_ws_mutex;
 std::map<int, Workspace> g_ws;
+
+// lambda_max estimates by operator (degree, mesh, box, n_q, penalty, scale,
+// projection): the Lanczos start vector is a fixed hash, so a repeated solve
+// on the same operator would compute the same value
+std::mutex g_lmax_mutex;
+std::map<std::vector<double>, double> g_lmax;
+
+std::vector<double> lmax_key(const dg_op_desc* d, bool project) {
+  return {(double)d->degree, (double)d->n_el[0], (double)d->n_el[1], (double)d->n_el[2], d->length[0],
+          d->length[1], d->length[2], (double)d->n_q, d->penalty_factor, d->scale, project ? 1.0 : 0.0};
+}
 
 hipError_t ensure(Workspace& w, long long n, long npartial) {
   hipError_t e;
@@ -229,7 +241,16 @@ int cg_run(const dg_op_desc* desc, const dg_cg_opts* opts, const double* b, doub
   double* H = W.host;
   const double dn = (double)n;
   double lmax = 0, theta = 0, delta = 0;
+  bool have_lmax = false;
   if (cheb) {
+    std::lock_guard<std::mutex> lk(g_lmax_mutex);
+    auto it = g_lmax.find(lmax_key(desc, S.project));
+    if (it != g_lmax.end()) {
+      lmax = it->second;
+      have_lmax = true;
+    }
+  }
+  if (cheb && !have_lmax) {
     // Lanczos coefficients of plain Jacobi-PCG on a random zero-mean vector
     const int L = 25;
     S.ok(cg_hash_fill(W.tmp, 12345ULL, n, W.partial, S.s));
@@ -271,10 +292,14 @@ int cg_run(const dg_op_desc* desc, const dg_cg_opts* opts, const double* b, doub
       if (i + 1 < m) tb[i] = std::sqrt(be[i]) / al[i];
     }
     lmax = 1.1 * tridiag_max_eig(ta, tb);
+    S.matvec64 = 0;
+    std::lock_guard<std::mutex> lk(g_lmax_mutex);
+    g_lmax[lmax_key(desc, S.project)] = lmax;
+  }
+  if (cheb) {
     const double lmin = lmax / opts->cheb_range;
     theta = 0.5 * (lmax + lmin);
     delta = 0.5 * (lmax - lmin);
-    S.matvec64 = 0;
   }
   if (!S.ok(hipStreamSynchronize(S.s))) return hip_fail(S.err, "setup");
   const double t_setup = now();

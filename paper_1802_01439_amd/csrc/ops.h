@@ -107,4 +107,21 @@ hipError_t launch_inverse_mass(int k, const std::vector<double>& Minv, double sc
 
 int vjp_max_degree(bool f32);
 
+// Dual-splitting step kernels (mixed.hip).  Mixed-order divergence
+// (grad = false: u [3][N_el][(k+1)^3] -> [N_el][k^3]) and gradient (grad =
+// true: p [N_el][k^3] -> [3][N_el][(k+1)^3]) of plan P (velocity degree
+// P.k >= 2), times scale.
+hipError_t launch_mixed(const DivPlan& P, bool grad, bool f32, const void* src, void* dst, double scale,
+                        hipStream_t s);
+// tau_d[e] = fd |u|_e, tau_c[e] = fc |u|_e, |u|_e the element average of the
+// velocity magnitude (FP64, degree k, k+1 Gauss points)
+hipError_t launch_penalty(int k, const MeshArgs& mesh, const double* u, double* tau_d, double* tau_c, double fd,
+                          double fc, hipStream_t s);
+// out2 = (sum_e int |u|^2, sum_e int grad u : grad u); partial: 2 N_el doubles
+hipError_t launch_diagnostics(int k, const MeshArgs& mesh, const double* u, double* partial, double* out2,
+                              double vol, const double ih[3], hipStream_t s);
+// y = a0 x0 + a1 x1 + a2 x2 (x1, x2 may be null); y may be one of the x
+hipError_t launch_lincomb(double* y, const double* x0, const double* x1, const double* x2, double a0, double a1,
+                          double a2, long long n, hipStream_t s);
+
 }  // namespace dgmf

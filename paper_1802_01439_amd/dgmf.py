@@ -25,7 +25,9 @@ DG_PC_JACOBI_F64, DG_PC_CHEB_F32 = 0, 1
 DG_OP_HELMHOLTZ, DG_OP_PROJECTION = 0, 1
 
 EXPORTS = ("dg_apply_laplace", "dg_apply_convective", "dg_vjp_convective", "dg_apply_divergence",
-           "dg_apply_inverse_mass", "dg_apply_helmholtz", "dg_apply_projection", "dg_apply_gradient", "dg_prolongate", "dg_restrict", "dg_gmg_vcycle", "dg_gmg_cg_solve", "dg_cg_solve", "dg_cg_solve_noalloc", "dg_mass_pcg_solve", "dg_laplace_diagonal", "dg_lgl_nodes", "dg_error_string", "dg_last_error")
+           "dg_apply_inverse_mass", "dg_apply_helmholtz", "dg_apply_projection", "dg_apply_gradient", "dg_prolongate", "dg_restrict", "dg_gmg_vcycle", "dg_gmg_cg_solve", "dg_cg_solve", "dg_cg_solve_noalloc", "dg_mass_pcg_solve", "dg_apply_divergence_mixed", "dg_apply_gradient_mixed",
+           "dg_tgv_diagnostics", "dg_dual_splitting_step", "dg_laplace_diagonal", "dg_lgl_nodes", "dg_error_string",
+           "dg_last_error")
 
 
 class OpDesc(ctypes.Structure):
@@ -44,6 +46,21 @@ class CgReport(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("matvec_f64", ctypes.c_int32), ("matvec_f32", ctypes.c_int32),
                 ("rel_res", ctypes.c_double), ("true_rel_res", ctypes.c_double), ("lambda_max", ctypes.c_double),
                 ("seconds_solve", ctypes.c_double), ("seconds_setup", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class StepOpts(ctypes.Structure):
+    _fields_ = [("order", ctypes.c_int32), ("dt", ctypes.c_double), ("nu", ctypes.c_double),
+                ("zeta_d", ctypes.c_double), ("zeta_c", ctypes.c_double), ("rtol_pressure", ctypes.c_double),
+                ("rtol_projection", ctypes.c_double), ("rtol_viscous", ctypes.c_double),
+                ("atol_pressure", ctypes.c_double), ("max_iter", ctypes.c_int32)]
+
+
+class StepReport(ctypes.Structure):
+    _fields_ = [("it_pressure", ctypes.c_int32), ("it_projection", ctypes.c_int32), ("it_viscous", ctypes.c_int32),
+                ("kinetic_energy", ctypes.c_double), ("dissipation", ctypes.c_double), ("seconds", ctypes.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -86,6 +103,11 @@ def lib():
         L.dg_cg_solve_noalloc.argtypes = [pd, ctypes.POINTER(CgOpts), vp, vp, ctypes.POINTER(CgReport), vp]
         L.dg_mass_pcg_solve.argtypes = [pd, ctypes.c_int32, ctypes.c_double, vp, vp, vp, vp, ctypes.c_double,
                                          ctypes.c_int32, ctypes.POINTER(CgReport), vp]
+        L.dg_apply_divergence_mixed.argtypes = [pd, ctypes.c_int, vp, vp, vp]
+        L.dg_apply_gradient_mixed.argtypes = [pd, ctypes.c_int, vp, vp, vp]
+        L.dg_tgv_diagnostics.argtypes = [pd, vp, ctypes.c_double, dp, vp]
+        L.dg_dual_splitting_step.argtypes = [pd, ctypes.POINTER(StepOpts), vp, vp, vp, vp,
+                                             ctypes.POINTER(StepReport), vp]
         L.dg_laplace_diagonal.argtypes = [pd, dp]
         L.dg_lgl_nodes.argtypes = [i32, dp]
         L.dg_error_string.argtypes = [ctypes.c_int]
@@ -93,7 +115,9 @@ def lib():
         L.dg_last_error.argtypes = []
         L.dg_last_error.restype = ctypes.c_char_p
         for name in ("dg_apply_laplace", "dg_apply_convective", "dg_vjp_convective", "dg_apply_divergence",
-                     "dg_apply_inverse_mass", "dg_apply_helmholtz", "dg_apply_projection", "dg_apply_gradient", "dg_prolongate", "dg_restrict", "dg_gmg_vcycle", "dg_gmg_cg_solve", "dg_cg_solve", "dg_cg_solve_noalloc", "dg_mass_pcg_solve", "dg_laplace_diagonal", "dg_lgl_nodes"):
+                     "dg_apply_inverse_mass", "dg_apply_helmholtz", "dg_apply_projection", "dg_apply_gradient", "dg_prolongate", "dg_restrict", "dg_gmg_vcycle", "dg_gmg_cg_solve", "dg_cg_solve", "dg_cg_solve_noalloc", "dg_mass_pcg_solve",
+                     "dg_apply_divergence_mixed", "dg_apply_gradient_mixed", "dg_tgv_diagnostics",
+                     "dg_dual_splitting_step", "dg_laplace_diagonal", "dg_lgl_nodes"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -413,6 +437,81 @@ def mass_pcg_solve(desc, op, b, x=None, mass_factor=0.0, tau_d=None, tau_c=None,
                                         ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(x.data_ptr()), float(rtol),
                                         int(max_iter), ctypes.byref(rep), _stream(b)), soft_ok=True)
     return x, rep.as_dict(), rc
+
+
+def apply_divergence_mixed(desc, u, out=None):
+    """d_h(q_i, u) for the degree-(k-1) pressure basis; u: [3, N_el, (k+1)^3] -> [N_el, k^3]."""
+    torch = _torch()
+    k = desc.degree
+    _check_tensor(u, "u", (3, _nel(desc), (k + 1) ** 3))
+    if out is None:
+        out = torch.empty((_nel(desc), k ** 3), dtype=u.dtype, device=u.device)
+    _check_tensor(out, "out", (_nel(desc), k ** 3), like=u)
+    _placed(u, out)
+    _check(lib().dg_apply_divergence_mixed(ctypes.byref(desc), _dtype_code(u), ctypes.c_void_p(u.data_ptr()),
+                                           ctypes.c_void_p(out.data_ptr()), _stream(u)))
+    return out
+
+
+def apply_gradient_mixed(desc, p, out=None):
+    """g_h(phi_i e_j, p) for the degree-k velocity basis; p: [N_el, k^3] -> [3, N_el, (k+1)^3]."""
+    torch = _torch()
+    k = desc.degree
+    _check_tensor(p, "p", (_nel(desc), k ** 3))
+    if out is None:
+        out = torch.empty((3, _nel(desc), (k + 1) ** 3), dtype=p.dtype, device=p.device)
+    _check_tensor(out, "out", (3, _nel(desc), (k + 1) ** 3), like=p)
+    _placed(p, out)
+    _check(lib().dg_apply_gradient_mixed(ctypes.byref(desc), _dtype_code(p), ctypes.c_void_p(p.data_ptr()),
+                                         ctypes.c_void_p(out.data_ptr()), _stream(p)))
+    return out
+
+
+def tgv_diagnostics(desc, u, nu):
+    """(e_k, eps) of a float64 velocity field u: [3, N_el, (k+1)^3]."""
+    torch = _torch()
+    _check_tensor(u, "u", (3, _nel(desc), (desc.degree + 1) ** 3), dtype=torch.float64)
+    _placed(u)
+    out = np.zeros(2)
+    _check(lib().dg_tgv_diagnostics(ctypes.byref(desc), ctypes.c_void_p(u.data_ptr()), float(nu),
+                                    out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _stream(u)))
+    return float(out[0]), float(out[1])
+
+
+def dual_splitting_step(desc, u_n, u_nm1=None, p=None, out=None, dt=1e-3, nu=1.0 / 1600, order=2,
+                        zeta_d=1.0, zeta_c=1.0, rtol=1e-6, rtol_pressure=None, rtol_projection=None,
+                        rtol_viscous=None, atol_pressure=1e-12, max_iter=2000):
+    """One dual-splitting step; u_n, u_nm1, out: float64 [3, N_el, (k+1)^3];
+    p: float64 [N_el, k^3], initial guess in, P^{n+1} out (zeros if None).
+    Returns (u_np1, p, report dict, return code)."""
+    torch = _torch()
+    k = desc.degree
+    vshape, pshape = (3, _nel(desc), (k + 1) ** 3), (_nel(desc), k ** 3)
+    _check_tensor(u_n, "u_n", vshape, dtype=torch.float64)
+    if order == 2:
+        if u_nm1 is None:
+            raise ValueError("order 2 needs u_nm1")
+        _check_tensor(u_nm1, "u_nm1", vshape, like=u_n)
+    if p is None:
+        p = torch.zeros(pshape, dtype=torch.float64, device=u_n.device)
+    _check_tensor(p, "p", pshape, like=u_n)
+    if out is None:
+        out = torch.empty_like(u_n)
+    _check_tensor(out, "out", vshape, like=u_n)
+    _placed(u_n, p, out, *([u_nm1] if order == 2 else []))
+    o = StepOpts()
+    o.order, o.dt, o.nu, o.zeta_d, o.zeta_c = int(order), float(dt), float(nu), float(zeta_d), float(zeta_c)
+    o.rtol_pressure = float(rtol if rtol_pressure is None else rtol_pressure)
+    o.rtol_projection = float(rtol if rtol_projection is None else rtol_projection)
+    o.rtol_viscous = float(rtol if rtol_viscous is None else rtol_viscous)
+    o.atol_pressure = float(atol_pressure)
+    o.max_iter = int(max_iter)
+    rep = StepReport()
+    nm1 = ctypes.c_void_p(u_nm1.data_ptr()) if order == 2 else None
+    rc = _check(lib().dg_dual_splitting_step(ctypes.byref(desc), ctypes.byref(o), ctypes.c_void_p(u_n.data_ptr()),
+                                             nm1, ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(p.data_ptr()),
+                                             ctypes.byref(rep), _stream(u_n)), soft_ok=True)
+    return out, p, rep.as_dict(), rc
 
 
 def laplace_diagonal(desc):

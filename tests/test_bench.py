@@ -86,7 +86,11 @@ def _full_record():
     extras = {"inverse_mass_sweep": per_k, "projection_sweep": per_k, "gradient_sweep": per_k,
               "divergence_sweep": per_k, "transfer_sweep": per_k, "cg_k7_24cubed": cg,
               "vjp_k4_32cubed": {"f64": {"dofs_per_s": 2e10, "us": 608.5, "hbm_frac": 0.061},
-                                 "f32": {"dofs_per_s": 4e10, "us": 266.0, "hbm_frac": 0.069}}}
+                                 "f32": {"dofs_per_s": 4e10, "us": 266.0, "hbm_frac": 0.069}},
+              "dual_splitting_k7_24cubed": {
+                  "dt": 0.01, "dofs": 22_643_712, "ms_per_step": 45.6789, "dofs_steps_per_s": 5e8,
+                  "steps": [{"it_pressure": 30, "it_projection": 12, "it_viscous": 3, "kinetic_energy": 0.1249876,
+                             "dissipation": 4.6877e-4, "seconds": 0.045, "wall_s": 0.0456}] * 5}}
     return {"metric": bench.METRIC, "value": 8.3e10, "unit": "DoFs/s", "n_gpus": 1, "steps": 20, "warmup": 5,
             "ms_per_step": 16.1, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
             "dtype": "f64+f32", "data": "synthetic",
@@ -124,6 +128,7 @@ def test_summary_line_is_compact_and_complete():
     assert all(len(v) == 10 for v in s["sweep"]["gdofs_per_s"].values())
     assert s["sweep"]["k"] == list(range(2, 12))
     assert s["cpu_baseline"]["config5_rel_err_vs_oracle_fdm"]["chebyshev5_f32"] == 2.3e-11
+    assert s["extras"]["dual_splitting_k7_24cubed"]["iterations_p_proj_visc"] == [30, 12, 3]
 
 
 def test_alu_peak_is_the_unpacked_vector_rate():
