@@ -356,21 +356,13 @@ def extras(torch, dgmf, inputs, dev, args, which=("vjp", "cg", "mass", "proj", "
             if keep is not None:
                 keep[name] = x.cpu().numpy()
         res["speedup_solve"] = res["jacobi_f64"]["seconds_solve"] / res["chebyshev5_f32"]["seconds_solve"]
-        # CG with one FP64 V-cycle per iteration (24^3 -> 3^3, four levels);
-        # level bounds of D^-1 A from dg_cg_solve's own set-up on each level
-        lam = []
-        for l in range(4):
-            dl = dgmf.make_desc(k, N >> l)
-            g = torch.Generator(device=dev)
-            g.manual_seed(109 + l)
-            bl = torch.rand(((N >> l) ** 3, (k + 1) ** 3), generator=g, dtype=torch.float64, device=dev) - 0.5
-            bl -= bl.mean()
-            _, rl, _ = dgmf.cg_solve(dl, bl, precond=dgmf.DG_PC_CHEB_F32, max_iter=1)
-            lam.append(rl["lambda_max"])
+        # CG with one V-cycle per iteration (24^3 -> 3^3, four levels); the
+        # library estimates the level bounds of D^-1 A (the Chebyshev CG's
+        # Lanczos bound, kept per operator)
         for cyc, cdt in (("f64", dgmf.DG_F64), ("f32", dgmf.DG_F32)):
             for rtol in (1e-10, 1e-6):
-                dgmf.gmg_cg_solve(d, b, lam, rtol=rtol, cycle_dtype=cdt)       # warm-up
-                x, rep, rc = dgmf.gmg_cg_solve(d, b, lam, rtol=rtol, cycle_dtype=cdt)
+                dgmf.gmg_cg_solve(d, b, levels=4, rtol=rtol, cycle_dtype=cdt)       # warm-up
+                x, rep, rc = dgmf.gmg_cg_solve(d, b, levels=4, rtol=rtol, cycle_dtype=cdt)
                 rep["rc"] = rc
                 res[f"gmg_vcycle_{cyc}_rtol{rtol:g}"] = rep
                 if keep is not None and rtol == 1e-10:
@@ -467,31 +459,21 @@ def mass_pcg_extra(torch, dgmf, inputs, dev, k=5, N=16):
 def _vcycle_extra(torch, dgmf, inputs, dev, k=7, N=24, levels=4, reps=5):
     """One V-cycle, FP64 and FP32, on the pressure Poisson size (k=7, 24^3 ->
     12^3 -> 6^3 -> 3^3), Chebyshev degree 5, coarse degree 10.  The per-level bounds
-    of D^-1 A come from the library's own Lanczos estimate (the setup of
-    dg_cg_solve with the Chebyshev preconditioner, one iteration, on each
-    level).  Wall time per cycle includes the cycle's set-up (level
-    diagonals, work vectors) and its final synchronisation."""
-    lam = []
-    for l in range(levels):
-        dl = dgmf.make_desc(k, N >> l)
-        g = torch.Generator(device=dev)
-        g.manual_seed(107 + l)
-        b = torch.rand(((N >> l) ** 3, (k + 1) ** 3), generator=g, dtype=torch.float64, device=dev) - 0.5
-        b -= b.mean()
-        _, rep, _ = dgmf.cg_solve(dl, b, precond=dgmf.DG_PC_CHEB_F32, max_iter=1)
-        lam.append(rep["lambda_max"])
+    of D^-1 A are the library's own Lanczos estimates (computed once per
+    operator and kept).  Wall time per cycle includes the cycle's set-up
+    (level diagonals, work vectors) and its final synchronisation."""
     d = dgmf.make_desc(k, N)
     g = torch.Generator(device=dev)
     g.manual_seed(108)
     r = torch.rand((N ** 3, (k + 1) ** 3), generator=g, dtype=torch.float64, device=dev) - 0.5
     r -= r.mean()
-    res = {"levels": levels, "lambda_max": lam, "fine_operator_applications": 2 * (5 - 1) + 2}
+    res = {"levels": levels, "fine_operator_applications": 2 * (5 - 1) + 2}
     for name, rr in (("f64", r), ("f32", r.float())):
-        z = dgmf.gmg_vcycle(d, rr, lam)
+        z = dgmf.gmg_vcycle(d, rr, levels=levels)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(reps):
-            dgmf.gmg_vcycle(d, rr, lam, out=z)
+            dgmf.gmg_vcycle(d, rr, levels=levels, out=z)
         t = (time.perf_counter() - t0) / reps
         res["ms_per_cycle" if name == "f64" else "ms_per_cycle_f32"] = t * 1e3
     return res

@@ -372,8 +372,10 @@ int dg_mass_pcg_solve(const dg_op_desc* desc, int32_t op, double mass_factor, co
  *   desc: the finest mesh, n_comp = 1, element counts divisible by
  *   2^(levels-1); lambda_max: host array of `levels` eigenvalue bounds of
  *   D_l^-1 A_l (level diagonals and Chebyshev coefficients are rounded to
- *   FP32 for DG_F32); dtype: DG_F64 or DG_F32; r, z: [N_el][n^3] values of
- *   that type (device), must not overlap.
+ *   FP32 for DG_F32), or NULL: then each level's bound is the one
+ *   dg_cg_solve estimates for the Chebyshev preconditioner (1.1 x the largest
+ *   Ritz value of 25 Lanczos steps, kept per operator); dtype: DG_F64 or
+ *   DG_F32; r, z: [N_el][n^3] values of that type (device), must not overlap.
  * Allocates its level vectors, blocks until the cycle has run.
  */
 int dg_gmg_vcycle(const dg_op_desc* desc, int32_t levels, int32_t degree, double smoothing_range,
@@ -385,12 +387,16 @@ int dg_gmg_vcycle(const dg_op_desc* desc, int32_t levels, int32_t degree, double
  * iterates are taken at zero coefficient mean) by FP64 CG preconditioned with
  * one V-cycle per iteration (Sec. 3.3: Chebyshev degree 5, smoothing
  * range 20, coarse Chebyshev of degree 10), flexible beta.
- *   lambda_max: host array of `levels` bounds as for dg_gmg_vcycle;
+ *   lambda_max: host array of `levels` bounds as for dg_gmg_vcycle, or NULL
+ *   (estimated per level as there);
  *   cycle_dtype: DG_F64 (the cycle of dg_gmg_vcycle) or DG_F32 (the cycle in
  *   single precision: the residual rounded to FP32 on entry, the correction
  *   widened on exit, the CG itself in FP64 as Sec. 3.3 splits the work);
  *   b, x: [N_el][n^3] doubles (device), x: initial guess in, solution out;
- *   stops when |r| <= rtol |b - mean(b)|; report: host pointer, may be NULL.
+ *   stops when |r| <= rtol |b - mean(b)|; report: host pointer, may be NULL;
+ *   its matvec_f64 / matvec_f32 count the outer FP64 applies and every
+ *   level apply of the cycles (all levels) by precision, lambda_max the
+ *   finest level's bound.
  * Returns DG_OK, DG_NOT_CONVERGED or DG_ERR_BREAKDOWN, or a negative error.
  * Blocks the calling thread.
  */

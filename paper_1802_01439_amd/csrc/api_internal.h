@@ -28,6 +28,9 @@ double cell_volume(const dg_op_desc* d);
 std::vector<double> inverse_mass_1d(int k);
 ProjPlan make_proj_plan(const dg_op_desc* d);
 DivPlan make_div_plan(const dg_op_desc* d);
+// lambda_max bound of D^-1 A for the SIPG form of d (n_comp = 1): 1.1 x the
+// largest Ritz value of 25 Lanczos steps, kept per operator (cg.cpp)
+int laplace_lambda_max(const dg_op_desc* d, bool project, void* hip_stream, double* lmax);
 int default_conv_nq(int k);
 int make_conv_plan(const dg_op_desc* d, ConvPlan& P);
 

@@ -181,6 +181,81 @@ struct Solver {
   }
 };
 
+// 1.1 x the largest Ritz value of 25 Lanczos steps of plain Jacobi-PCG on D^-1 A
+// (the Lanczos tridiagonal from the PCG coefficients), started from a hashed
+// zero-mean (with projection) vector; W.dinv must hold D^-1 of one element.
+// Stored in the per-operator cache.
+int lanczos_lmax(Solver& S, const dg_op_desc* desc, double* lmax_out) {
+  Workspace& W = *S.w;
+  double* H = W.host;
+  const long long n = S.n;
+  const double dn = (double)n;
+  const int L = 25;
+  S.ok(cg_hash_fill(W.tmp, 12345ULL, n, W.partial, S.s));
+  if (!S.fetch(1)) return hip_fail(S.err, "Lanczos start");
+  const double mu0 = S.project ? H[0] / dn : 0.0;
+  S.ok(cg_axpb(W.r, W.tmp, 1.0, -mu0, n, S.s));
+  S.ok(cg_fill(W.zold, 0.0, n, S.s));
+  S.ok(cg_jacobi(W.r, W.z, W.zold, W.dinv, S.n3, 0.0, n, W.partial, S.s));
+  if (!S.fetch(4)) return hip_fail(S.err, "Lanczos start");
+  double muz = S.project ? H[0] / dn : 0.0, rz = H[1];
+  S.ok(cg_update_p(W.z, W.p, W.zold, muz, 0.0, n, S.s));
+  std::vector<double> al, be;
+  for (int it = 0; it < L; ++it) {
+    S.apply64(W.p, W.q);
+    S.ok(cg_dot(W.p, W.q, n, W.partial, S.s));
+    if (!S.fetch(1)) return hip_fail(S.err, "Lanczos");
+    const double pq = H[0];
+    if (!(pq > 0) || !(rz > 0)) break;
+    const double alpha = rz / pq;
+    S.ok(cg_update_xr(W.tmp, W.r, W.p, W.q, alpha, n, W.partial, S.s));
+    if (!S.fetch(1)) return hip_fail(S.err, "Lanczos");
+    const double mur = S.project ? H[0] / dn : 0.0;
+    S.ok(cg_jacobi(W.r, W.z, W.zold, W.dinv, S.n3, mur, n, W.partial, S.s));
+    if (!S.fetch(4)) return hip_fail(S.err, "Lanczos");
+    muz = S.project ? H[0] / dn : 0.0;
+    const double rz_new = H[1];
+    const double beta = rz_new / rz;
+    al.push_back(alpha);
+    be.push_back(beta);
+    S.ok(cg_update_p(W.z, W.p, W.zold, muz, beta, n, S.s));
+    rz = rz_new;
+    if (!(rz > 0)) break;
+  }
+  const int m = (int)al.size();
+  if (m == 0) return fail(DG_ERR_BREAKDOWN, "eigenvalue estimate failed (operator not positive definite?)");
+  std::vector<double> ta(m), tb(m > 1 ? m - 1 : 0);
+  for (int i = 0; i < m; ++i) {
+    ta[i] = 1.0 / al[i] + (i > 0 ? be[i - 1] / al[i - 1] : 0.0);
+    if (i + 1 < m) tb[i] = std::sqrt(be[i]) / al[i];
+  }
+  *lmax_out = 1.1 * tridiag_max_eig(ta, tb);
+  std::lock_guard<std::mutex> lk(g_lmax_mutex);
+  g_lmax[lmax_key(desc, S.project)] = *lmax_out;
+  return DG_OK;
+}
+
+// D^-1 of one element of the operator of desc, in W.dinv / W.dinv32
+int upload_dinv(const dg_op_desc* desc, Workspace& W, hipStream_t s, std::vector<double>& dinv) {
+  const long long n3 = dofs_per_element(desc);
+  std::vector<double> diag(n3);
+  std::vector<float> dinv32(n3);
+  dinv.assign(n3, 0.0);
+  int rc = dg_laplace_diagonal(desc, diag.data());
+  if (rc) return rc;
+  for (long long i = 0; i < n3; ++i) {
+    if (!(diag[i] > 0)) return fail(DG_ERR_BREAKDOWN, "operator diagonal is not positive");
+    dinv[i] = 1.0 / diag[i];
+    dinv32[i] = (float)dinv[i];
+  }
+  hipError_t e;
+  if ((e = hipMemcpyAsync(W.dinv, dinv.data(), n3 * 8, hipMemcpyHostToDevice, s)) != hipSuccess ||
+      (e = hipMemcpyAsync(W.dinv32, dinv32.data(), n3 * 4, hipMemcpyHostToDevice, s)) != hipSuccess ||
+      (e = hipStreamSynchronize(s)) != hipSuccess)
+    return hip_fail(e, "diagonal upload");
+  return DG_OK;
+}
+
 // Arguments of dg_cg_solve and its allocation-free variant; sets the DoF
 // counts.
 int cg_validate(const dg_op_desc* desc, const dg_cg_opts* opts, const double* b, const double* x, long long* n_out,
@@ -226,18 +301,8 @@ int cg_run(const dg_op_desc* desc, const dg_cg_opts* opts, const double* b, doub
   S.project = opts->project_mean != 0;
 
   // ---- setup: diagonal, eigenvalue estimate ----
-  std::vector<double> diag(n3), dinv(n3);
-  std::vector<float> dinv32(n3);
-  rc = dg_laplace_diagonal(desc, diag.data());
-  if (rc) return rc;
-  for (long long i = 0; i < n3; ++i) {
-    if (!(diag[i] > 0)) return fail(DG_ERR_BREAKDOWN, "operator diagonal is not positive");
-    dinv[i] = 1.0 / diag[i];
-    dinv32[i] = (float)dinv[i];
-  }
-  if (!S.ok(hipMemcpyAsync(W.dinv, dinv.data(), n3 * 8, hipMemcpyHostToDevice, S.s)) ||
-      !S.ok(hipMemcpyAsync(W.dinv32, dinv32.data(), n3 * 4, hipMemcpyHostToDevice, S.s)))
-    return hip_fail(S.err, "diagonal upload");
+  std::vector<double> dinv;
+  if ((rc = upload_dinv(desc, W, S.s, dinv)) != DG_OK) return rc;
   double* H = W.host;
   const double dn = (double)n;
   double lmax = 0, theta = 0, delta = 0;
@@ -251,50 +316,8 @@ int cg_run(const dg_op_desc* desc, const dg_cg_opts* opts, const double* b, doub
     }
   }
   if (cheb && !have_lmax) {
-    // Lanczos coefficients of plain Jacobi-PCG on a random zero-mean vector
-    const int L = 25;
-    S.ok(cg_hash_fill(W.tmp, 12345ULL, n, W.partial, S.s));
-    if (!S.fetch(1)) return hip_fail(S.err, "Lanczos start");
-    const double mu0 = S.project ? H[0] / dn : 0.0;
-    S.ok(cg_axpb(W.r, W.tmp, 1.0, -mu0, n, S.s));
-    S.ok(cg_fill(W.zold, 0.0, n, S.s));
-    S.ok(cg_jacobi(W.r, W.z, W.zold, W.dinv, S.n3, 0.0, n, W.partial, S.s));
-    if (!S.fetch(4)) return hip_fail(S.err, "Lanczos start");
-    double muz = S.project ? H[0] / dn : 0.0, rz = H[1];
-    S.ok(cg_update_p(W.z, W.p, W.zold, muz, 0.0, n, S.s));
-    std::vector<double> al, be;
-    for (int it = 0; it < L; ++it) {
-      S.apply64(W.p, W.q);
-      S.ok(cg_dot(W.p, W.q, n, W.partial, S.s));
-      if (!S.fetch(1)) return hip_fail(S.err, "Lanczos");
-      const double pq = H[0];
-      if (!(pq > 0) || !(rz > 0)) break;
-      const double alpha = rz / pq;
-      S.ok(cg_update_xr(W.tmp, W.r, W.p, W.q, alpha, n, W.partial, S.s));
-      if (!S.fetch(1)) return hip_fail(S.err, "Lanczos");
-      const double mur = S.project ? H[0] / dn : 0.0;
-      S.ok(cg_jacobi(W.r, W.z, W.zold, W.dinv, S.n3, mur, n, W.partial, S.s));
-      if (!S.fetch(4)) return hip_fail(S.err, "Lanczos");
-      muz = S.project ? H[0] / dn : 0.0;
-      const double rz_new = H[1];
-      const double beta = rz_new / rz;
-      al.push_back(alpha);
-      be.push_back(beta);
-      S.ok(cg_update_p(W.z, W.p, W.zold, muz, beta, n, S.s));
-      rz = rz_new;
-      if (!(rz > 0)) break;
-    }
-    const int m = (int)al.size();
-    if (m == 0) return fail(DG_ERR_BREAKDOWN, "eigenvalue estimate failed (operator not positive definite?)");
-    std::vector<double> ta(m), tb(m > 1 ? m - 1 : 0);
-    for (int i = 0; i < m; ++i) {
-      ta[i] = 1.0 / al[i] + (i > 0 ? be[i - 1] / al[i - 1] : 0.0);
-      if (i + 1 < m) tb[i] = std::sqrt(be[i]) / al[i];
-    }
-    lmax = 1.1 * tridiag_max_eig(ta, tb);
+    if ((rc = lanczos_lmax(S, desc, &lmax)) != DG_OK) return rc;
     S.matvec64 = 0;
-    std::lock_guard<std::mutex> lk(g_lmax_mutex);
-    g_lmax[lmax_key(desc, S.project)] = lmax;
   }
   if (cheb) {
     const double lmin = lmax / opts->cheb_range;
@@ -433,6 +456,40 @@ int cg_run(const dg_op_desc* desc, const dg_cg_opts* opts, const double* b, doub
 }
 
 }  // namespace
+
+int laplace_lambda_max(const dg_op_desc* desc, bool project, void* hip_stream, double* lmax) {
+  int rc = validate_desc(desc);
+  if (rc) return rc;
+  if (desc->n_comp != 1) return fail(DG_ERR_INVALID_ARG, "the eigenvalue estimate needs n_comp = 1");
+  {
+    std::lock_guard<std::mutex> lk(g_lmax_mutex);
+    auto it = g_lmax.find(lmax_key(desc, project));
+    if (it != g_lmax.end()) {
+      *lmax = it->second;
+      return DG_OK;
+    }
+  }
+  std::lock_guard<std::mutex> lock(g_ws_mutex);
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  Workspace& W = g_ws[dev];
+  const LaplacePlan LP = make_laplace_plan(desc, 1);
+  const long long n = num_elements(desc) * dofs_per_element(desc);
+  if ((e = ensure(W, n, std::max(cg_apply_grid(LP, false), 3 * cg_apply_grid(LP, true)))) != hipSuccess)
+    return hip_fail(e, "CG workspace allocation");
+  Solver S;
+  S.desc = desc;
+  S.P = LP;
+  S.w = &W;
+  S.s = (hipStream_t)hip_stream;
+  S.n = n;
+  S.n3 = (int)dofs_per_element(desc);
+  S.project = project;
+  std::vector<double> dinv;
+  if ((rc = upload_dinv(desc, W, S.s, dinv)) != DG_OK) return rc;
+  return lanczos_lmax(S, desc, lmax);
+}
 
 }  // namespace dgmf
 

@@ -49,6 +49,7 @@ struct MgRun {
   double range = 20.0;
   hipStream_t s = nullptr;
   std::vector<double> P0, P1;
+  long long applies = 0;   // level operator applications launched (all levels)
 
   ~MgRun() {
     for (void* p : owned) (void)hipFree(p);
@@ -73,6 +74,7 @@ struct MgRun {
       // in place), so that the fused steps, which alternate between x and
       // L.t, end in x
       if ((e = launch_laplace(L.plan, F32, x, L.t, s)) != hipSuccess) return e;
+      ++applies;
       const double rho = 1.0 / (2.0 * theta / delta - rho_prev);
       if ((e = mg_cheb_next(b, L.t, L.dinv, n3, (T)(rho * rho_prev), (T)(2.0 * rho / delta), L.d, x, L.n, s)) !=
           hipSuccess)
@@ -86,6 +88,7 @@ struct MgRun {
       if ((e = mg_apply_cheb<T>(L.plan, cur, b, L.dinv, (T)(rho * rho_prev), (T)(2.0 * rho / delta), L.d, nxt, s)) !=
           hipSuccess)
         return e;
+      ++applies;
       std::swap(cur, nxt);
       rho_prev = rho;
     }
@@ -112,12 +115,14 @@ struct MgRun {
     if ((e = cheb(L, L.b, L.x, last ? coarse_degree : degree)) != hipSuccess) return e;
     if (last) return hipSuccess;
     if ((e = mg_apply_residual<T>(L.plan, L.x, L.b, L.res, s)) != hipSuccess) return e;
+    ++applies;
     const TransferPlan TP = transfer_plan(l + 1);
     if ((e = launch_transfer(TP, false, F32, L.res, lv[l + 1].b, s)) != hipSuccess) return e;
     if ((e = cycle(l + 1)) != hipSuccess) return e;
     if ((e = launch_transfer(TP, true, F32, lv[l + 1].x, L.t, s)) != hipSuccess) return e;
     if ((e = mg_add(L.x, L.t, L.n, s)) != hipSuccess) return e;
     if ((e = mg_apply_residual<T>(L.plan, L.x, L.b, L.res, s)) != hipSuccess) return e;
+    ++applies;
     if ((e = cheb(L, L.res, L.e, degree)) != hipSuccess) return e;
     return mg_add(L.x, L.e, L.n, s);
   }
@@ -146,12 +151,12 @@ int mg_setup(MgRun<T>& M, const dg_op_desc* desc, int levels, int degree, double
   if (degree < 1 || coarse_degree < 1) return fail(DG_ERR_INVALID_ARG, "smoother degrees must be >= 1");
   if (!(smoothing_range > 1.0) || !std::isfinite(smoothing_range))
     return fail(DG_ERR_INVALID_ARG, "smoothing_range must be finite and > 1");
-  if (!lambda_max) return fail(DG_ERR_INVALID_ARG, "lambda_max is NULL");
   if (desc->n_q != 0 && desc->n_q < desc->degree + 1)
     return fail(DG_ERR_UNSUPPORTED, "the Laplace form needs n_q >= k+1 (exact Gauss integration)");
-  for (int l = 0; l < levels; ++l)
-    if (!(lambda_max[l] > 0.0) || !std::isfinite(lambda_max[l]))
-      return fail(DG_ERR_INVALID_ARG, "lambda_max must be finite and > 0 on every level");
+  if (lambda_max)
+    for (int l = 0; l < levels; ++l)
+      if (!(lambda_max[l] > 0.0) || !std::isfinite(lambda_max[l]))
+        return fail(DG_ERR_INVALID_ARG, "lambda_max must be finite and > 0 on every level");
   for (int d = 0; d < 3; ++d)
     if (desc->n_el[d] % (1 << (levels - 1)) != 0)
       return fail(DG_ERR_INVALID_ARG, "element counts must be divisible by 2^(levels-1)");
@@ -175,7 +180,11 @@ int mg_setup(MgRun<T>& M, const dg_op_desc* desc, int levels, int degree, double
     for (int d = 0; d < 3; ++d) L.desc.n_el[d] = desc->n_el[d] >> l;
     L.plan = make_laplace_plan(&L.desc, 1);
     L.n = num_elements(&L.desc) * M.n3;
-    L.lmax = lambda_max[l];
+    if (lambda_max) {
+      L.lmax = lambda_max[l];
+    } else if ((rc = laplace_lambda_max(&L.desc, true, M.s, &L.lmax)) != DG_OK) {
+      return rc;   // the level's bound: the estimate of the Chebyshev-preconditioned CG
+    }
     if ((rc = dg_laplace_diagonal(&L.desc, diag.data())) != DG_OK) return rc;
     for (int i = 0; i < M.n3; ++i) dinv[i] = (T)(1.0 / diag[i]);
     if ((e = M.alloc(&L.dinv, M.n3)) != hipSuccess) return hip_fail(e, "V-cycle tables");
@@ -351,11 +360,12 @@ int gmg_cg(const dg_op_desc* desc, int32_t levels, const double* lambda_max, con
     const double true_rr = host[1] - host[0] * host[0] / dn;
     const double bn = std::sqrt(bb);
     report->iterations = it;
-    report->matvec_f64 = matvec;
-    report->matvec_f32 = 0;
+    // outer FP64 applies plus every level apply of the cycles, by precision
+    report->matvec_f64 = matvec + (MgRun<T>::F32 ? 0 : (int)M.applies);
+    report->matvec_f32 = MgRun<T>::F32 ? (int)M.applies : 0;
     report->rel_res = bn > 0 ? std::sqrt(std::max(rr, 0.0)) / bn : 0.0;
     report->true_rel_res = bn > 0 ? std::sqrt(std::max(true_rr, 0.0)) / bn : 0.0;
-    report->lambda_max = lambda_max[0];
+    report->lambda_max = M.lv[0].lmax;
     report->seconds_solve = std::chrono::duration<double>(t2 - t1).count();
     report->seconds_setup = std::chrono::duration<double>(t1 - t0).count();
   }

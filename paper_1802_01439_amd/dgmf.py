@@ -306,9 +306,21 @@ def restrict(coarse, rf, out=None):
     return out
 
 
-def gmg_vcycle(desc, r, lambda_max, degree=5, smoothing_range=20.0, coarse_degree=10, out=None):
+def _levels_and_bounds(lambda_max, levels):
+    if lambda_max is None:
+        if levels is None:
+            raise ValueError("give lambda_max or levels")
+        return int(levels), None
+    lam = np.ascontiguousarray(lambda_max, dtype=np.float64)
+    if levels is not None and int(levels) != len(lam):
+        raise ValueError("levels does not match len(lambda_max)")
+    return len(lam), lam
+
+
+def gmg_vcycle(desc, r, lambda_max=None, degree=5, smoothing_range=20.0, coarse_degree=10, out=None, levels=None):
     """z = V r, one V-cycle in r's precision (float64 or float32);
-    lambda_max: one bound of D^-1 A per level (finest first)."""
+    lambda_max: one bound of D^-1 A per level (finest first), or None: the
+    library estimates them (then `levels` gives the number of levels)."""
     torch = _torch()
     shape = (_nel(desc), (desc.degree + 1) ** 3)
     _check_tensor(r, "r", shape)
@@ -317,29 +329,31 @@ def gmg_vcycle(desc, r, lambda_max, degree=5, smoothing_range=20.0, coarse_degre
     if out is None:
         out = torch.empty_like(r)
     _check_tensor(out, "out", shape, like=r)
-    lam = np.ascontiguousarray(lambda_max, dtype=np.float64)
+    nlev, lam = _levels_and_bounds(lambda_max, levels)
     _placed(r, out)
-    _check(lib().dg_gmg_vcycle(ctypes.byref(desc), int(len(lam)), int(degree), float(smoothing_range),
-                               int(coarse_degree), lam.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+    _check(lib().dg_gmg_vcycle(ctypes.byref(desc), nlev, int(degree), float(smoothing_range),
+                               int(coarse_degree), None if lam is None else lam.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                DG_F32 if r.dtype == torch.float32 else DG_F64, ctypes.c_void_p(r.data_ptr()), ctypes.c_void_p(out.data_ptr()), _stream(r)))
     return out
 
 
-def gmg_cg_solve(desc, b, lambda_max, x=None, rtol=1e-10, max_iter=200, cycle_dtype=DG_F64):
+def gmg_cg_solve(desc, b, lambda_max=None, x=None, rtol=1e-10, max_iter=200, cycle_dtype=DG_F64, levels=None):
     """FP64 CG with one V-cycle per iteration (periodic: zero-mean iterates),
-    the cycle in FP64 (DG_F64) or FP32 (DG_F32); returns (x, report dict,
-    return code)."""
+    the cycle in FP64 (DG_F64) or FP32 (DG_F32); lambda_max: per-level
+    bounds, or None with `levels` (estimated by the library); returns (x,
+    report dict, return code)."""
     torch = _torch()
     shape = (_nel(desc), (desc.degree + 1) ** 3)
     _check_tensor(b, "b", shape, dtype=torch.float64)
     if x is None:
         x = torch.zeros_like(b)
     _check_tensor(x, "x", shape, like=b)
-    lam = np.ascontiguousarray(lambda_max, dtype=np.float64)
+    nlev, lam = _levels_and_bounds(lambda_max, levels)
     rep = CgReport()
     _placed(b, x)
-    rc = _check(lib().dg_gmg_cg_solve(ctypes.byref(desc), int(len(lam)),
-                                      lam.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(cycle_dtype),
+    rc = _check(lib().dg_gmg_cg_solve(ctypes.byref(desc), nlev,
+                                      None if lam is None else lam.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                      int(cycle_dtype),
                                       ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(x.data_ptr()), float(rtol),
                                       int(max_iter), ctypes.byref(rep), _stream(b)), soft_ok=True)
     return x, rep.as_dict(), rc

@@ -145,3 +145,35 @@ def test_vcycle_pcg_config5_against_fdm(cycle):
     assert np.linalg.norm(xs - x_ref) / np.linalg.norm(x_ref) < 1e-7
     assert rep["true_rel_res"] < 1e-9 and rep["iterations"] <= 20, rep
     announce(f"V-cycle PCG config 5 report {rep}")
+
+
+@pytest.mark.parametrize("cycle", [dgmf.DG_F64, dgmf.DG_F32])
+def test_gmg_cg_estimates_level_bounds_and_counts_applies(cycle):
+    """lambda_max = None: the library estimates each level's bound with the
+    Chebyshev CG's Lanczos (kept per operator), giving the same solve as the
+    bounds fetched level by level through dg_cg_solve; the report counts every
+    operator application by precision: per cycle 2 (5 - 1) + 2 on each
+    smoothing level and 10 - 1 on the coarsest, one FP64 apply per
+    iteration plus the initial and the final (true) residual."""
+    k, N, levels = 3, 8, 3
+    d = dgmf.make_desc(k, N)
+    b = to_dev(inputs.uniform((N ** 3, (k + 1) ** 3), seed=1601))
+    b -= b.mean()
+    lam = []
+    for l in range(levels):
+        dl = dgmf.make_desc(k, N >> l)
+        bl = to_dev(inputs.uniform(((N >> l) ** 3, (k + 1) ** 3), seed=1602 + l))
+        bl -= bl.mean()
+        _, rl, _ = dgmf.cg_solve(dl, bl, precond=dgmf.DG_PC_CHEB_F32, max_iter=1)
+        lam.append(rl["lambda_max"])
+    announce(f"gmg cg with estimated bounds, cycle dtype {cycle}")
+    x1, r1, rc1 = dgmf.gmg_cg_solve(d, b, lam, rtol=1e-10, cycle_dtype=cycle)
+    x2, r2, rc2 = dgmf.gmg_cg_solve(d, b, levels=levels, rtol=1e-10, cycle_dtype=cycle)
+    assert rc1 == rc2 == dgmf.DG_OK
+    assert r2["lambda_max"] == lam[0] and r2["iterations"] == r1["iterations"]
+    assert torch.equal(x1, x2)
+    it = r2["iterations"]
+    per_cycle = (levels - 1) * (2 * (5 - 1) + 2) + (10 - 1)
+    cyc = it * per_cycle   # one cycle before the loop and one per iteration but the last
+    assert r2["matvec_f64"] == it + 2 + (cyc if cycle == dgmf.DG_F64 else 0), r2
+    assert r2["matvec_f32"] == (cyc if cycle == dgmf.DG_F32 else 0), r2
