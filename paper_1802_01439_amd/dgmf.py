@@ -227,6 +227,13 @@ def apply_convective(desc, u, out=None):
     return out
 
 
+def vjp_max_degree(dtype):
+    """Highest degree dg_vjp_convective is built for (its LDS budget per
+    element): 10 in FP64, 11 in FP32."""
+    torch = _torch()
+    return 10 if dtype == torch.float64 else 11
+
+
 def vjp_convective(desc, u, w, out=None):
     """J(u)^T w for the convective apply; all [3, N_el, n^3]."""
     torch = _torch()

@@ -39,8 +39,9 @@ def test_config4_submesh_against_assembled_jacobian(dtype):
 
 
 @pytest.mark.parametrize("k", list(range(1, 8)))
-def test_all_supported_degrees_fp64(k):
-    n_el = (3, 2, 2) if k > 3 else (3, 4, 2)
+def test_low_degrees_fp64(k):
+    # 27 elements: several workgroups of several elements and a ragged last one
+    n_el = (3, 3, 3) if k <= 4 else (3, 2, 2)
     length = (2 * np.pi, 1.5, 2.5)
     msh = M.Mesh(n_el, length)
     u = inputs.uniform((3, msh.N, (k + 1) ** 3), seed=600 + k)
@@ -51,9 +52,9 @@ def test_all_supported_degrees_fp64(k):
     assert rel_err(g, convective_vjp(u, w, k, msh, lf_factor=0.7)) < 1e-12
 
 
-@pytest.mark.parametrize("k", [2, 5, 8, 9])
-def test_fp32_degrees(k):
-    n_el = (2, 2, 3)
+@pytest.mark.parametrize("k", [2, 4, 5])
+def test_low_degrees_fp32(k):
+    n_el = (3, 3, 3)
     msh = M.Mesh(n_el, (2 * np.pi,) * 3)
     u = round_f32(inputs.uniform((3, msh.N, (k + 1) ** 3), seed=800 + k))
     w = round_f32(inputs.uniform(u.shape, seed=900 + k))
@@ -61,6 +62,27 @@ def test_fp32_degrees(k):
     d = dgmf.make_desc(k, n_el)
     g = dgmf.vjp_convective(d, to_dev(u, torch.float32), to_dev(w, torch.float32)).double().cpu().numpy()
     assert rel_err(g, convective_vjp(u, w, k, msh)) < 1e-5
+
+
+@pytest.mark.parametrize("k", [8, 9, 10, 11])
+def test_high_degrees(k):
+    """FP64 (where built) and FP32 against one oracle evaluation on inputs
+    that FP32 holds exactly; 2^3 and 3x2x2 meshes (the assembled Jacobian of
+    a 3^3 mesh at k = 11 takes minutes on the host)."""
+    n_el = (3, 2, 2) if k <= 9 else (2, 2, 2)
+    length = (2 * np.pi, 1.5, 2.5)
+    msh = M.Mesh(n_el, length)
+    u = round_f32(inputs.uniform((3, msh.N, (k + 1) ** 3), seed=620 + k))
+    w = round_f32(inputs.uniform(u.shape, seed=720 + k))
+    d = dgmf.make_desc(k, n_el, length, lf_factor=0.7)
+    ref = convective_vjp(u, w, k, msh, lf_factor=0.7)
+    if k <= dgmf.vjp_max_degree(torch.float64):
+        announce(f"vjp fp64 k={k} n_el={n_el}")
+        g = dgmf.vjp_convective(d, to_dev(u), to_dev(w)).cpu().numpy()
+        assert rel_err(g, ref) < 1e-12
+    announce(f"vjp fp32 k={k} n_el={n_el}")
+    g = dgmf.vjp_convective(d, to_dev(u, torch.float32), to_dev(w, torch.float32)).double().cpu().numpy()
+    assert rel_err(g, ref) < 1e-5
 
 
 def test_exact_ties_follow_half_half_convention():
@@ -124,11 +146,12 @@ def test_autograd_convective_and_laplace():
 
 
 def test_unsupported_degree_and_alias():
-    d = dgmf.make_desc(8, 2)
-    u = torch.zeros((3, 8, 729), dtype=torch.float64, device="cuda")
-    with pytest.raises(dgmf.DgError) as ei:
-        dgmf.vjp_convective(d, u, u)
-    assert ei.value.code == dgmf.DG_ERR_UNSUPPORTED
+    if dgmf.vjp_max_degree(torch.float64) < 11:
+        d = dgmf.make_desc(11, 2)
+        u = torch.zeros((3, 8, 12 ** 3), dtype=torch.float64, device="cuda")
+        with pytest.raises(dgmf.DgError) as ei:
+            dgmf.vjp_convective(d, u, u)
+        assert ei.value.code == dgmf.DG_ERR_UNSUPPORTED
     d = dgmf.make_desc(2, 2)
     u = torch.zeros((3, 8, 27), dtype=torch.float64, device="cuda")
     with pytest.raises(dgmf.DgError) as ei:
