@@ -110,8 +110,8 @@ int dg_apply_convective(const dg_op_desc* desc, dg_dtype dtype, const void* u, v
  * dF*_i/du-_j).  At kinks of the max the derivative takes 1/2 from each side
  * on exact ties |u-.n| = |u+.n|, and sign(0) = 0.
  *   u, w, grad_u: [3][N_el][n^3] of `dtype`; grad_u must not overlap u or w.
- * Built for k <= 10 in FP64 and k <= 11 in FP32 (LDS per element); higher
- * degrees return DG_ERR_UNSUPPORTED.
+ * Built for k <= 11 in FP64 and FP32; higher degrees return
+ * DG_ERR_UNSUPPORTED.
  */
 int dg_vjp_convective(const dg_op_desc* desc, dg_dtype dtype, const void* u, const void* w,
                       void* grad_u, void* hip_stream);

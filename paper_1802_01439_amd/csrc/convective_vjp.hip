@@ -1,6 +1,5 @@
 // Vector-Jacobian product of the convective term: g = J(u)^T w, by sum
-// factorisation, FP64 (k <= 10) and FP32 (k <= 11), floor(3k/2)+1 Gauss
-// points.
+// factorisation, FP64 and FP32, k <= 11, floor(3k/2)+1 Gauss points.
 //
 // Linearising R_c = -sum_j s_j (d_j phi, u_c u_j) + faces (Sec. 3.2, weak
 // form of c_h) and transposing against the coefficient vector w gives
@@ -47,10 +46,12 @@
 //   P3   as in the one-pass kernel with the share of w_i, accumulated in
 //        registers.
 //   Y, X as in the one-pass kernel.
-// Where the G_x and G_y slots of w_i do not fit in LDS (FP64, k = 10), the z
-// pencils form d_x w_i and d_y w_i from S_y S_x w_i instead, by the
+// Where the G_x and G_y slots of w_i do not fit in LDS (FP64, k >= 10), the
+// z pencils form d_x w_i and d_y w_i from S_y S_x w_i instead, by the
 // collocation derivative at the Gauss points along q1 and q2.  That is exact:
 // along each line the values are those of a polynomial of degree k < m.
+// Where even that does not fit (FP64, k = 11), the x faces are taken after
+// the three passes, in LDS the passes have freed.
 // The back sweeps use S^T only, so all three components fit at once.
 #include <cmath>
 
@@ -610,7 +611,11 @@ vjp_onepass_kernel(const T* __restrict__ u, const T* __restrict__ wv, T* __restr
 //                              S^T_z result for component k
 //   XR:                        x-face terms after S^T_y, [k][s][cz][b], in the
 //                              sigma = 1 half of FX (free by then)
-template <int N, int Q, int SZ, int DER>
+// FXL = 1 (FP64, k = 11): no FX during the passes.  The x faces are taken
+// after them, in the slots [3n, SLOTS) that the passes leave free: the y
+// sweeps of the x-face layers of u and of all three components of w,
+// [sigma][s][f = u_0..2, w_0..2][c][q], then XR.
+template <int N, int Q, int SZ, int DER, int FXL>
 struct VjpShapeC {
   static constexpr int N2 = N * N, N3 = N * N * N;
   static constexpr int MP = Q | 1;
@@ -619,9 +624,10 @@ struct VjpShapeC {
   static constexpr int SU = 0, SW = 3 * (N + 2), SWGY = 4 * (N + 2), SWGX = 4 * (N + 2) + N;
   static constexpr int SLOTS = 4 * (N + 2) + (DER ? 0 : 2 * N);
   static constexpr int FL = 16 * LAYER;
-  static constexpr int PER = SLOTS * COLS + 2 * FL;
+  static constexpr int XL = 3 * N * COLS;   // late x-face region (FXL)
+  static constexpr int PER = SLOTS * COLS + (FXL ? 1 : 2) * FL;
   static constexpr int BYTES = PER * SZ;
-  static constexpr int ITEMS = Q * Q + 4 * Q;   // z pencils and face pencils per element
+  static constexpr int ITEMS = Q * Q + (FXL ? 2 : 4) * Q;   // z pencils and face pencils per element
   static constexpr int E0 = (56 * 1024) / BYTES;
   static constexpr int E = E0 < 1 ? 1 : (E0 > 8 ? 8 : E0);
   // one workgroup per CU (more than 80 KB): at most one wave per SIMD, which
@@ -630,23 +636,34 @@ struct VjpShapeC {
   static constexpr int TH = E * BYTES > 80 * 1024 ? (TH0 > 256 ? 256 : TH0) : (TH0 > 512 ? 512 : TH0);
   static constexpr bool FITS = E * BYTES <= 160 * 1024;
   static_assert(6 * N2 <= 8 * LAYER, "x-face results must fit in half of FX");
+  static_assert(!FXL || 24 * LAYER + 6 * N2 <= (SLOTS - 3 * N) * COLS, "late x faces must fit in the free slots");
 };
 
-// DER = 0 where the derivative slots fit, else 1.
+// DER = 0 where the derivative slots fit, else 1; FXL = 1 where even that
+// does not fit.
 template <int N, int Q, int SZ>
 constexpr int vjp_der() {
-  return VjpShapeC<N, Q, SZ, 0>::FITS ? 0 : 1;
+  return VjpShapeC<N, Q, SZ, 0, 0>::FITS ? 0 : 1;
+}
+template <int N, int Q, int SZ>
+constexpr int vjp_fxl() {
+  return VjpShapeC<N, Q, SZ, vjp_der<N, Q, SZ>(), 0>::FITS ? 0 : 1;
 }
 
-template <int N, int Q, typename T, int E, int TH, int DER>
+template <int N, int Q, typename T, int E, int TH, int DER, int FXL>
 __global__ void __launch_bounds__(TH) __attribute__((amdgpu_waves_per_eu(2)))
 vjp_percomp_kernel(const T* __restrict__ u, const T* __restrict__ wv, T* __restrict__ g, MeshArgs mesh,
                       const ConvTab<N, Q, T>* __restrict__ tab, const GaussDeriv<Q, T>* __restrict__ gd,
                       ConvScal<T> sc) {
-  using Sh = VjpShapeC<N, Q, (int)sizeof(T), DER>;
+  using Sh = VjpShapeC<N, Q, (int)sizeof(T), DER, FXL>;
   constexpr int N2 = Sh::N2, N3 = Sh::N3, MP = Sh::MP, COLS = Sh::COLS, LAYER = Sh::LAYER, PER = Sh::PER;
   constexpr int NH = N / 2, QH = Q / 2, QC = (Q + 1) / 2;
-  constexpr int FYo = Sh::SLOTS * COLS, FXo = FYo + Sh::FL, XRo = FXo + 8 * LAYER;
+  // FP64 at the highest degree: Gauss-point loops not unrolled, so that the
+  // table rows of one point are loaded when used (unrolled, the FP64 table
+  // entries exhaust the scalar registers and spill)
+  constexpr int RQ = (sizeof(T) == 8 && N >= 12) ? 1 : QC;
+  constexpr int FYo = Sh::SLOTS * COLS, FXo = FYo + Sh::FL;
+  constexpr int XRo = FXL ? Sh::XL + 24 * LAYER : FXo + 8 * LAYER;
   __shared__ T lds[E * PER];
   const int tid = threadIdx.x;
   const int e0 = xcd_remap(blockIdx.x, gridDim.x) * E;
@@ -672,7 +689,7 @@ vjp_percomp_kernel(const T* __restrict__ u, const T* __restrict__ wv, T* __restr
   // kind 0: x pencil (b, c) of the element; 1: x pencil p of the z neighbour's
   // facing layer (side s); 2: x pencil p of the y neighbour's facing layer;
   // 3: y pencil c of the x-face layer (own sigma = 0 / neighbour 1, side s).
-  constexpr int nM = E * N2, nZ = E * 2 * N, nY = E * 2 * N, nX = E * 4 * N;
+  constexpr int nM = E * N2, nZ = E * 2 * N, nY = E * 2 * N, nX = FXL ? 0 : E * 4 * N;
   constexpr int P1N = nM + nZ + nY + nX;
   constexpr int NI1 = (P1N + TH - 1) / TH;
   int kd[NI1], ile[NI1], ia[NI1], ib[NI1], ic[NI1], ist[NI1];
@@ -757,6 +774,22 @@ vjp_percomp_kernel(const T* __restrict__ u, const T* __restrict__ wv, T* __restr
     }
   };
 
+  // share of w_i in the transposed flux derivative at one face point from
+  // the own (m) and neighbour (p) traces of u_d (normal component), u_i and
+  // w_i; outward sign sgn; G_k weighted by wgt
+  auto face_i = [&](T umd, T upd, T umi, T upi, T wm, T wp, int i, int d, T sgn, T wgt, T (&G)[3]) {
+    const T unm = sgn * umd, unp = sgn * upd;
+    const T am = fabs(unm), ap = fabs(unp);
+    const T lam = fmax(am, ap);
+    const T sm = am > ap ? T(1) : (am == ap ? T(0.5) : T(0));
+    const T sgu = unm > T(0) ? T(1) : (unm < T(0) ? T(-1) : T(0));
+    const T dw = wgt * (wm - wp);
+    const T diag = dw * fmadd(T(0.5), unm, sc.lf * lam);
+    const T ex = sgn * dw * fmadd(T(0.5), umi, sc.lf * sm * sgu * (umi - upi));
+#pragma unroll
+    for (int k = 0; k < 3; ++k) G[k] = (k == i ? diag : T(0)) + (k == d ? ex : T(0));
+  };
+
   // loads of w_i, kept in registers until the LDS slots of w_{i-1} are free
   T pre[NI1][N];
   auto load_w = [&](int i) {
@@ -782,7 +815,8 @@ vjp_percomp_kernel(const T* __restrict__ u, const T* __restrict__ wv, T* __restr
   }
 
   // ---------------- P3 state ----------------
-  constexpr int nCell = E * Q * Q, nH = E * 4 * Q;
+  constexpr int FAM = FXL ? 1 : 2;   // face families taken in the passes
+  constexpr int nCell = E * Q * Q, nH = E * FAM * 2 * Q;
   constexpr int NIT = (nCell + nH + TH - 1) / TH;
   EoT<N, T, 1> acc[NIT][3];
   T gz[NIT][2][3];   // z-face terms of a z pencil at its two end nodes
@@ -846,21 +880,6 @@ vjp_percomp_kernel(const T* __restrict__ u, const T* __restrict__ wv, T* __restr
     }
     lds_barrier();
 
-    // share of w_i in the transposed flux derivative at one face point from
-    // the own (m) and neighbour (p) traces of u_d (normal component), u_i and
-    // w_i; outward sign sgn; G_k weighted by wgt
-    auto face_i = [&](T umd, T upd, T umi, T upi, T wm, T wp, int d, T sgn, T wgt, T (&G)[3]) {
-      const T unm = sgn * umd, unp = sgn * upd;
-      const T am = fabs(unm), ap = fabs(unp);
-      const T lam = fmax(am, ap);
-      const T sm = am > ap ? T(1) : (am == ap ? T(0.5) : T(0));
-      const T sgu = unm > T(0) ? T(1) : (unm < T(0) ? T(-1) : T(0));
-      const T dw = wgt * (wm - wp);
-      const T diag = dw * fmadd(T(0.5), unm, sc.lf * lam);
-      const T ex = sgn * dw * fmadd(T(0.5), umi, sc.lf * sm * sgu * (umi - upi));
-#pragma unroll
-      for (int k = 0; k < 3; ++k) G[k] = (k == i ? diag : T(0)) + (k == d ? ex : T(0));
-    };
     // W_q3 times the share of w_i in P_k at one point: v = u_0, u_1, u_2,
     // d_x w_i, d_y w_i, d_z w_i
     auto pk_i = [&](const T (&v)[6], T wq, T (&P)[3]) {
@@ -891,7 +910,7 @@ vjp_percomp_kernel(const T* __restrict__ u, const T* __restrict__ wv, T* __restr
           const T* ui = col + (Sh::SU + i * (N + 2)) * COLS;
           const T* ws = col + Sh::SW * COLS;
           T G[3];
-          face_i(ud[own * COLS], ud[nb * COLS], ui[own * COLS], ui[nb * COLS], ws[own * COLS], ws[nb * COLS], 2,
+          face_i(ud[own * COLS], ud[nb * COLS], ui[own * COLS], ui[nb * COLS], ws[own * COLS], ws[nb * COLS], i, 2,
                  s ? T(1) : T(-1), w12 * sc.area[2], G);
 #pragma unroll
           for (int k = 0; k < 3; ++k) gz[it][s][k] += G[k];
@@ -939,7 +958,7 @@ vjp_percomp_kernel(const T* __restrict__ u, const T* __restrict__ wv, T* __restr
           }
           xm[f] = (N % 2) ? x[NH] : T(0);
         }
-#pragma unroll
+#pragma unroll RQ
         for (int q = 0; q < QC; ++q) {
           // the six fields at q and at its mirror m-1-q
           T vq[6], vr[6];
@@ -984,10 +1003,10 @@ vjp_percomp_kernel(const T* __restrict__ u, const T* __restrict__ wv, T* __restr
         }
       } else {   // face pencil: fam 0 = y face (q = q1), 1 = x face (q = q2)
         const int h = w - nCell;
-        const int le = h / (4 * Q);
+        const int le = h / (FAM * 2 * Q);
         if (le >= ne) continue;
-        int rem = h - le * 4 * Q;
-        const int fam = rem / (2 * Q);
+        int rem = h - le * FAM * 2 * Q;
+        const int fam = FXL ? 0 : rem / (2 * Q);
         rem -= fam * 2 * Q;
         const int s = rem / Q, q = rem - s * Q;
         const T* F = lds + le * PER + (fam ? FXo : FYo) + q;
@@ -1011,7 +1030,7 @@ vjp_percomp_kernel(const T* __restrict__ u, const T* __restrict__ wv, T* __restr
           }
         const T sgn = s ? T(1) : T(-1);
         const T wq = t.w[q] * (fam ? sc.area[0] : sc.area[1]);
-#pragma unroll
+#pragma unroll RQ
         for (int q3 = 0; q3 < QC; ++q3) {
           T vq[2][3], vr[2][3];
 #pragma unroll
@@ -1030,10 +1049,10 @@ vjp_percomp_kernel(const T* __restrict__ u, const T* __restrict__ wv, T* __restr
             }
           const T wgt = wq * t.w[q3];
           T Gq[3];
-          face_i(vq[0][0], vq[1][0], vq[0][1], vq[1][1], vq[0][2], vq[1][2], d, sgn, wgt, Gq);
+          face_i(vq[0][0], vq[1][0], vq[0][1], vq[1][1], vq[0][2], vq[1][2], i, d, sgn, wgt, Gq);
           if (q3 < QH) {
             T Gr[3];
-            face_i(vr[0][0], vr[1][0], vr[0][1], vr[1][1], vr[0][2], vr[1][2], d, sgn, wgt, Gr);
+            face_i(vr[0][0], vr[1][0], vr[0][1], vr[1][1], vr[0][2], vr[1][2], i, d, sgn, wgt, Gr);
 #pragma unroll
             for (int k = 0; k < 3; ++k) acc[it][k].pair(t.Tp[q3], t.Tm[q3], Gq[k], Gr[k]);
           } else {
@@ -1069,10 +1088,10 @@ vjp_percomp_kernel(const T* __restrict__ u, const T* __restrict__ wv, T* __restr
         }
     } else {
       const int h = w - nCell;
-      const int le = h / (4 * Q);
+      const int le = h / (FAM * 2 * Q);
       if (le >= ne) continue;
-      int rem = h - le * 4 * Q;
-      const int fam = rem / (2 * Q);
+      int rem = h - le * FAM * 2 * Q;
+      const int fam = FXL ? 0 : rem / (2 * Q);
       rem -= fam * 2 * Q;
       const int s = rem / Q, q = rem - s * Q;
       T* F = lds + le * PER + (fam ? FXo : FYo) + q;
@@ -1083,6 +1102,100 @@ vjp_percomp_kernel(const T* __restrict__ u, const T* __restrict__ wv, T* __restr
     }
   }
   lds_barrier();
+
+  // late x faces (FXL): layer offset of (sigma, s, f), f = u_0..2, w_0..2
+  auto fx = [](int sg, int s, int f) { return Sh::XL + ((sg * 2 + s) * 6 + f) * LAYER; };
+  if constexpr (FXL) {
+    // y sweeps of the x-face layers, one (pencil, field) per item
+    constexpr int nXL = E * 4 * N * 6;
+    for (int w = tid; w < nXL; w += TH) {
+      CONV_TABLES(t);
+      const int f = w % 6, v = w / 6;
+      const int le = v / (4 * N);
+      if (le >= ne) continue;
+      const int r = v - le * 4 * N, sg = r / (2 * N), r2 = r - sg * 2 * N, s = r2 / N, c = r2 - s * N;
+      int e = e0 + le, a = s ? N - 1 : 0;
+      if (sg) {
+        e = nbr(le, 0, s);
+        a = s ? 0 : N - 1;
+      }
+      const T* src = (f < 3 ? u + f * cs : wv + (f - 3) * cs) + (size_t)e * N3 + a + N2 * c;
+      T x[N];
+      load_pencil<N, Q, T>(src, N, x);
+      T* d = lds + le * PER + fx(sg, s, f) + c * Q;
+      eo_interp<N, Q, T>(t, x, [&](int q, T val) { d[q] = val; });
+    }
+    lds_barrier();
+    // x-face pencils (side s, point q), the three shares of w in turn
+    constexpr int nF = E * 2 * Q;
+    for (int w = tid; w < nF; w += TH) {
+      CONV_TABLES(t);
+      const int le = w / (2 * Q);
+      if (le >= ne) continue;
+      const int rem = w - le * 2 * Q, s = rem / Q, q = rem - s * Q;
+      T* F = lds + le * PER + q;
+      const T sgn = s ? T(1) : T(-1);
+      const T wq = t.w[q] * sc.area[0];
+      EoT<N, T, 1> fa[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) fa[k].zero();
+#pragma unroll 1
+      for (int i = 0; i < 3; ++i) {
+        T xe[2][3][NH], xo[2][3][NH], xm[2][3];
+#pragma unroll
+        for (int sg = 0; sg < 2; ++sg)
+#pragma unroll
+          for (int f = 0; f < 3; ++f) {
+            const T* src = F + fx(sg, s, f == 0 ? 0 : (f == 1 ? i : 3 + i));
+            T x[N];
+#pragma unroll
+            for (int c = 0; c < N; ++c) x[c] = src[c * Q];
+#pragma unroll
+            for (int a = 0; a < NH; ++a) {
+              xe[sg][f][a] = x[a] + x[N - 1 - a];
+              xo[sg][f][a] = x[a] - x[N - 1 - a];
+            }
+            xm[sg][f] = (N % 2) ? x[NH] : T(0);
+          }
+#pragma unroll RQ
+        for (int q3 = 0; q3 < QC; ++q3) {
+          T vq[2][3], vr[2][3];
+#pragma unroll
+          for (int sg = 0; sg < 2; ++sg)
+#pragma unroll
+            for (int f = 0; f < 3; ++f) {
+              T e = t.Sp[q3][0] * xe[sg][f][0], o = t.Sm[q3][0] * xo[sg][f][0];
+#pragma unroll
+              for (int a = 1; a < NH; ++a) {
+                e = fmadd(t.Sp[q3][a], xe[sg][f][a], e);
+                o = fmadd(t.Sm[q3][a], xo[sg][f][a], o);
+              }
+              if constexpr (N % 2 == 1) e = fmadd(t.Sc[q3], xm[sg][f], e);
+              vq[sg][f] = e + o;
+              vr[sg][f] = e - o;
+            }
+          const T wgt = wq * t.w[q3];
+          T Gq[3];
+          face_i(vq[0][0], vq[1][0], vq[0][1], vq[1][1], vq[0][2], vq[1][2], i, 0, sgn, wgt, Gq);
+          if (q3 < QH) {
+            T Gr[3];
+            face_i(vr[0][0], vr[1][0], vr[0][1], vr[1][1], vr[0][2], vr[1][2], i, 0, sgn, wgt, Gr);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) fa[k].pair(t.Tp[q3], t.Tm[q3], Gq[k], Gr[k]);
+          } else {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) fa[k].mid(t.Tc, Gq[k]);
+          }
+        }
+      }
+      // own u layers of this (s, q): read by no other pencil
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int c = 0; c < N; ++c) F[fx(0, s, k) + c * Q] = fa[k].out(c);
+    }
+    lds_barrier();
+  }
 
   // ---------------- Y: S^T_y in place, y-face terms; S^T_y of the x-face terms ----------------
   {
@@ -1117,7 +1230,7 @@ vjp_percomp_kernel(const T* __restrict__ u, const T* __restrict__ wv, T* __restr
         const int le = r2 % E, k = r2 / E;
         if (le >= ne) continue;
         T* L = lds + le * PER;
-        const T* xf = L + FXo + fl(0, s, k) + cz * Q;
+        const T* xf = L + (FXL ? fx(0, s, k) : FXo + fl(0, s, k)) + cz * Q;
         EoT<N, T, 1> o;
         o.zero();
 #pragma unroll
@@ -1170,8 +1283,8 @@ constexpr bool vjp_onepass() {
 
 template <int N, int Q, typename T>
 static hipError_t launch_vjp_nq(const ConvPlan& P, const void* u, const void* w, void* g, hipStream_t s) {
-  constexpr int DER = vjp_der<N, Q, (int)sizeof(T)>();
-  using ShC = VjpShapeC<N, Q, (int)sizeof(T), DER>;
+  constexpr int DER = vjp_der<N, Q, (int)sizeof(T)>(), FXL = vjp_fxl<N, Q, (int)sizeof(T)>();
+  using ShC = VjpShapeC<N, Q, (int)sizeof(T), DER, FXL>;
   using Sh1 = VjpShape1<N, Q, (int)sizeof(T)>;
   constexpr bool ONE = vjp_onepass<N>();
   if constexpr (ONE ? !Sh1::FITS : !ShC::FITS) {
@@ -1209,7 +1322,7 @@ static hipError_t launch_vjp_nq(const ConvPlan& P, const void* u, const void* w,
         if (!dd) return err;
       }
       const int grid = (P.mesh.n_el + ShC::E - 1) / ShC::E;
-      hipLaunchKernelGGL((vjp_percomp_kernel<N, Q, T, ShC::E, ShC::TH, DER>), dim3(grid), dim3(ShC::TH), 0, s,
+      hipLaunchKernelGGL((vjp_percomp_kernel<N, Q, T, ShC::E, ShC::TH, DER, FXL>), dim3(grid), dim3(ShC::TH), 0, s,
                          (const T*)u, (const T*)w, (T*)g, P.mesh, dt, dd, sc);
     }
     return hipGetLastError();
@@ -1229,14 +1342,12 @@ static hipError_t launch_vjp_t(const ConvPlan& P, const void* u, const void* w, 
     case 8: return launch_vjp_nq<9, 13, T>(P, u, w, g, s);
     case 9: return launch_vjp_nq<10, 14, T>(P, u, w, g, s);
     case 10: return launch_vjp_nq<11, 16, T>(P, u, w, g, s);
-    case 11:
-      if constexpr (sizeof(T) == 4) return launch_vjp_nq<12, 17, T>(P, u, w, g, s);
-      else return hipErrorInvalidConfiguration;
+    case 11: return launch_vjp_nq<12, 17, T>(P, u, w, g, s);
     default: return hipErrorInvalidConfiguration;
   }
 }
 
-int vjp_max_degree(bool f32) { return f32 ? 11 : 10; }
+int vjp_max_degree(bool) { return 11; }
 
 hipError_t launch_convective_vjp(const ConvPlan& P, bool f32, const void* u, const void* w, void* g,
                                  hipStream_t s) {

@@ -228,10 +228,8 @@ def apply_convective(desc, u, out=None):
 
 
 def vjp_max_degree(dtype):
-    """Highest degree dg_vjp_convective is built for (its LDS budget per
-    element): 10 in FP64, 11 in FP32."""
-    torch = _torch()
-    return 10 if dtype == torch.float64 else 11
+    """Highest degree dg_vjp_convective is built for: 11 in FP64 and FP32."""
+    return 11
 
 
 def vjp_convective(desc, u, w, out=None):
