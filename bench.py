@@ -51,7 +51,7 @@ KERNEL_NAME = {"laplace": "laplace_march_kernel|laplace_batch_kernel", "convecti
 # every source file that defines each kernel (the traffic record is keyed by their hash)
 SOURCES = {"laplace": ("laplace.hip", "laplace_kernels.h", "common.h"),
            "convective": ("convective.hip", "conv_common.h", "basis_ct.h", "common.h"),
-           "vjp": ("convective_vjp.hip", "conv_common.h", "common.h")}
+           "vjp": ("convective_vjp.hip", "conv_common.h", "basis_ct.h", "common.h")}
 
 
 def sweep_mesh(k):
@@ -332,6 +332,7 @@ def extras(torch, dgmf, inputs, dev, args, which=("vjp", "cg", "mass", "proj", "
             res[dtype] = {"dofs_per_s": dofs / t, "us": t * 1e6,
                           "hbm_frac": BYTES_PER_DOF[("vjp", dtype)] * dofs / t / (HBM_PEAK_GBS * 1e9)}
         out["vjp_k4_32cubed"] = res
+        out["vjp_sweep"] = _vjp_sweep(torch, dgmf, dev, args)
     except _Skip:
         pass
     except dgmf.DgError as ex:
@@ -599,6 +600,40 @@ def _sweep_extra(torch, dgmf, dev, args, comps, seed, apply):
     return res
 
 
+def _vjp_sweep(torch, dgmf, dev, args):
+    """dg_vjp_convective over the degree-sweep meshes: seeded U[-1,1] velocity
+    and cotangent, two input sets in rotation.  Algorithmic bytes: u and w
+    read once, g written once (24 B per DoF in FP64, 12 B in FP32)."""
+    res = {}
+    R = 2
+    for k in range(args.kmin, args.kmax + 1):
+        N = sweep_mesh(k)
+        d = dgmf.make_desc(k, N)
+        g = torch.Generator(device=dev)
+        g.manual_seed(910 + k)
+        shape = (3, N ** 3, (k + 1) ** 3)
+        for dtype, tdt in (("f64", torch.float64), ("f32", torch.float32)):
+            us = [(torch.rand(shape, generator=g, dtype=torch.float64, device=dev) * 2 - 1).to(tdt) for _ in range(R)]
+            ws = [(torch.rand(shape, generator=g, dtype=torch.float64, device=dev) * 2 - 1).to(tdt) for _ in range(R)]
+            gs = [torch.empty_like(us[0]) for _ in range(R)]
+            for i in range(R):
+                dgmf.vjp_convective(d, us[i], ws[i], gs[i])
+            torch.cuda.synchronize()
+            s0, e0 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            reps = 3 * R
+            s0.record()
+            for i in range(reps):
+                dgmf.vjp_convective(d, us[i % R], ws[i % R], gs[i % R])
+            e0.record()
+            torch.cuda.synchronize()
+            t = s0.elapsed_time(e0) / 1e3 / reps
+            n = us[0].numel()
+            res[f"k{k}_{dtype}"] = {"us": t * 1e6, "dofs_per_s": n / t,
+                                    "hbm_frac": BYTES_PER_DOF[("vjp", dtype)] * n / t / (HBM_PEAK_GBS * 1e9)}
+            del us, ws, gs
+    return res
+
+
 class _Skip(Exception):
     pass
 
@@ -771,7 +806,7 @@ def summary(res):
                                            "iterations_p_proj_visc": [last["it_pressure"], last["it_projection"],
                                                                       last["it_viscous"]],
                                            "e_k": _r(last["kinetic_energy"], 6), "eps": _r(last["dissipation"], 4)}
-    for name in ("inverse_mass_sweep", "projection_sweep", "gradient_sweep", "divergence_sweep"):
+    for name in ("vjp_sweep", "inverse_mass_sweep", "projection_sweep", "gradient_sweep", "divergence_sweep"):
         v = ex.get(name)
         if isinstance(v, dict) and v:
             fr = [e["hbm_frac"] for e in v.values() if isinstance(e, dict) and "hbm_frac" in e]
