@@ -52,12 +52,6 @@ __device__ __forceinline__ const_ptr<P> fresh(const P* p) {
   return (const_ptr<P>)(((uint64_t)hi << 32) | lo);
 }
 
-// Workgroup barrier for LDS traffic only: waits for this wave's LDS (and
-// scalar) operations, not for its global loads, so loads issued before it
-// stay in flight across it.  The memory clobber keeps the compiler from
-// moving shared-memory accesses across it.
-__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
-
 // Host-side launch status: 0 or a hipError_t from the launch.
 struct LaunchStatus {
   hipError_t err = hipSuccess;

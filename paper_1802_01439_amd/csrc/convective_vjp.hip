@@ -62,6 +62,12 @@
 
 namespace dgmf {
 
+// Workgroup barrier for LDS traffic only: waits for this wave's LDS (and
+// scalar) operations, not for its global loads, so loads issued before it
+// stay in flight across it.  The memory clobber keeps the compiler from
+// moving shared-memory accesses across it.
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
 // Collocation derivative at the m Gauss points: d[q][p] = l_p'(z_q) for the
 // Lagrange basis of the Gauss points (barycentric form).
 template <int Q, typename T>
