@@ -392,13 +392,17 @@ int dg_gmg_vcycle(const dg_op_desc* desc, int32_t levels, int32_t degree, double
  *   lambda_max: host array of `levels` bounds as for dg_gmg_vcycle, or NULL
  *   (estimated per level as there);
  *   cycle_dtype: DG_F64 (the cycle of dg_gmg_vcycle) or DG_F32 (the cycle in
- *   single precision: the residual rounded to FP32 on entry, the correction
- *   widened on exit, the CG itself in FP64 as Sec. 3.3 splits the work);
+ *   single precision: the residual rounded to FP32 on entry, the cycle's
+ *   output entering the FP64 direction update, the CG itself in FP64 as
+ *   Sec. 3.3 splits the work);
  *   b, x: [N_el][n^3] doubles (device), x: initial guess in, solution out;
  *   stops when |r| <= rtol |b - mean(b)|; report: host pointer, may be NULL;
  *   its matvec_f64 / matvec_f32 count the outer FP64 applies and every
  *   level apply of the cycles (all levels) by precision, lambda_max the
- *   finest level's bound.
+ *   finest level's bound.  The iteration scalars stay on the device; the
+ *   host reads the state once per batch of up to four iterations, so the
+ *   counts include the cycle after the last iteration and any iterations
+ *   queued after convergence (which leave x unchanged).
  * Returns DG_OK, DG_NOT_CONVERGED or DG_ERR_BREAKDOWN, or a negative error.
  * Blocks the calling thread.
  */

@@ -58,6 +58,18 @@ hipError_t cg_update_p_jacobi(const double* r, double* p, const double* dinv, in
                               hipStream_t s);
 hipError_t cg_update_p_cheb(const float* z, double* p, const double* st, long long n, hipStream_t s);
 
+// a preconditioner that is a separate call (the V-cycle), in FP64 or FP32:
+// its input r' = r - mu_r, the partials of the flexible beta (for
+// cg_fin_cheb with kCgBlocks), and p = (z - mu_z) + beta p
+hipError_t cg_rprime(const double* r, const double* st, double* out, long long n, hipStream_t s);
+hipError_t cg_rprime(const double* r, const double* st, float* out, long long n, hipStream_t s);
+hipError_t cg_zsums(const double* r, const double* z, const double* zprev, const double* st, long long n,
+                    double* partial, hipStream_t s);
+hipError_t cg_zsums(const double* r, const float* z, const float* zprev, const double* st, long long n,
+                    double* partial, hipStream_t s);
+hipError_t cg_update_p_z(const double* z, double* p, const double* st, long long n, hipStream_t s);
+hipError_t cg_update_p_z(const float* z, double* p, const double* st, long long n, hipStream_t s);
+
 // inverse-mass-preconditioned CG with device-side scalars (same state layout)
 hipError_t mpcg_start(const double* partial, double* st, hipStream_t s);
 hipError_t mpcg_beta(const double* rr_partial, const double* rz_partial, int nblocks, double* st, hipStream_t s);

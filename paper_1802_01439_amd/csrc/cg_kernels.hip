@@ -368,6 +368,43 @@ __global__ void __launch_bounds__(kThreads) k_fin_cheb(const double* __restrict_
   }
 }
 
+// Preconditioners that are a separate call (the multigrid V-cycle): the
+// cycle's input r' = r - mu_r in the cycle's precision, the partials sum z,
+// r'.z, r'.(zprev - mu_z_prev) of the flexible beta (k_fin_cheb), and
+// p = (z - mu_z) + beta p, for an output z in either precision.
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_rprime(const double* __restrict__ r, const double* __restrict__ st,
+                                                     T* __restrict__ out, long long n) {
+  const double mu = st[kMuR];
+  for (long long i = blockIdx.x * (long long)kThreads + threadIdx.x; i < n; i += (long long)gridDim.x * kThreads)
+    out[i] = (T)(r[i] - mu);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_zsums(const double* __restrict__ r, const T* __restrict__ z,
+                                                    const T* __restrict__ zprev, const double* __restrict__ st,
+                                                    long long n, double* partial) {
+  const double mu = st[kMuR], muzp = st[kMuZ];
+  double v[3] = {};
+  for (long long i = blockIdx.x * (long long)kThreads + threadIdx.x; i < n; i += (long long)gridDim.x * kThreads) {
+    const double rp = r[i] - mu, zi = (double)z[i];
+    v[0] += zi;
+    v[1] += rp * zi;
+    v[2] += rp * ((double)zprev[i] - muzp);
+  }
+  block_partials<3>(v, partial);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_update_p_z(const T* __restrict__ z, double* __restrict__ p,
+                                                         const double* __restrict__ st, long long n) {
+  const double muz = st[kMuZ], beta = st[kBeta];
+  for (long long i = blockIdx.x * (long long)kThreads + threadIdx.x; i < n; i += (long long)gridDim.x * kThreads) {
+    const double zi = (double)z[i] - muz;
+    p[i] = beta != 0.0 ? zi + beta * p[i] : zi;   // a zero beta never reads the old direction
+  }
+}
+
 // state set-up: zero, then the constants
 __global__ void k_state_init(double* __restrict__ st, double tol2, double max_it, double sum_d, double n,
                              double proj) {
@@ -454,6 +491,39 @@ hipError_t cg_fill32(float* y, float c, long long n, hipStream_t s) { DG_LAUNCH(
 hipError_t cg_update_p_jacobi(const double* r, double* p, const double* dinv, int n3, const double* st, long long n,
                               hipStream_t s) {
   DG_LAUNCH(k_update_p_jacobi, r, p, dinv, n3, st, n);
+}
+template <typename T>
+static hipError_t rprime_t(const double* r, const double* st, T* out, long long n, hipStream_t s) {
+  DG_LAUNCH(k_rprime<T>, r, st, out, n);
+}
+hipError_t cg_rprime(const double* r, const double* st, double* out, long long n, hipStream_t s) {
+  return rprime_t(r, st, out, n, s);
+}
+hipError_t cg_rprime(const double* r, const double* st, float* out, long long n, hipStream_t s) {
+  return rprime_t(r, st, out, n, s);
+}
+template <typename T>
+static hipError_t zsums_t(const double* r, const T* z, const T* zprev, const double* st, long long n,
+                          double* partial, hipStream_t s) {
+  DG_LAUNCH(k_zsums<T>, r, z, zprev, st, n, partial);
+}
+hipError_t cg_zsums(const double* r, const double* z, const double* zprev, const double* st, long long n,
+                    double* partial, hipStream_t s) {
+  return zsums_t(r, z, zprev, st, n, partial, s);
+}
+hipError_t cg_zsums(const double* r, const float* z, const float* zprev, const double* st, long long n,
+                    double* partial, hipStream_t s) {
+  return zsums_t(r, z, zprev, st, n, partial, s);
+}
+template <typename T>
+static hipError_t update_p_z_t(const T* z, double* p, const double* st, long long n, hipStream_t s) {
+  DG_LAUNCH(k_update_p_z<T>, z, p, st, n);
+}
+hipError_t cg_update_p_z(const double* z, double* p, const double* st, long long n, hipStream_t s) {
+  return update_p_z_t(z, p, st, n, s);
+}
+hipError_t cg_update_p_z(const float* z, double* p, const double* st, long long n, hipStream_t s) {
+  return update_p_z_t(z, p, st, n, s);
 }
 hipError_t cg_update_p_cheb(const float* z, double* p, const double* st, long long n, hipStream_t s) {
   DG_LAUNCH(k_update_p_cheb, z, p, st, n);

@@ -23,6 +23,7 @@
 
 #include "api_internal.h"
 #include "cg_kernels.h"
+#include "cg_laplace.h"
 #include "dgmf.h"
 #include "ops.h"
 
@@ -243,9 +244,12 @@ namespace {
 // pressure Poisson equation (Sec. 3.3): residual and preconditioned residual
 // kept at zero coefficient mean, flexible (Polak-Ribiere) beta as in the
 // Chebyshev-preconditioned CG.  The cycle runs in T: with T = float the
-// residual is rounded to FP32 on the way in and the correction widened on the
-// way out, the outer iteration staying FP64 (the mixed-precision split of
-// Sec. 3.3).  Scalars go through the host (a few reads per iteration); the
+// residual r' = r - mean is rounded to FP32 on the way in and the cycle's
+// output enters the FP64 direction update directly, the outer iteration
+// staying FP64 (the mixed-precision split of Sec. 3.3).  The iteration
+// scalars stay on the device (the state array and kernels of the CG loop):
+// the host enqueues a batch of iterations and reads the state once per
+// batch; iterations queued after convergence leave x and r unchanged.  The
 // level vectors are set up once per solve.
 template <typename T>
 int gmg_cg(const dg_op_desc* desc, int32_t levels, const double* lambda_max, const double* b, double* x, double rtol,
@@ -257,20 +261,28 @@ int gmg_cg(const dg_op_desc* desc, int32_t levels, const double* lambda_max, con
   const long long n = M.lv[0].n;
   hipStream_t s = M.s;
   hipError_t e;
-  double *r, *z, *zold, *p, *q, *ones, *partial, *res, *host;
+  const LaplacePlan& A = M.lv[0].plan;
+  const long grid64 = cg_apply_grid(A, false);
+  double *r, *p, *q, *partial, *res, *st, *host;
+  T *rin, *zb[2];
 #define GMG_CHECK(call, what)                                 \
   do {                                                        \
     if ((e = (call)) != hipSuccess) return hip_fail(e, what); \
   } while (0)
   GMG_CHECK(M.alloc(&r, n), "work vectors");
-  GMG_CHECK(M.alloc(&z, n), "work vectors");
-  GMG_CHECK(M.alloc(&zold, n), "work vectors");
   GMG_CHECK(M.alloc(&p, n), "work vectors");
   GMG_CHECK(M.alloc(&q, n), "work vectors");
-  GMG_CHECK(M.alloc(&ones, n), "work vectors");
-  GMG_CHECK(M.alloc(&partial, 4LL * kCgBlocks), "work vectors");
+  GMG_CHECK(M.alloc(&zb[0], n), "work vectors");
+  GMG_CHECK(M.alloc(&zb[1], n), "work vectors");
+  if constexpr (MgRun<T>::F32) {
+    rin = M.lv[0].b;   // the level's own FP32 input vector
+  } else {
+    GMG_CHECK(M.alloc(&rin, n), "work vectors");
+  }
+  GMG_CHECK(M.alloc(&partial, std::max<long long>(4LL * kCgBlocks, (long long)grid64)), "work vectors");
   GMG_CHECK(M.alloc(&res, 4), "work vectors");
-  GMG_CHECK(hipHostMalloc((void**)&host, 4 * sizeof(double), 0), "pinned results");
+  GMG_CHECK(M.alloc(&st, kStateSize), "work vectors");
+  GMG_CHECK(hipHostMalloc((void**)&host, kStateSize * sizeof(double), 0), "pinned results");
   struct HostFree {
     double* h;
     ~HostFree() { (void)hipHostFree(h); }
@@ -281,87 +293,91 @@ int gmg_cg(const dg_op_desc* desc, int32_t levels, const double* lambda_max, con
     if ((er = hipMemcpyAsync(host, res, nq * sizeof(double), hipMemcpyDeviceToHost, s)) != hipSuccess) return er;
     return hipStreamSynchronize(s);
   };
-  const LaplacePlan& A = M.lv[0].plan;
   const double dn = (double)n;
-  // z = V r, projected on zero mean
-  auto precond = [&]() -> hipError_t {
-    hipError_t er;
-    if constexpr (MgRun<T>::F32) {
-      if ((er = mg_convert(r, M.lv[0].b, n, s)) != hipSuccess) return er;
-      if ((er = M.cycle(0)) != hipSuccess) return er;
-      if ((er = mg_convert(M.lv[0].x, z, n, s)) != hipSuccess) return er;
-    } else {
-      M.lv[0].b = r;
-      M.lv[0].x = z;
-      if ((er = M.cycle(0)) != hipSuccess) return er;
-    }
-    if ((er = cg_dot(z, ones, n, partial, s)) != hipSuccess) return er;
-    if ((er = sums(1)) != hipSuccess) return er;
-    return cg_axpb(z, z, 1.0, -host[0] / dn, n, s);
-  };
   const auto t1 = std::chrono::steady_clock::now();
-  GMG_CHECK(cg_fill(ones, 1.0, n, s), "fill");
-  int matvec = 0, it = 0, status = DG_OK;
+  long long matvec = 0;
+  int it = 0, status = DG_OK;
+  double rr = 0.0;
   GMG_CHECK(launch_laplace(A, false, x, q, s), "operator launch");
   ++matvec;
   GMG_CHECK(cg_residual(b, q, r, n, partial, s), "residual");
   GMG_CHECK(sums(4), "sums");
   const double bb = host[3] - host[2] * host[2] / dn;   // |b - mean(b)|^2
-  double rr = host[1] - host[0] * host[0] / dn;
-  GMG_CHECK(cg_axpb(r, r, 1.0, -host[0] / dn, n, s), "projection");
   const double tol2 = rtol * rtol * bb;
-  if (bb > 0.0 && rr > tol2) {
-    GMG_CHECK(precond(), "V-cycle");
-    GMG_CHECK(cg_dot(r, z, n, partial, s), "dot");
-    GMG_CHECK(sums(1), "sums");
-    double rz = host[0];
-    GMG_CHECK(cg_axpb(p, z, 1.0, 0.0, n, s), "copy");
-    for (;;) {
-      if (it >= max_iter) {
-        status = DG_NOT_CONVERGED;
-        break;
-      }
-      GMG_CHECK(launch_laplace(A, false, p, q, s), "operator launch");
-      ++matvec;
-      GMG_CHECK(cg_dot(p, q, n, partial, s), "dot");
-      GMG_CHECK(sums(1), "sums");
-      const double pq = host[0];
-      if (!(pq > 0.0) || !(rz > 0.0)) {
-        status = DG_ERR_BREAKDOWN;
-        break;
-      }
-      GMG_CHECK(cg_update_xr(x, r, p, q, rz / pq, n, partial, s), "update");
-      GMG_CHECK(sums(1), "sums");
-      GMG_CHECK(cg_axpb(r, r, 1.0, -host[0] / dn, n, s), "projection");
-      GMG_CHECK(cg_dot(r, r, n, partial, s), "dot");
-      GMG_CHECK(sums(1), "sums");
-      rr = host[0];
-      ++it;
-      if (rr <= tol2) break;
-      GMG_CHECK(cg_axpb(zold, z, 1.0, 0.0, n, s), "copy");
-      GMG_CHECK(precond(), "V-cycle");
-      GMG_CHECK(cg_dot(r, z, n, partial, s), "dot");
-      GMG_CHECK(cg_dot(r, zold, n, partial + kCgBlocks, s), "dot");
-      GMG_CHECK(sums(2), "sums");
-      const double rz_new = host[0];
-      GMG_CHECK(cg_xpby(p, z, (rz_new - host[1]) / rz, n, s), "direction update");
-      rz = rz_new;
+  // z = V r' with the sums of the flexible beta, then the direction update;
+  // zb[zn] receives the new output, zb[1 - zn] holds the previous one
+  int zn = 0;
+  auto precondition = [&](bool start) -> hipError_t {
+    hipError_t er;
+    if ((er = cg_fin_resid(partial, st, start, s)) != hipSuccess) return er;
+    if ((er = cg_rprime(r, st, rin, n, s)) != hipSuccess) return er;
+    M.lv[0].b = rin;
+    M.lv[0].x = zb[zn];
+    if ((er = M.cycle(0)) != hipSuccess) return er;
+    if ((er = cg_zsums(r, zb[zn], zb[1 - zn], st, n, partial, s)) != hipSuccess) return er;
+    if ((er = cg_fin_cheb(partial, kCgBlocks, st, start, s)) != hipSuccess) return er;
+    if ((er = cg_update_p_z(zb[zn], p, st, n, s)) != hipSuccess) return er;
+    zn = 1 - zn;
+    return hipSuccess;
+  };
+  if (bb > 0.0) {
+    GMG_CHECK(cg_state_init(st, tol2, max_iter, 0.0, n, true, s), "state");
+    GMG_CHECK(cg_fill(p, 0.0, n, s), "fill");
+    if constexpr (MgRun<T>::F32) {
+      GMG_CHECK(mg_convert(p, zb[1], n, s), "fill");   // zeros
+    } else {
+      GMG_CHECK(cg_fill(zb[1], 0.0, n, s), "fill");
     }
+    // start: alpha is 0 in the fresh state, so this only forms the sums of r0
+    GMG_CHECK(cg_update_xr_st(x, r, p, q, nullptr, M.n3, st, false, n, partial, s), "update");
+    GMG_CHECK(precondition(true), "V-cycle");
+    // batch size: up to 4, fewer when the observed contraction rate says the
+    // tolerance is that close (keeps queued no-op iterations rare)
+    constexpr int max_batch = 4;
+    long long queued = 0;
+    double rn2_prev = -1, it_prev = 0;
+    for (;;) {
+      GMG_CHECK(hipMemcpyAsync(host, st, kStateSize * sizeof(double), hipMemcpyDeviceToHost, s), "CG state");
+      GMG_CHECK(hipStreamSynchronize(s), "CG state");
+      if (host[kDone] != 0.0 || queued > (long long)max_iter + max_batch) break;
+      int batch = max_batch;
+      if (rn2_prev > 0 && host[kRN2] > 0 && host[kRN2] < rn2_prev && host[kIter] > it_prev) {
+        const double rate = std::log(host[kRN2] / rn2_prev) / (host[kIter] - it_prev);   // per iteration, < 0
+        const double left = std::log(host[kTol2] / host[kRN2]) / rate;
+        if (std::isfinite(left)) batch = (int)std::max(1.0, std::min((double)max_batch, std::ceil(left)));
+      }
+      rn2_prev = host[kRN2];
+      it_prev = host[kIter];
+      for (int b2 = 0; b2 < batch; ++b2) {
+        // q = A p with the p.q partials, alpha, x/r update with the sums of r
+        ++matvec;
+        GMG_CHECK(cg_apply_dot(A, p, q, partial, s), "operator launch");
+        GMG_CHECK(cg_fin_alpha(partial, (int)grid64, st, s), "alpha");
+        GMG_CHECK(cg_update_xr_st(x, r, p, q, nullptr, M.n3, st, false, n, partial, s), "update");
+        GMG_CHECK(precondition(false), "V-cycle");
+      }
+      queued += batch;
+    }
+    it = (int)host[kIter];
+    rr = host[kRN2];
+    if (host[kStatus] == 2.0) status = DG_ERR_BREAKDOWN;
+    else if (host[kStatus] == 1.0 || host[kDone] == 0.0) status = DG_NOT_CONVERGED;
   } else if (bb == 0.0) {
     GMG_CHECK(cg_fill(x, 0.0, n, s), "fill");
-    rr = 0.0;
   }
+  GMG_CHECK(hipStreamSynchronize(s), "solve");
   const auto t2 = std::chrono::steady_clock::now();
   if (report) {
     GMG_CHECK(launch_laplace(A, false, x, q, s), "operator launch");
     ++matvec;
-    GMG_CHECK(cg_residual(b, q, z, n, partial, s), "residual");
+    GMG_CHECK(cg_residual(b, q, r, n, partial, s), "residual");
     GMG_CHECK(sums(4), "sums");
     const double true_rr = host[1] - host[0] * host[0] / dn;
     const double bn = std::sqrt(bb);
     report->iterations = it;
-    // outer FP64 applies plus every level apply of the cycles, by precision
-    report->matvec_f64 = matvec + (MgRun<T>::F32 ? 0 : (int)M.applies);
+    // outer FP64 applies (queued no-op iterations included) plus every level
+    // apply of the cycles, by precision
+    report->matvec_f64 = (int)matvec + (MgRun<T>::F32 ? 0 : (int)M.applies);
     report->matvec_f32 = MgRun<T>::F32 ? (int)M.applies : 0;
     report->rel_res = bn > 0 ? std::sqrt(std::max(rr, 0.0)) / bn : 0.0;
     report->true_rel_res = bn > 0 ? std::sqrt(std::max(true_rr, 0.0)) / bn : 0.0;
@@ -370,7 +386,7 @@ int gmg_cg(const dg_op_desc* desc, int32_t levels, const double* lambda_max, con
     report->seconds_setup = std::chrono::duration<double>(t1 - t0).count();
   }
 #undef GMG_CHECK
-  if (status == DG_ERR_BREAKDOWN) return fail(DG_ERR_BREAKDOWN, "p.Ap <= 0");
+  if (status == DG_ERR_BREAKDOWN) return fail(DG_ERR_BREAKDOWN, "p.Ap <= 0 or a non-finite residual");
   if (status == DG_NOT_CONVERGED) return fail(DG_NOT_CONVERGED, "max_iter reached");
   return ok();
 }
