@@ -395,20 +395,29 @@ def step_extra(torch, dgmf, inputs, dev, k=7, N=24, steps=5):
     x, y, z = inputs.node_positions(dgmf.lgl_nodes(k), (N, N, N), (L,) * 3)
     u0 = torch.from_numpy(inputs.taylor_green(x, y, z)).to(dev)
     d = dgmf.make_desc(k, N)
-    bufs = [u0, torch.empty_like(u0), torch.empty_like(u0)]
-    _, p, rep0, rc = dgmf.dual_splitting_step(d, bufs[0], out=bufs[1], dt=dt, nu=nu, order=1)
-    res = {"dt": dt, "dofs": N ** 3 * (3 * (k + 1) ** 3 + k ** 3), "startup": rep0, "rc": [rc], "steps": []}
-    cur, prev, nxt = 1, 0, 2
-    for _ in range(steps):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        _, p, rep, rc = dgmf.dual_splitting_step(d, bufs[cur], bufs[prev], p=p, out=bufs[nxt], dt=dt, nu=nu, order=2)
-        res["steps"].append(dict(rep, wall_s=time.perf_counter() - t0))
-        res["rc"].append(rc)
-        cur, prev, nxt = nxt, cur, prev
-    w = [r["wall_s"] for r in res["steps"]]
-    res["ms_per_step"] = 1e3 * float(np.median(w))
-    res["dofs_steps_per_s"] = res["dofs"] / float(np.median(w))
+
+    def run(pc):
+        bufs = [u0.clone(), torch.empty_like(u0), torch.empty_like(u0)]
+        _, p, rep0, rc = dgmf.dual_splitting_step(d, bufs[0], out=bufs[1], dt=dt, nu=nu, order=1, pressure_precond=pc)
+        res = {"dt": dt, "dofs": N ** 3 * (3 * (k + 1) ** 3 + k ** 3), "startup": rep0, "rc": [rc], "steps": []}
+        cur, prev, nxt = 1, 0, 2
+        for _ in range(steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, p, rep, rc = dgmf.dual_splitting_step(d, bufs[cur], bufs[prev], p=p, out=bufs[nxt], dt=dt, nu=nu,
+                                                     order=2, pressure_precond=pc)
+            res["steps"].append(dict(rep, wall_s=time.perf_counter() - t0))
+            res["rc"].append(rc)
+            cur, prev, nxt = nxt, cur, prev
+        w = [r["wall_s"] for r in res["steps"]]
+        res["ms_per_step"] = 1e3 * float(np.median(w))
+        res["dofs_steps_per_s"] = res["dofs"] / float(np.median(w))
+        return res
+
+    # pressure CG with one FP32 V-cycle per iteration (24^3 -> 3^3, four
+    # levels; Sec. 3.3), then with the FP32 Chebyshev(5) smoother
+    res = run(dgmf.DG_STEP_PC_GMG_F32)
+    res["chebyshev_pressure"] = run(dgmf.DG_STEP_PC_CHEB_F32)
     return res
 
 
@@ -806,6 +815,10 @@ def summary(res):
                                            "iterations_p_proj_visc": [last["it_pressure"], last["it_projection"],
                                                                       last["it_viscous"]],
                                            "e_k": _r(last["kinetic_energy"], 6), "eps": _r(last["dissipation"], 4)}
+        g = st.get("chebyshev_pressure") or {}
+        if "ms_per_step" in g:
+            xs["dual_splitting_k7_24cubed"]["chebyshev_pressure"] = {"ms_per_step": _r(g["ms_per_step"]),
+                                                                     "it_pressure": g["steps"][-1]["it_pressure"]}
     for name in ("vjp_sweep", "inverse_mass_sweep", "projection_sweep", "gradient_sweep", "divergence_sweep"):
         v = ex.get(name)
         if isinstance(v, dict) and v:

@@ -293,7 +293,15 @@ typedef struct {
   double  rtol_viscous;
   double  atol_pressure;  /* absolute tolerance of the pressure solve (the paper: 1e-12) */
   int32_t max_iter;       /* iteration limit of each solve */
+  int32_t pressure_precond;   /* DG_STEP_PC_GMG_F32 (0, the default) or DG_STEP_PC_CHEB_F32 */
 } dg_step_opts;
+
+/* Preconditioners of the pressure CG of dg_dual_splitting_step: one FP32
+ * V-cycle of dg_gmg_cg_solve per iteration (Sec. 3.3, the paper's choice) on
+ * as many levels as the element counts allow (all halved while even with
+ * halves of at least 2, at most 5 levels), with the library's level bounds;
+ * or the FP32 Chebyshev(5) smoother of dg_cg_solve. */
+enum { DG_STEP_PC_GMG_F32 = 0, DG_STEP_PC_CHEB_F32 = 1 };
 
 typedef struct {
   int32_t it_pressure, it_projection, it_viscous;   /* CG iterations of the three solves */
@@ -307,7 +315,8 @@ typedef struct {
  * Sec. 3.3) on the periodic mesh of desc, in double precision, no body force:
  *   convective step  U^ = (sum_i alpha_i U^{n-i} - dt M^-1 sum_i beta_i C(U^{n-i})) / gamma_0
  *   pressure step    L P = -(gamma_0/dt) D U^        (degree k-1; FP64 CG with the FP32
- *                                                     Chebyshev(5) preconditioner)
+ *                                                     V-cycle or Chebyshev(5)
+ *                                                     preconditioner, opts->pressure_precond)
  *   projection step  (M + A_D + A_C) U^^ = M U^ - (dt/gamma_0) G P   (inverse-mass PCG)
  *   viscous step     (gamma_0/dt M + nu L) U^{n+1} = (gamma_0/dt) M U^^  (inverse-mass PCG)
  * BDF1: gamma_0 = 1, alpha = 1, beta = 1; BDF2: gamma_0 = 3/2,

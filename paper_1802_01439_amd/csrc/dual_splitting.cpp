@@ -4,8 +4,9 @@
 // library's operators and solvers:
 //
 //   1. convective step   U^ = (sum_i alpha_i U^{n-i} - dt M^-1 sum_i beta_i C(U^{n-i})) / gamma_0
-//   2. pressure step     L P = -(gamma_0/dt) D U^   (degree k-1: FP64 CG with the FP32 Chebyshev
-//                                                    preconditioner, zero-mean iterates)
+//   2. pressure step     L P = -(gamma_0/dt) D U^   (degree k-1: FP64 CG with the FP32 V-cycle
+//                                                    or FP32 Chebyshev preconditioner, zero-mean
+//                                                    iterates)
 //   3. projection step   (M + A_D + A_C) U^^ = M U^ - (dt/gamma_0) G P   (inverse-mass PCG)
 //   4. viscous step      (gamma_0/dt M + nu L) U^{n+1} = (gamma_0/dt) M U^^   (inverse-mass PCG)
 //
@@ -179,6 +180,8 @@ extern "C" int dg_dual_splitting_step(const dg_op_desc* desc, const dg_step_opts
   if (!(opts->atol_pressure >= 0) || !std::isfinite(opts->atol_pressure))
     return fail(DG_ERR_INVALID_ARG, "atol_pressure must be finite and >= 0");
   if (opts->max_iter < 1) return fail(DG_ERR_INVALID_ARG, "max_iter must be >= 1");
+  if (opts->pressure_precond != DG_STEP_PC_CHEB_F32 && opts->pressure_precond != DG_STEP_PC_GMG_F32)
+    return fail(DG_ERR_INVALID_ARG, "pressure_precond must be DG_STEP_PC_CHEB_F32 or DG_STEP_PC_GMG_F32");
   if (!u_n || !u_np1 || !p || (opts->order == 2 && !u_nm1))
     return fail(DG_ERR_INVALID_ARG, "u_n, u_np1, p (and u_nm1 for order 2) must not be NULL");
   const int k = desc->degree;
@@ -236,16 +239,33 @@ extern "C" int dg_dual_splitting_step(const dg_op_desc* desc, const dg_step_opts
   const DivPlan DP = make_div_plan(&dv);
   if ((e = launch_mixed(DP, false, false, uhat, W.bp, -g0 / dt, s)) != hipSuccess)
     return hip_fail(e, "mixed divergence kernel launch");
-  dg_cg_opts co{};
-  co.precond = DG_PC_CHEB_F32;
-  co.cheb_degree = 5;
-  co.cheb_range = 20.0;
-  co.rtol = opts->rtol_pressure;
-  co.atol = opts->atol_pressure;
-  co.max_iter = opts->max_iter;
-  co.project_mean = 1;
   dg_cg_report cr{};
-  rc = dg_cg_solve(&dp, &co, W.bp, p, &cr, hip_stream);
+  if (opts->pressure_precond == DG_STEP_PC_GMG_F32) {
+    // as many levels as the element counts allow: all halved while even with
+    // halves of at least 2, at most 5 levels
+    int levels = 1;
+    while (levels < 5) {
+      bool ok = true;
+      for (int d = 0; d < 3; ++d) {
+        const int m = dp.n_el[d] >> (levels - 1);
+        ok = ok && m % 2 == 0 && m / 2 >= 2;
+      }
+      if (!ok) break;
+      ++levels;
+    }
+    rc = gmg_cg_solve(&dp, levels, nullptr, DG_F32, W.bp, p, opts->rtol_pressure, opts->atol_pressure,
+                      opts->max_iter, &cr, hip_stream);
+  } else {
+    dg_cg_opts co{};
+    co.precond = DG_PC_CHEB_F32;
+    co.cheb_degree = 5;
+    co.cheb_range = 20.0;
+    co.rtol = opts->rtol_pressure;
+    co.atol = opts->atol_pressure;
+    co.max_iter = opts->max_iter;
+    co.project_mean = 1;
+    rc = dg_cg_solve(&dp, &co, W.bp, p, &cr, hip_stream);
+  }
   if (rc) return step_fail(rc, "pressure CG");
   // 3. projection step: penalties from the extrapolated velocity
   const double* uex = u_n;

@@ -19,6 +19,9 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <vector>
 
 #include "api_internal.h"
@@ -30,6 +33,39 @@
 namespace dgmf {
 
 namespace {
+
+// Device and pinned host buffers of the multigrid calls, kept for reuse: a
+// cycle or solve borrows them and hands them back when it returns (both
+// calls block until their work is done), so repeated calls on the same
+// hierarchy (the pressure solve of every time step) allocate nothing.
+struct MgPool {
+  std::mutex m;
+  std::multimap<std::tuple<int, bool, size_t>, void*> free;   // (device, pinned host, bytes)
+};
+MgPool& mg_pool() {
+  static MgPool pool;
+  return pool;
+}
+hipError_t pool_get(bool host, size_t bytes, void** p, int* dev) {
+  hipError_t e = hipGetDevice(dev);
+  if (e != hipSuccess) return e;
+  {
+    MgPool& P = mg_pool();
+    std::lock_guard<std::mutex> lk(P.m);
+    auto it = P.free.find(std::make_tuple(*dev, host, bytes));
+    if (it != P.free.end()) {
+      *p = it->second;
+      P.free.erase(it);
+      return hipSuccess;
+    }
+  }
+  return host ? hipHostMalloc(p, bytes, 0) : hipMalloc(p, bytes);
+}
+void pool_put(int dev, bool host, size_t bytes, void* p) {
+  MgPool& P = mg_pool();
+  std::lock_guard<std::mutex> lk(P.m);
+  P.free.emplace(std::make_tuple(dev, host, bytes), p);
+}
 
 template <typename T>
 struct MgLevel {
@@ -45,7 +81,13 @@ template <typename T>
 struct MgRun {
   static constexpr bool F32 = sizeof(T) == 4;
   std::vector<MgLevel<T>> lv;
-  std::vector<void*> owned;
+  struct Owned {
+    void* p;
+    size_t bytes;
+    int dev;
+    bool host;
+  };
+  std::vector<Owned> owned;   // borrowed from the pool, handed back at destruction
   int degree = 5, coarse_degree = 10, n3 = 0, k = 0;
   double range = 20.0;
   hipStream_t s = nullptr;
@@ -53,12 +95,14 @@ struct MgRun {
   long long applies = 0;   // level operator applications launched (all levels)
 
   ~MgRun() {
-    for (void* p : owned) (void)hipFree(p);
+    for (const Owned& o : owned) pool_put(o.dev, o.host, o.bytes, o.p);
   }
   template <typename U>
-  hipError_t alloc(U** p, long long n) {
-    hipError_t e = hipMalloc((void**)p, (size_t)n * sizeof(U));
-    if (e == hipSuccess) owned.push_back(*p);
+  hipError_t alloc(U** p, long long n, bool host = false) {
+    int dev = 0;
+    const size_t bytes = (size_t)n * sizeof(U);
+    hipError_t e = pool_get(host, bytes, (void**)p, &dev);
+    if (e == hipSuccess) owned.push_back({(void*)*p, bytes, dev, host});
     return e;
   }
 
@@ -253,7 +297,7 @@ namespace {
 // level vectors are set up once per solve.
 template <typename T>
 int gmg_cg(const dg_op_desc* desc, int32_t levels, const double* lambda_max, const double* b, double* x, double rtol,
-           int32_t max_iter, dg_cg_report* report, void* hip_stream) {
+           double atol, int32_t max_iter, dg_cg_report* report, void* hip_stream) {
   const auto t0 = std::chrono::steady_clock::now();
   MgRun<T> M;
   int rc = mg_setup(M, desc, levels, 5, 20.0, 10, lambda_max, (hipStream_t)hip_stream, b, x, MgRun<T>::F32);
@@ -282,11 +326,7 @@ int gmg_cg(const dg_op_desc* desc, int32_t levels, const double* lambda_max, con
   GMG_CHECK(M.alloc(&partial, std::max<long long>(4LL * kCgBlocks, (long long)grid64)), "work vectors");
   GMG_CHECK(M.alloc(&res, 4), "work vectors");
   GMG_CHECK(M.alloc(&st, kStateSize), "work vectors");
-  GMG_CHECK(hipHostMalloc((void**)&host, kStateSize * sizeof(double), 0), "pinned results");
-  struct HostFree {
-    double* h;
-    ~HostFree() { (void)hipHostFree(h); }
-  } host_free{host};
+  GMG_CHECK(M.alloc(&host, kStateSize, true), "pinned results");
   auto sums = [&](int nq) -> hipError_t {
     hipError_t er;
     if ((er = cg_finalize(partial, nq, res, s)) != hipSuccess) return er;
@@ -303,7 +343,8 @@ int gmg_cg(const dg_op_desc* desc, int32_t levels, const double* lambda_max, con
   GMG_CHECK(cg_residual(b, q, r, n, partial, s), "residual");
   GMG_CHECK(sums(4), "sums");
   const double bb = host[3] - host[2] * host[2] / dn;   // |b - mean(b)|^2
-  const double tol2 = rtol * rtol * bb;
+  const double tol = std::max(rtol * std::sqrt(std::max(bb, 0.0)), atol);
+  const double tol2 = tol * tol;
   // z = V r' with the sums of the flexible beta, then the direction update;
   // zb[zn] receives the new output, zb[1 - zn] holds the previous one
   int zn = 0;
@@ -392,15 +433,24 @@ int gmg_cg(const dg_op_desc* desc, int32_t levels, const double* lambda_max, con
 }
 
 }  // namespace
+
+int gmg_cg_solve(const dg_op_desc* desc, int levels, const double* lambda_max, int cycle_dtype, const double* b,
+                 double* x, double rtol, double atol, int max_iter, dg_cg_report* report, void* hip_stream) {
+  if (!b || !x) return fail(DG_ERR_INVALID_ARG, "b/x is NULL");
+  if (!(rtol > 0.0) || !std::isfinite(rtol)) return fail(DG_ERR_INVALID_ARG, "rtol must be finite and > 0");
+  if (!(atol >= 0.0) || !std::isfinite(atol)) return fail(DG_ERR_INVALID_ARG, "atol must be finite and >= 0");
+  if (max_iter < 0) return fail(DG_ERR_INVALID_ARG, "max_iter must be >= 0");
+  if (cycle_dtype == DG_F64)
+    return gmg_cg<double>(desc, levels, lambda_max, b, x, rtol, atol, max_iter, report, hip_stream);
+  if (cycle_dtype == DG_F32)
+    return gmg_cg<float>(desc, levels, lambda_max, b, x, rtol, atol, max_iter, report, hip_stream);
+  return fail(DG_ERR_INVALID_ARG, "cycle_dtype must be DG_F64 or DG_F32");
+}
+
 }  // namespace dgmf
 
 extern "C" int dg_gmg_cg_solve(const dg_op_desc* desc, int32_t levels, const double* lambda_max, int32_t cycle_dtype,
                                const double* b, double* x, double rtol, int32_t max_iter, dg_cg_report* report,
                                void* hip_stream) {
-  if (!b || !x) return fail(DG_ERR_INVALID_ARG, "b/x is NULL");
-  if (!(rtol > 0.0) || !std::isfinite(rtol)) return fail(DG_ERR_INVALID_ARG, "rtol must be finite and > 0");
-  if (max_iter < 0) return fail(DG_ERR_INVALID_ARG, "max_iter must be >= 0");
-  if (cycle_dtype == DG_F64) return gmg_cg<double>(desc, levels, lambda_max, b, x, rtol, max_iter, report, hip_stream);
-  if (cycle_dtype == DG_F32) return gmg_cg<float>(desc, levels, lambda_max, b, x, rtol, max_iter, report, hip_stream);
-  return fail(DG_ERR_INVALID_ARG, "cycle_dtype must be DG_F64 or DG_F32");
+  return dgmf::gmg_cg_solve(desc, levels, lambda_max, cycle_dtype, b, x, rtol, 0.0, max_iter, report, hip_stream);
 }

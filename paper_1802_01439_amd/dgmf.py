@@ -23,6 +23,7 @@ DG_ERR_BREAKDOWN = 2
 DG_F64, DG_F32 = 0, 1
 DG_PC_JACOBI_F64, DG_PC_CHEB_F32 = 0, 1
 DG_OP_HELMHOLTZ, DG_OP_PROJECTION = 0, 1
+DG_STEP_PC_GMG_F32, DG_STEP_PC_CHEB_F32 = 0, 1
 
 EXPORTS = ("dg_apply_laplace", "dg_apply_convective", "dg_vjp_convective", "dg_apply_divergence",
            "dg_apply_inverse_mass", "dg_apply_helmholtz", "dg_apply_projection", "dg_apply_gradient", "dg_prolongate", "dg_restrict", "dg_gmg_vcycle", "dg_gmg_cg_solve", "dg_cg_solve", "dg_cg_solve_noalloc", "dg_mass_pcg_solve", "dg_apply_divergence_mixed", "dg_apply_gradient_mixed",
@@ -55,7 +56,8 @@ class StepOpts(ctypes.Structure):
     _fields_ = [("order", ctypes.c_int32), ("dt", ctypes.c_double), ("nu", ctypes.c_double),
                 ("zeta_d", ctypes.c_double), ("zeta_c", ctypes.c_double), ("rtol_pressure", ctypes.c_double),
                 ("rtol_projection", ctypes.c_double), ("rtol_viscous", ctypes.c_double),
-                ("atol_pressure", ctypes.c_double), ("max_iter", ctypes.c_int32)]
+                ("atol_pressure", ctypes.c_double), ("max_iter", ctypes.c_int32),
+                ("pressure_precond", ctypes.c_int32)]
 
 
 class StepReport(ctypes.Structure):
@@ -499,9 +501,11 @@ def tgv_diagnostics(desc, u, nu):
 
 def dual_splitting_step(desc, u_n, u_nm1=None, p=None, out=None, dt=1e-3, nu=1.0 / 1600, order=2,
                         zeta_d=1.0, zeta_c=1.0, rtol=1e-6, rtol_pressure=None, rtol_projection=None,
-                        rtol_viscous=None, atol_pressure=1e-12, max_iter=2000):
+                        rtol_viscous=None, atol_pressure=1e-12, max_iter=2000, pressure_precond=DG_STEP_PC_GMG_F32):
     """One dual-splitting step; u_n, u_nm1, out: float64 [3, N_el, (k+1)^3];
-    p: float64 [N_el, k^3], initial guess in, P^{n+1} out (zeros if None).
+    p: float64 [N_el, k^3], initial guess in, P^{n+1} out (zeros if None);
+    pressure_precond: DG_STEP_PC_GMG_F32 (one FP32 V-cycle per pressure CG
+    iteration, the default) or DG_STEP_PC_CHEB_F32 (FP32 Chebyshev(5)).
     Returns (u_np1, p, report dict, return code)."""
     torch = _torch()
     k = desc.degree
@@ -525,6 +529,7 @@ def dual_splitting_step(desc, u_n, u_nm1=None, p=None, out=None, dt=1e-3, nu=1.0
     o.rtol_viscous = float(rtol if rtol_viscous is None else rtol_viscous)
     o.atol_pressure = float(atol_pressure)
     o.max_iter = int(max_iter)
+    o.pressure_precond = int(pressure_precond)
     rep = StepReport()
     nm1 = ctypes.c_void_p(u_nm1.data_ptr()) if order == 2 else None
     rc = _check(lib().dg_dual_splitting_step(ctypes.byref(desc), ctypes.byref(o), ctypes.c_void_p(u_n.data_ptr()),

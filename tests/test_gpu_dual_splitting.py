@@ -63,27 +63,29 @@ def test_diagnostics(k, N):
     assert abs(ek - rk) < 1e-12 * abs(rk) and abs(eps - re) < 1e-12 * abs(re)
 
 
-@pytest.mark.parametrize("k,N", [(3, 3), (5, 2), (2, 4)])
-def test_bdf1_then_bdf2_step_against_oracle(k, N):
+@pytest.mark.parametrize("pc", [dgmf.DG_STEP_PC_CHEB_F32, dgmf.DG_STEP_PC_GMG_F32])
+@pytest.mark.parametrize("k,N", [(3, 3), (5, 2), (2, 4), (2, 8)])
+def test_bdf1_then_bdf2_step_against_oracle(k, N, pc):
     """Taylor-Green + noise velocity, dt from the CFL condition (Cr = 0.2),
-    nu = 0.01; the GPU solves to 1e-12, the oracle's to 1e-13 (pressure:
-    exact)."""
+    nu = 0.01; the GPU solves to 1e-12 (pressure CG with the Chebyshev or the
+    V-cycle preconditioner: 1, 1, 2 and 3 levels on these meshes), the
+    oracle's to 1e-13 (pressure: exact)."""
     msh = M.cube(N)
     d = dgmf.make_desc(k, N)
     h = 2 * np.pi / N
     dt, nu = 0.2 / k ** 1.5 * h, 0.01
     u0 = inputs.tgv_plus_noise(basis.lgl_nodes(k), msh.n_el, msh.length, seed=1500 + k, noise_std=0.05)
-    announce(f"step BDF1 k={k} N={N}")
+    announce(f"step BDF1 k={k} N={N} pc={pc}")
     u1, p1, rep1, rc1 = dgmf.dual_splitting_step(d, to_dev(u0), dt=dt, nu=nu, order=1, rtol=1e-12,
-                                                 atol_pressure=0.0)
+                                                 atol_pressure=0.0, pressure_precond=pc)
     assert rc1 == dgmf.DG_OK, rep1
     r1 = dual_splitting_step([u0], k, msh, dt, nu, order=1)
     assert rel_err(u1.cpu().numpy(), r1["u"]) < 1e-9
     pg = p1.cpu().numpy()
     assert rel_err(pg - pg.mean(), r1["p"]) < 1e-8
-    announce(f"step BDF2 k={k} N={N}")
+    announce(f"step BDF2 k={k} N={N} pc={pc}")
     u2, p2, rep2, rc2 = dgmf.dual_splitting_step(d, u1, to_dev(u0), p=p1.clone(), dt=dt, nu=nu, order=2,
-                                                 rtol=1e-12, atol_pressure=0.0)
+                                                 rtol=1e-12, atol_pressure=0.0, pressure_precond=pc)
     assert rc2 == dgmf.DG_OK, rep2
     r2 = dual_splitting_step([r1["u"], u0], k, msh, dt, nu, order=2)
     assert rel_err(u2.cpu().numpy(), r2["u"]) < 1e-8
@@ -118,6 +120,9 @@ def test_step_argument_errors():
     with pytest.raises(dgmf.DgError) as ei:
         dgmf.dual_splitting_step(d, u, u, out=u, order=2)
     assert ei.value.code == dgmf.DG_ERR_ALIAS
+    with pytest.raises(dgmf.DgError) as ei:
+        dgmf.dual_splitting_step(d, u, order=1, pressure_precond=7)
+    assert ei.value.code == dgmf.DG_ERR_INVALID_ARG
     d1 = dgmf.make_desc(1, N)
     with pytest.raises(dgmf.DgError) as ei:
         dgmf.apply_divergence_mixed(d1, torch.zeros((3, N ** 3, 8), dtype=torch.float64, device="cuda"))
