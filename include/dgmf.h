@@ -396,8 +396,9 @@ int dg_gmg_vcycle(const dg_op_desc* desc, int32_t levels, int32_t degree, double
 /*
  * Solve A x = b with the SIPG form (n_comp = 1, periodic: b and the
  * iterates are taken at zero coefficient mean) by FP64 CG preconditioned with
- * one V-cycle per iteration (Sec. 3.3: Chebyshev degree 5, smoothing
- * range 20, coarse Chebyshev of degree 10), flexible beta.
+ * one V-cycle per iteration (the cycle of dg_gmg_vcycle: degree,
+ * smoothing_range and coarse_degree as there; Sec. 3.3 uses 5, 20 and a
+ * coarse Chebyshev solve of degree 10), flexible beta.
  *   lambda_max: host array of `levels` bounds as for dg_gmg_vcycle, or NULL
  *   (estimated per level as there);
  *   cycle_dtype: DG_F64 (the cycle of dg_gmg_vcycle) or DG_F32 (the cycle in
@@ -415,9 +416,9 @@ int dg_gmg_vcycle(const dg_op_desc* desc, int32_t levels, int32_t degree, double
  * Returns DG_OK, DG_NOT_CONVERGED or DG_ERR_BREAKDOWN, or a negative error.
  * Blocks the calling thread.
  */
-int dg_gmg_cg_solve(const dg_op_desc* desc, int32_t levels, const double* lambda_max, int32_t cycle_dtype,
-                    const double* b, double* x, double rtol, int32_t max_iter, dg_cg_report* report,
-                    void* hip_stream);
+int dg_gmg_cg_solve(const dg_op_desc* desc, int32_t levels, int32_t degree, double smoothing_range,
+                    int32_t coarse_degree, const double* lambda_max, int32_t cycle_dtype, const double* b, double* x,
+                    double rtol, int32_t max_iter, dg_cg_report* report, void* hip_stream);
 
 /*
  * diag(A) of the SIPG form on one element (identical on every element of a

@@ -35,8 +35,9 @@ int laplace_lambda_max(const dg_op_desc* d, bool project, void* hip_stream, doub
 // FP64 CG with one V-cycle (T = cycle precision, DG_F64 or DG_F32) per
 // iteration, stopping at |r| <= max(rtol |b - mean b|, atol); the body of
 // dg_gmg_cg_solve (which passes atol = 0).
-int gmg_cg_solve(const dg_op_desc* desc, int levels, const double* lambda_max, int cycle_dtype, const double* b,
-                 double* x, double rtol, double atol, int max_iter, dg_cg_report* report, void* hip_stream);
+int gmg_cg_solve(const dg_op_desc* desc, int levels, int degree, double smoothing_range, int coarse_degree,
+                 const double* lambda_max, int cycle_dtype, const double* b, double* x, double rtol, double atol,
+                 int max_iter, dg_cg_report* report, void* hip_stream);
 int default_conv_nq(int k);
 int make_conv_plan(const dg_op_desc* d, ConvPlan& P);
 

@@ -253,7 +253,7 @@ extern "C" int dg_dual_splitting_step(const dg_op_desc* desc, const dg_step_opts
       if (!ok) break;
       ++levels;
     }
-    rc = gmg_cg_solve(&dp, levels, nullptr, DG_F32, W.bp, p, opts->rtol_pressure, opts->atol_pressure,
+    rc = gmg_cg_solve(&dp, levels, 5, 20.0, 10, nullptr, DG_F32, W.bp, p, opts->rtol_pressure, opts->atol_pressure,
                       opts->max_iter, &cr, hip_stream);
   } else {
     dg_cg_opts co{};

@@ -296,11 +296,13 @@ namespace {
 // batch; iterations queued after convergence leave x and r unchanged.  The
 // level vectors are set up once per solve.
 template <typename T>
-int gmg_cg(const dg_op_desc* desc, int32_t levels, const double* lambda_max, const double* b, double* x, double rtol,
-           double atol, int32_t max_iter, dg_cg_report* report, void* hip_stream) {
+int gmg_cg(const dg_op_desc* desc, int32_t levels, int degree, double smoothing_range, int coarse_degree,
+           const double* lambda_max, const double* b, double* x, double rtol, double atol, int32_t max_iter,
+           dg_cg_report* report, void* hip_stream) {
   const auto t0 = std::chrono::steady_clock::now();
   MgRun<T> M;
-  int rc = mg_setup(M, desc, levels, 5, 20.0, 10, lambda_max, (hipStream_t)hip_stream, b, x, MgRun<T>::F32);
+  int rc = mg_setup(M, desc, levels, degree, smoothing_range, coarse_degree, lambda_max, (hipStream_t)hip_stream, b,
+                    x, MgRun<T>::F32);
   if (rc) return rc;
   const long long n = M.lv[0].n;
   hipStream_t s = M.s;
@@ -434,23 +436,27 @@ int gmg_cg(const dg_op_desc* desc, int32_t levels, const double* lambda_max, con
 
 }  // namespace
 
-int gmg_cg_solve(const dg_op_desc* desc, int levels, const double* lambda_max, int cycle_dtype, const double* b,
-                 double* x, double rtol, double atol, int max_iter, dg_cg_report* report, void* hip_stream) {
+int gmg_cg_solve(const dg_op_desc* desc, int levels, int degree, double smoothing_range, int coarse_degree,
+                 const double* lambda_max, int cycle_dtype, const double* b, double* x, double rtol, double atol,
+                 int max_iter, dg_cg_report* report, void* hip_stream) {
   if (!b || !x) return fail(DG_ERR_INVALID_ARG, "b/x is NULL");
   if (!(rtol > 0.0) || !std::isfinite(rtol)) return fail(DG_ERR_INVALID_ARG, "rtol must be finite and > 0");
   if (!(atol >= 0.0) || !std::isfinite(atol)) return fail(DG_ERR_INVALID_ARG, "atol must be finite and >= 0");
   if (max_iter < 0) return fail(DG_ERR_INVALID_ARG, "max_iter must be >= 0");
   if (cycle_dtype == DG_F64)
-    return gmg_cg<double>(desc, levels, lambda_max, b, x, rtol, atol, max_iter, report, hip_stream);
+    return gmg_cg<double>(desc, levels, degree, smoothing_range, coarse_degree, lambda_max, b, x, rtol, atol,
+                          max_iter, report, hip_stream);
   if (cycle_dtype == DG_F32)
-    return gmg_cg<float>(desc, levels, lambda_max, b, x, rtol, atol, max_iter, report, hip_stream);
+    return gmg_cg<float>(desc, levels, degree, smoothing_range, coarse_degree, lambda_max, b, x, rtol, atol,
+                         max_iter, report, hip_stream);
   return fail(DG_ERR_INVALID_ARG, "cycle_dtype must be DG_F64 or DG_F32");
 }
 
 }  // namespace dgmf
 
-extern "C" int dg_gmg_cg_solve(const dg_op_desc* desc, int32_t levels, const double* lambda_max, int32_t cycle_dtype,
-                               const double* b, double* x, double rtol, int32_t max_iter, dg_cg_report* report,
-                               void* hip_stream) {
-  return dgmf::gmg_cg_solve(desc, levels, lambda_max, cycle_dtype, b, x, rtol, 0.0, max_iter, report, hip_stream);
+extern "C" int dg_gmg_cg_solve(const dg_op_desc* desc, int32_t levels, int32_t degree, double smoothing_range,
+                               int32_t coarse_degree, const double* lambda_max, int32_t cycle_dtype, const double* b,
+                               double* x, double rtol, int32_t max_iter, dg_cg_report* report, void* hip_stream) {
+  return dgmf::gmg_cg_solve(desc, levels, degree, smoothing_range, coarse_degree, lambda_max, cycle_dtype, b, x, rtol,
+                            0.0, max_iter, report, hip_stream);
 }

@@ -98,8 +98,9 @@ def lib():
         L.dg_prolongate.argtypes = [pd, ctypes.c_int, vp, vp, vp]
         L.dg_gmg_vcycle.argtypes = [pd, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
                                      ctypes.POINTER(ctypes.c_double), ctypes.c_int32, vp, vp, vp]
-        L.dg_gmg_cg_solve.argtypes = [pd, ctypes.c_int32, ctypes.POINTER(ctypes.c_double), ctypes.c_int32, vp, vp,
-                                       ctypes.c_double, ctypes.c_int32, ctypes.POINTER(CgReport), vp]
+        L.dg_gmg_cg_solve.argtypes = [pd, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
+                                       ctypes.POINTER(ctypes.c_double), ctypes.c_int32, vp, vp, ctypes.c_double,
+                                       ctypes.c_int32, ctypes.POINTER(CgReport), vp]
         L.dg_restrict.argtypes = [pd, ctypes.c_int, vp, vp, vp]
         L.dg_cg_solve.argtypes = [pd, ctypes.POINTER(CgOpts), vp, vp, ctypes.POINTER(CgReport), vp]
         L.dg_cg_solve_noalloc.argtypes = [pd, ctypes.POINTER(CgOpts), vp, vp, ctypes.POINTER(CgReport), vp]
@@ -344,11 +345,12 @@ def gmg_vcycle(desc, r, lambda_max=None, degree=5, smoothing_range=20.0, coarse_
     return out
 
 
-def gmg_cg_solve(desc, b, lambda_max=None, x=None, rtol=1e-10, max_iter=200, cycle_dtype=DG_F64, levels=None):
+def gmg_cg_solve(desc, b, lambda_max=None, x=None, rtol=1e-10, max_iter=200, cycle_dtype=DG_F64, levels=None,
+                 degree=5, smoothing_range=20.0, coarse_degree=10):
     """FP64 CG with one V-cycle per iteration (periodic: zero-mean iterates),
-    the cycle in FP64 (DG_F64) or FP32 (DG_F32); lambda_max: per-level
-    bounds, or None with `levels` (estimated by the library); returns (x,
-    report dict, return code)."""
+    the cycle in FP64 (DG_F64) or FP32 (DG_F32) with the smoother of
+    gmg_vcycle; lambda_max: per-level bounds, or None with `levels`
+    (estimated by the library); returns (x, report dict, return code)."""
     torch = _torch()
     shape = (_nel(desc), (desc.degree + 1) ** 3)
     _check_tensor(b, "b", shape, dtype=torch.float64)
@@ -358,7 +360,8 @@ def gmg_cg_solve(desc, b, lambda_max=None, x=None, rtol=1e-10, max_iter=200, cyc
     nlev, lam = _levels_and_bounds(lambda_max, levels)
     rep = CgReport()
     _placed(b, x)
-    rc = _check(lib().dg_gmg_cg_solve(ctypes.byref(desc), nlev,
+    rc = _check(lib().dg_gmg_cg_solve(ctypes.byref(desc), nlev, int(degree), float(smoothing_range),
+                                      int(coarse_degree),
                                       None if lam is None else lam.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                       int(cycle_dtype),
                                       ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(x.data_ptr()), float(rtol),

@@ -135,14 +135,16 @@ def test_validation_errors_of_the_multigrid_entry_points_without_gpu():
                            None) == dgmf.DG_ERR_ALIAS
     rep = dgmf.CgReport()
 
-    def cg(desc, levels, lam, b, x, rtol=1e-10, it=10, cycle=dgmf.DG_F64):
-        return L.dg_gmg_cg_solve(ctypes.byref(desc), levels, lam, cycle, vp(b), vp(x), rtol, it, ctypes.byref(rep),
-                                 None)
+    def cg(desc, levels, lam, b, x, rtol=1e-10, it=10, cycle=dgmf.DG_F64, deg=5, rng=20.0, cdeg=10):
+        return L.dg_gmg_cg_solve(ctypes.byref(desc), levels, deg, rng, cdeg, lam, cycle, vp(b), vp(x), rtol, it,
+                                 ctypes.byref(rep), None)
     assert cg(d, 2, lam2, fa, fb, rtol=0.0) == dgmf.DG_ERR_INVALID_ARG
     assert cg(d, 2, lam2, fa, fb, cycle=7) == dgmf.DG_ERR_INVALID_ARG       # cycle precision F64 or F32
     assert cg(d, 2, lam2, fa, fa + 8, cycle=dgmf.DG_F32) == dgmf.DG_ERR_ALIAS
     assert cg(d, 2, lam2, fa, fb, it=-1) == dgmf.DG_ERR_INVALID_ARG
     assert cg(d, 2, bad, fa, fb) == dgmf.DG_ERR_INVALID_ARG
+    assert cg(d, 2, lam2, fa, fb, deg=0) == dgmf.DG_ERR_INVALID_ARG          # smoother degrees >= 1
+    assert cg(d, 2, lam2, fa, fb, rng=0.5) == dgmf.DG_ERR_INVALID_ARG        # smoothing range > 1
     assert cg(d, 2, lam2, fa, fa + 8) == dgmf.DG_ERR_ALIAS
 
 

@@ -147,6 +147,31 @@ def test_vcycle_pcg_config5_against_fdm(cycle):
     announce(f"V-cycle PCG config 5 report {rep}")
 
 
+@pytest.mark.parametrize("degree,rng,cdeg", [(3, 10.0, 6), (7, 30.0, 12)])
+def test_vcycle_pcg_smoother_parameters_match_the_oracle(degree, rng, cdeg):
+    """The solver's smoother degree, smoothing range and coarse degree reach
+    the cycle: same iteration count (within one) and solution as the
+    oracle's flexible PCG with the oracle cycle of those parameters."""
+    from oracle.solvers import pcg
+    k, fine, levels = 2, M.cube(8), 3
+    lam = _lams(k, fine, levels, 1.0, 1.0)
+    b = inputs.uniform((fine.N, (k + 1) ** 3), seed=1130 + degree)
+    b -= b.mean()
+    announce(f"V-cycle PCG smoother degree={degree} range={rng} coarse={cdeg}")
+    x, rep, rc = dgmf.gmg_cg_solve(dgmf.make_desc(k, 8), to_dev(b), lam, rtol=1e-10, degree=degree,
+                                   smoothing_range=rng, coarse_degree=cdeg)
+    assert rc == dgmf.DG_OK, rep
+    xr, info = pcg(lambda v: laplace_apply(v, k, fine), b,
+                   precond=lambda r: vcycle(r, k, fine, levels, lam, degree=degree, smoothing_range=rng,
+                                            coarse_degree=cdeg),
+                   rtol=1e-10, project=True)
+    xs = x.cpu().numpy()
+    xs -= xs.mean()
+    xr -= xr.mean()
+    assert abs(rep["iterations"] - info["iterations"]) <= 1, (rep["iterations"], info["iterations"])
+    assert rel_err(xs, xr) < 1e-8
+
+
 @pytest.mark.parametrize("cycle", [dgmf.DG_F64, dgmf.DG_F32])
 def test_gmg_cg_estimates_level_bounds_and_counts_applies(cycle):
     """lambda_max = None: the library estimates each level's bound with the
