@@ -12,6 +12,21 @@
 
 namespace dgmf {
 
+// Workgroup barrier for LDS traffic only: waits for this wave's LDS (and
+// scalar) operations, not for its global loads, so loads issued before it
+// stay in flight across it.  The memory clobber keeps the compiler from
+// moving shared-memory accesses across it.
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+// Index of the first item of a second kind of work that follows n0 items
+// of a first kind in a loop over items by th threads: the next wavefront
+// boundary when that adds no round of th items, so that no wavefront runs the
+// (divergent) code of both kinds one after the other.
+constexpr int wave_split(int n0, int n1, int th) {
+  const int p = (n0 + 63) / 64 * 64;
+  return (p + n1 + th - 1) / th == (n0 + n1 + th - 1) / th ? p : n0;
+}
+
 // 1D tables in even-odd form.  The LGL nodes and the Gauss points are
 // symmetric about 1/2, so S[m-1-q][n-1-a] = S[q][a] and
 // G[m-1-q][n-1-a] = -G[q][a].  With x_e[a] = x[a] + x[n-1-a] and

@@ -62,12 +62,6 @@
 
 namespace dgmf {
 
-// Workgroup barrier for LDS traffic only: waits for this wave's LDS (and
-// scalar) operations, not for its global loads, so loads issued before it
-// stay in flight across it.  The memory clobber keeps the compiler from
-// moving shared-memory accesses across it.
-__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
-
 // Collocation derivative at the m Gauss points: d[q][p] = l_p'(z_q) for the
 // Lagrange basis of the Gauss points (barycentric form).
 template <int Q, typename T>
@@ -277,7 +271,8 @@ vjp_onepass_kernel(const T* __restrict__ u, const T* __restrict__ wv, T* __restr
   // ---------------- P2: y sweeps in place ----------------
   {
     constexpr int nUW = 2 * 3 * E * (N + 2) * Q, nG = 3 * E * N * Q;
-    for (int w = tid; w < nUW + nG; w += TH) {
+    constexpr int FG = wave_split(nUW, nG, TH);   // first WGX item
+    for (int w = tid; w < FG + nG; w += TH) {
       CONV_TABLES(t);
       if (w < nUW) {   // U or WS column block (q1, layer c')
         const int q1 = w % Q, rest = w / Q;
@@ -295,8 +290,8 @@ vjp_onepass_kernel(const T* __restrict__ u, const T* __restrict__ wv, T* __restr
           eo_interp_g<N, Q, T>(t, x, [&](int q, T val) { pg[MP * q] = val; });
         }
         eo_interp<N, Q, T>(t, x, [&](int q, T val) { p[MP * q] = val; });
-      } else {          // WGX column block: S_y in place
-        const int v = w - nUW;
+      } else if (w >= FG) {   // WGX column block: S_y in place
+        const int v = w - FG;
         const int q1 = v % Q, rest = v / Q;
         const int c = rest % N, r2 = rest / N;
         const int le = r2 % E, j = r2 / E;
@@ -337,7 +332,8 @@ vjp_onepass_kernel(const T* __restrict__ u, const T* __restrict__ wv, T* __restr
   // ---------------- P3: z pencils and face pencils ----------------
   {
     constexpr int nCell = E * Q * Q, nH = E * 4 * Q;
-    for (int w = tid; w < nCell + nH; w += TH) {
+    constexpr int FO = wave_split(nCell, nH, TH);   // first face-pencil item
+    for (int w = tid; w < FO + nH; w += TH) {
       CONV_TABLES(t);
       if (w < nCell) {
         const int le = w / (Q * Q), qq = w - le * (Q * Q);
@@ -452,8 +448,8 @@ vjp_onepass_kernel(const T* __restrict__ u, const T* __restrict__ wv, T* __restr
             if (c == N - 1) o += Gz[1][k];
             col[(k * N + c) * COLS] = o;
           }
-      } else {   // face pencil: fam 0 = y face (q = q1), 1 = x face (q = q2)
-        const int h = w - nCell;
+      } else if (w >= FO) {   // face pencil: fam 0 = y face (q = q1), 1 = x face (q = q2)
+        const int h = w - FO;
         const int le = h / (4 * Q);
         if (le >= ne) continue;
         int rem = h - le * 4 * Q;
@@ -529,7 +525,8 @@ vjp_onepass_kernel(const T* __restrict__ u, const T* __restrict__ wv, T* __restr
   // ---------------- Y: S^T_y in place, y-face terms; S^T_y of the x-face terms ----------------
   {
     constexpr int nY = 3 * E * N * Q, nXf = 3 * E * 2 * N;
-    for (int w = tid; w < nY + nXf; w += TH) {
+    constexpr int FX = wave_split(nY, nXf, TH);   // first x-face item
+    for (int w = tid; w < FX + nXf; w += TH) {
       CONV_TABLES(t);
       if (w < nY) {
         const int q1 = w % Q, rest = w / Q;
@@ -552,8 +549,8 @@ vjp_onepass_kernel(const T* __restrict__ u, const T* __restrict__ wv, T* __restr
           if (b == N - 1) o += f1;
           tb[MP * b] = o;
         }
-      } else {
-        const int vv = w - nY;
+      } else if (w >= FX) {
+        const int vv = w - FX;
         const int cz = vv % N, rest = vv / N;
         const int s = rest % 2, r2 = rest / 2;
         const int le = r2 % E, k = r2 / E;
@@ -823,7 +820,8 @@ vjp_percomp_kernel(const T* __restrict__ u, const T* __restrict__ wv, T* __restr
   // ---------------- P3 state ----------------
   constexpr int FAM = FXL ? 1 : 2;   // face families taken in the passes
   constexpr int nCell = E * Q * Q, nH = E * FAM * 2 * Q;
-  constexpr int NIT = (nCell + nH + TH - 1) / TH;
+  constexpr int FO = wave_split(nCell, nH, TH);   // first face-pencil item
+  constexpr int NIT = (FO + nH + TH - 1) / TH;
   EoT<N, T, 1> acc[NIT][3];
   T gz[NIT][2][3];   // z-face terms of a z pencil at its two end nodes
 #pragma unroll
@@ -899,7 +897,7 @@ vjp_percomp_kernel(const T* __restrict__ u, const T* __restrict__ wv, T* __restr
 #pragma unroll
     for (int it = 0; it < NIT; ++it) {
       const int w = tid + it * TH;
-      if (w >= nCell + nH) continue;
+      if (w >= FO + nH || (w >= nCell && w < FO)) continue;
       CONV_TABLES(t);
       if (w < nCell) {
         const int le = w / (Q * Q), qq = w - le * (Q * Q);
@@ -1008,7 +1006,7 @@ vjp_percomp_kernel(const T* __restrict__ u, const T* __restrict__ wv, T* __restr
           }
         }
       } else {   // face pencil: fam 0 = y face (q = q1), 1 = x face (q = q2)
-        const int h = w - nCell;
+        const int h = w - FO;
         const int le = h / (FAM * 2 * Q);
         if (le >= ne) continue;
         int rem = h - le * FAM * 2 * Q;
@@ -1075,7 +1073,7 @@ vjp_percomp_kernel(const T* __restrict__ u, const T* __restrict__ wv, T* __restr
 #pragma unroll
   for (int it = 0; it < NIT; ++it) {
     const int w = tid + it * TH;
-    if (w >= nCell + nH) continue;
+    if (w >= FO + nH || (w >= nCell && w < FO)) continue;
     if (w < nCell) {
       const int le = w / (Q * Q), qq = w - le * (Q * Q);
       if (le >= ne) continue;
@@ -1093,7 +1091,7 @@ vjp_percomp_kernel(const T* __restrict__ u, const T* __restrict__ wv, T* __restr
           col[(k * N + c) * COLS] = o;
         }
     } else {
-      const int h = w - nCell;
+      const int h = w - FO;
       const int le = h / (FAM * 2 * Q);
       if (le >= ne) continue;
       int rem = h - le * FAM * 2 * Q;
@@ -1206,7 +1204,8 @@ vjp_percomp_kernel(const T* __restrict__ u, const T* __restrict__ wv, T* __restr
   // ---------------- Y: S^T_y in place, y-face terms; S^T_y of the x-face terms ----------------
   {
     constexpr int nYs = 3 * E * N * Q, nXf = 3 * E * 2 * N;
-    for (int w = tid; w < nYs + nXf; w += TH) {
+    constexpr int FX = wave_split(nYs, nXf, TH);   // first x-face item
+    for (int w = tid; w < FX + nXf; w += TH) {
       CONV_TABLES(t);
       if (w < nYs) {
         const int q1 = w % Q, rest = w / Q;
@@ -1229,8 +1228,8 @@ vjp_percomp_kernel(const T* __restrict__ u, const T* __restrict__ wv, T* __restr
           if (b == N - 1) o += f1;
           tb[MP * b] = o;
         }
-      } else {
-        const int vv = w - nYs;
+      } else if (w >= FX) {
+        const int vv = w - FX;
         const int cz = vv % N, rest = vv / N;
         const int s = rest % 2, r2 = rest / 2;
         const int le = r2 % E, k = r2 / E;

@@ -106,6 +106,33 @@ def test_full_size_sampled(dtype):
     assert rel_err(y[:, sample], ref) < tol
 
 
+@pytest.mark.parametrize("k,n_el", [(6, (8, 8, 13)), (9, (7, 7, 7)), (10, (5, 6, 9)), (11, (4, 7, 10)),
+                                    (6, (2, 2, 2)), (9, (5, 1, 1)), (11, (3, 1, 4))])
+def test_persistent_batch_walk_fp64(k, n_el):
+    """FP64 k = 11 runs one persistent workgroup per CU that walks its XCD's
+    share of element batches, loading the next batch while it finishes the
+    current one: more batches than compute units, shares of unequal length,
+    grids of fewer than 8 and of 8..16 workgroups.  FP64 k = 6, 9, 10 (one
+    workgroup per CU, one batch each) on meshes of the same kind, k = 6 with
+    a ragged last batch (three elements per batch: 832 = 3 * 277 + 1,
+    8 = 3 * 2 + 2).  Anisotropic box; sampled elements include the first and
+    last of the mesh and an x row end."""
+    length = (2 * np.pi, 1.5, 2.5)
+    msh = M.Mesh(n_el, length)
+    n3 = (k + 1) ** 3
+    u = inputs.uniform((3, msh.N, n3), seed=1100 + k)
+    announce(f"convective persistent fp64 k={k} n_el={n_el}")
+    y = _run(k, n_el, length, u, lf_factor=0.8)
+    nel = msh.N
+    rng = np.random.default_rng(1200 + k)
+    fixed = [0, 1, n_el[0] - 1, nel // 2, nel - 3, nel - 2, nel - 1]
+    sample = np.unique(np.concatenate([fixed, rng.integers(0, nel, 40)]))
+    ref = convective_apply(u, k, msh, lf_factor=0.8, elems=sample)
+    ys = y[:, sample]
+    assert rel_err(ys, ref) < 1e-12
+    assert np.abs(ys - ref).max() <= 1e-11 * np.abs(ref).max()
+
+
 def test_unsupported_nq():
     d = dgmf.make_desc(3, 4, n_q=4)
     u = torch.zeros((3, 64, 64), dtype=torch.float64, device="cuda")
