@@ -128,6 +128,35 @@ __device__ __forceinline__ void load_pencil(const T* __restrict__ p, int stride,
   for (int i = 0; i < N; ++i) in[i] = p[i * stride];
 }
 
+// A pencil of n contiguous values in 16-byte loads; n values fill whole
+// 16-byte words and p is 16-byte aligned (the caller guarantees both).
+template <int N, typename T>
+__device__ __forceinline__ void load_pencil16(const T* __restrict__ p, T (&in)[N]) {
+  constexpr int V = 16 / (int)sizeof(T);
+  static_assert((N * sizeof(T)) % 16 == 0, "pencil does not fill whole 16-byte words");
+  typedef T vec __attribute__((ext_vector_type(V)));
+  const vec* q = reinterpret_cast<const vec*>(__builtin_assume_aligned(p, 16));
+#pragma unroll
+  for (int i = 0; i < N / V; ++i) {
+    const vec x = q[i];
+#pragma unroll
+    for (int c = 0; c < V; ++c) in[i * V + c] = x[c];
+  }
+}
+
+// load_pencil, in 16-byte loads where they apply: n values fill whole 16-byte
+// words, the pencil is contiguous (stride 1) and a16 says it is 16-byte aligned.
+template <int N, int Q, typename T>
+__device__ __forceinline__ void load_pencil_a16(const T* __restrict__ p, int stride, bool a16, T (&in)[N]) {
+  if constexpr ((N * sizeof(T)) % 16 == 0) {
+    if (a16 && stride == 1) {
+      load_pencil16<N, T>(p, in);
+      return;
+    }
+  }
+  load_pencil<N, Q, T>(p, stride, in);
+}
+
 // y = S x in even-odd form; st(q, y[q]) receives every output.
 template <int N, int Q, typename T, typename Tab, typename St>
 __device__ __forceinline__ void eo_interp(const Tab& t, const T (&x)[N], St&& st) {

@@ -109,13 +109,17 @@ struct ConvShape {
   // next one while finishing the current.  Measured only at FP64 k=11 faster
   // (5 %); at FP64 k=6, 9, 10, also one workgroup per CU, 0 to 5 % slower
   static constexpr bool PERS = N == 12 && SZ == 8;
+  // 16-byte loads of contiguous pencils (where n values fill whole 16-byte
+  // words; the launch uses them only for a 16-byte aligned input): 2 % (FP64
+  // k=9) to 11 % (FP32 k=7) faster; at FP64 k=11 (persistent) 40 % slower
+  static constexpr bool VEC = !PERS && (N * SZ) % 16 == 0;
   static_assert(E * PER * SZ <= 160 * 1024, "convective LDS footprint exceeds 160 KB");
 };
 
 template <int N, int Q, typename T, int E, int TH, bool ALLC, bool PERS>
 __global__ void __launch_bounds__(TH) __attribute__((amdgpu_waves_per_eu(ConvShape<N, Q, (int)sizeof(T)>::MINW, 8)))
 convective_kernel(const T* __restrict__ u, T* __restrict__ r, MeshArgs mesh,
-                  const ConvTab<N, Q, T>* __restrict__ tab, ConvScal<T> sc) {
+                  const ConvTab<N, Q, T>* __restrict__ tab, ConvScal<T> sc, bool u16) {
   using Sh = ConvShape<N, Q, (int)sizeof(T)>;
   static_assert(!(PERS && ALLC), "the persistent form prefetches during the per-component back sweeps");
   constexpr int N2 = Sh::N2, N3 = Sh::N3, MP = Sh::MP, COLS = Sh::COLS, LAYER = Sh::LAYER;
@@ -191,7 +195,9 @@ convective_kernel(const T* __restrict__ u, T* __restrict__ r, MeshArgs mesh,
   // share its index arithmetic; all of a thread's loads are issued before any
   // sweep, so the global load latency is paid once per thread.
   constexpr int nM = E * N2, nL = E * 4 * N, nX = E * 4 * N;   // cell, y/z neighbour, x-face items
-  constexpr int total = nM + nL + nX;
+  // first x-face item: its strided loads start a wavefront where the others take 16-byte loads
+  constexpr int FXI = Sh::VEC ? wave_split(nM + nL, nX, TH) : nM + nL;
+  constexpr int total = FXI + nX;
   constexpr int D1S = (N + 2) * COLS;   // component stride of the BC slots
   // item w of batch p -> source pencil of component 0 (src, stride), LDS
   // destination of component 0 (d1) with its component stride (dstr), second
@@ -228,8 +234,8 @@ convective_kernel(const T* __restrict__ u, T* __restrict__ r, MeshArgs mesh,
         d1 = L + FYo + (1 * 2 + s) * 3 * LAYER + q * Q;
         dstr = LAYER;
       }
-    } else {        // x-face layer (own or neighbour), swept in y
-      const int v = w - nM - nL;
+    } else if (w >= FXI) {   // x-face layer (own or neighbour), swept in y
+      const int v = w - FXI;
       const int le = v / (4 * N);
       if (le >= p.ne) return;
       const int rem = v - le * 4 * N;
@@ -263,8 +269,18 @@ convective_kernel(const T* __restrict__ u, T* __restrict__ r, MeshArgs mesh,
         int sstride;
         item(p, w, src, sstride, d1[i], ds[i], d2[i]);
         if (d1[i] >= 0) {
+          bool done = false;
+          if constexpr (Sh::VEC) {
+            if (u16 && sstride == 1) {
 #pragma unroll
-          for (int j = 0; j < 3; ++j) load_pencil<N, Q, T>(src + j * cs, sstride, in[i][j]);
+              for (int j = 0; j < 3; ++j) load_pencil16<N, T>(src + j * cs, in[i][j]);
+              done = true;
+            }
+          }
+          if (!done) {
+#pragma unroll
+            for (int j = 0; j < 3; ++j) load_pencil<N, Q, T>(src + j * cs, sstride, in[i][j]);
+          }
         }
       }
       if constexpr (PERS) {
@@ -670,8 +686,12 @@ static hipError_t launch_conv_nq(const ConvPlan& P, const void* u, void* r, hipS
     if (err != hipSuccess) return err;
     grid = std::min(grid, cus);
   }
+  // every pencil of n contiguous values starts at a multiple of n values
+  // from u, so a 16-byte aligned u aligns them all where n values fill whole
+  // 16-byte words
+  const bool u16 = Sh::VEC && (reinterpret_cast<uintptr_t>(u) % 16) == 0;
   hipLaunchKernelGGL((convective_kernel<N, Q, T, Sh::E, Sh::TH, Sh::ALLC, Sh::PERS>), dim3(grid), dim3(Sh::TH), 0,
-                     s, (const T*)u, (T*)r, P.mesh, dt, sc);
+                     s, (const T*)u, (T*)r, P.mesh, dt, sc, u16);
   return hipGetLastError();
 }
 
