@@ -122,6 +122,7 @@ convective_kernel(const T* __restrict__ u, T* __restrict__ r, MeshArgs mesh,
                   const ConvTab<N, Q, T>* __restrict__ tab, ConvScal<T> sc, bool u16) {
   using Sh = ConvShape<N, Q, (int)sizeof(T)>;
   static_assert(!(PERS && ALLC), "the persistent form prefetches during the per-component back sweeps");
+  static_assert(ALLC || TH >= E * Q * Q, "per-component mode keeps one z pencil per thread in registers");
   constexpr int N2 = Sh::N2, N3 = Sh::N3, MP = Sh::MP, COLS = Sh::COLS, LAYER = Sh::LAYER;
   constexpr int NH = N / 2, QH = Q / 2;
   constexpr int PER = Sh::per(ALLC);
