@@ -87,18 +87,20 @@ struct ConvShape {
   static constexpr int PER = per(ALLC);
   static constexpr int BYTES = PER * SZ;
   // about 52 KB per workgroup (three per CU), 1..16 elements; FP64 k=6
-  // measured 14 % faster with three elements (300 z pencils in 320 threads)
-  // than with the two that fit the budget (200 pencils in 256 threads)
+  // takes two (76 KB, two workgroups per CU): 10 % faster than three
+  // elements in one 512-thread workgroup per CU, once cell and face pencils
+  // no longer share wavefronts (before that, three measured 14 % faster)
   static constexpr int E0 = (52 * 1024) / BYTES;
-  static constexpr int E = (N == 7 && SZ == 8) ? 3 : (E0 < 1 ? 1 : (E0 > 16 ? 16 : E0));
+  static constexpr int E = (N == 7 && SZ == 8) ? 2 : (E0 < 1 ? 1 : (E0 > 16 ? 16 : E0));
   // per-component mode keeps one z pencil per thread in registers.  Where
-  // one workgroup fills a CU's LDS (the highest degrees, FP64 k=6) 512
-  // threads hide more latency (FP64 k=6: 10 % faster than 320); below that
-  // a larger group only lowers the register limit
-  // FP64 k=7 (121 z pencils, 256 VGPRs either way) measured 5 % faster with
-  // two wavefronts than with four; elsewhere fewer threads than 256 cost
-  // occupancy (the freed register budget gets used)
-  static constexpr int TH0 = (N == 8 && SZ == 8) ? 128 : (E * Q * Q > 256) ? ((E * Q * Q + 63) / 64) * 64 : 256;
+  // one workgroup fills a CU's LDS (the highest degrees) 512 threads hide
+  // more latency; below that a larger group only lowers the register limit.
+  // FP64 k=7 (121 z pencils, 44 face pencils) runs three wavefronts, the
+  // face pencils in the third: 10 % faster than two wavefronts (two rounds
+  // of items) and than four; elsewhere fewer threads than 256 cost
+  // occupancy (the freed register budget gets used), and 320-thread groups
+  // measured slower (FP64 k=4: 2x, FP32 k=9: 33 %)
+  static constexpr int TH0 = (N == 8 && SZ == 8) ? 192 : (E * Q * Q > 256) ? ((E * Q * Q + 63) / 64) * 64 : 256;
   static constexpr int TH = ((E == 1 && Q >= 16) || E * BYTES > 80 * 1024) ? (TH0 > 512 ? TH0 : 512) : TH0;
   // minimum wavefronts per SIMD (register cap) where registers, not LDS,
   // limited the groups per CU: at 128 VGPRs FP32 k=11 fits two 512-thread
