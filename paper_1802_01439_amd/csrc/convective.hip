@@ -132,9 +132,10 @@ convective_kernel(const T* __restrict__ u, T* __restrict__ r, MeshArgs mesh,
   constexpr int FXo = FYo + Sh::FL;
   constexpr int XRo = FXo + Sh::FL;
   __shared__ T lds[E * PER];
-  // the thread index, opaque to the compiler, taken afresh in each loop step:
-  // otherwise the index arithmetic of every phase, which depends on it alone,
-  // is hoisted out of the batch loop and held in registers throughout
+  // the thread index; in the persistent form opaque to the compiler (its
+  // range restated) and taken afresh in each loop step: otherwise the index
+  // arithmetic of every phase, which depends on it alone, is hoisted out of
+  // the batch loop and held in registers throughout
   auto thread_index = []() {
     int t = threadIdx.x;
     if constexpr (PERS) {
