@@ -106,16 +106,16 @@ def test_full_size_sampled(dtype):
     assert rel_err(y[:, sample], ref) < tol
 
 
-@pytest.mark.parametrize("k,n_el", [(6, (8, 8, 13)), (9, (7, 7, 7)), (10, (5, 6, 9)), (11, (4, 7, 10)),
-                                    (6, (2, 2, 2)), (9, (5, 1, 1)), (11, (3, 1, 4))])
+@pytest.mark.parametrize("k,n_el", [(6, (7, 9, 13)), (9, (7, 7, 7)), (10, (5, 6, 9)), (11, (4, 7, 10)),
+                                    (6, (3, 1, 3)), (9, (5, 1, 1)), (11, (3, 1, 4))])
 def test_persistent_batch_walk_fp64(k, n_el):
     """FP64 k = 11 runs one persistent workgroup per CU that walks its XCD's
     share of element batches, loading the next batch while it finishes the
     current one: more batches than compute units, shares of unequal length,
-    grids of fewer than 8 and of 8..16 workgroups.  FP64 k = 6, 9, 10 (one
-    workgroup per CU, one batch each) on meshes of the same kind, k = 6 with
-    a ragged last batch (three elements per batch: 832 = 3 * 277 + 1,
-    8 = 3 * 2 + 2).  Anisotropic box; sampled elements include the first and
+    grids of fewer than 8 and of 8..16 workgroups.  FP64 k = 9, 10 (one
+    workgroup per CU, one batch each) and k = 6 (two elements per batch) on
+    meshes of the same kind, k = 6 with a ragged last batch (819 = 2 * 409 + 1,
+    9 = 2 * 4 + 1).  Anisotropic box; sampled elements include the first and
     last of the mesh and an x row end."""
     length = (2 * np.pi, 1.5, 2.5)
     msh = M.Mesh(n_el, length)
