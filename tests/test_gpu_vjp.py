@@ -52,9 +52,9 @@ def test_low_degrees_fp64(k):
     assert rel_err(g, convective_vjp(u, w, k, msh, lf_factor=0.7)) < 1e-12
 
 
-@pytest.mark.parametrize("k", [2, 4, 5])
+@pytest.mark.parametrize("k", list(range(1, 8)))
 def test_low_degrees_fp32(k):
-    n_el = (3, 3, 3)
+    n_el = (3, 3, 3) if k <= 5 else (3, 2, 2)
     msh = M.Mesh(n_el, (2 * np.pi,) * 3)
     u = round_f32(inputs.uniform((3, msh.N, (k + 1) ** 3), seed=800 + k))
     w = round_f32(inputs.uniform(u.shape, seed=900 + k))
