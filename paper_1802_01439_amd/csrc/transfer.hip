@@ -27,9 +27,15 @@ namespace dgmf {
 
 namespace {
 
+// The restriction applies P transposed: with R it walks rows in memory order,
+// as the prolongation does with P.  Walking P by columns made the compiler
+// keep the whole table in scalar registers, which spilled into vector lanes
+// at n = 9..12 in FP64 (the FP64 restriction at n = 9 and 11 ran 2.2-2.6x
+// slower).
 template <int N, typename T>
 struct TransferTab {
   T P[2][N][N];   // P[c][i][a] = l_a((xi_i + c)/2)
+  T R[2][N][N];   // R[c][a][i] = P[c][i][a]
 };
 
 struct LevelArgs {
@@ -159,9 +165,9 @@ restrict_kernel(const T* __restrict__ rf, T* __restrict__ rc, LevelArgs lv,
       for (int l = 0; l < N; ++l) x[l] = g[N2 * l];
 #pragma unroll
       for (int c = 0; c < N; ++c) {
-        T s = tab->P[cz][0][c] * x[0];
+        T s = tab->R[cz][c][0] * x[0];
 #pragma unroll
-        for (int l = 1; l < N; ++l) s = fmadd(tab->P[cz][l][c], x[l], s);
+        for (int l = 1; l < N; ++l) s = fmadd(tab->R[cz][c][l], x[l], s);
         y[c] = s;
       }
       const int base = p0 + PX * p1;
@@ -176,9 +182,9 @@ restrict_kernel(const T* __restrict__ rf, T* __restrict__ rc, LevelArgs lv,
       for (int j = 0; j < N; ++j) x[j] = Ue[base + PX * j];
 #pragma unroll
       for (int b = 0; b < N; ++b) {
-        T s = tab->P[cy][0][b] * x[0];
+        T s = tab->R[cy][b][0] * x[0];
 #pragma unroll
-        for (int j = 1; j < N; ++j) s = fmadd(tab->P[cy][j][b], x[j], s);
+        for (int j = 1; j < N; ++j) s = fmadd(tab->R[cy][b][j], x[j], s);
         y[b] = s;
       }
 #pragma unroll
@@ -192,9 +198,9 @@ restrict_kernel(const T* __restrict__ rf, T* __restrict__ rc, LevelArgs lv,
       for (int i = 0; i < N; ++i) x[i] = Ue[base + i];
 #pragma unroll
       for (int a = 0; a < N; ++a) {
-        T s = tab->P[cx][0][a] * x[0];
+        T s = tab->R[cx][a][0] * x[0];
 #pragma unroll
-        for (int i = 1; i < N; ++i) s = fmadd(tab->P[cx][i][a], x[i], s);
+        for (int i = 1; i < N; ++i) s = fmadd(tab->R[cx][a][i], x[i], s);
         acc[a] += s;
       }
     }
@@ -213,7 +219,7 @@ hipError_t launch_n(const TransferPlan& P, bool prolong, const void* src, void* 
   TransferTab<N, T> t;
   for (int c = 0; c < 2; ++c)
     for (int i = 0; i < N; ++i)
-      for (int a = 0; a < N; ++a) t.P[c][i][a] = (T)P.P[c][i * N + a];
+      for (int a = 0; a < N; ++a) t.R[c][a][i] = t.P[c][i][a] = (T)P.P[c][i * N + a];
   hipError_t err;
   const TransferTab<N, T>* dt = device_table_of("transfer", t, &err);
   if (!dt) return err;
