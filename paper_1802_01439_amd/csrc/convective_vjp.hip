@@ -634,9 +634,13 @@ struct VjpShapeC {
   static constexpr int E0 = (56 * 1024) / BYTES;
   static constexpr int E = E0 < 1 ? 1 : (E0 > 8 ? 8 : E0);
   // one workgroup per CU (more than 80 KB): at most one wave per SIMD, which
-  // then has the whole register file
+  // then has the whole register file.  With the late x faces (FP64 k = 11)
+  // the registers spill either way, and 512 threads (one z pencil each, two
+  // wavefronts per SIMD) measured 5.5 % faster than 256.
   static constexpr int TH0 = (E * ITEMS + 63) / 64 * 64;
-  static constexpr int TH = E * BYTES > 80 * 1024 ? (TH0 > 256 ? 256 : TH0) : (TH0 > 512 ? 512 : TH0);
+  static constexpr int TH = FXL                    ? 512
+                            : E * BYTES > 80 * 1024 ? (TH0 > 256 ? 256 : TH0)
+                                                    : (TH0 > 512 ? 512 : TH0);
   static constexpr bool FITS = E * BYTES <= 160 * 1024;
   static_assert(6 * N2 <= 8 * LAYER, "x-face results must fit in half of FX");
   static_assert(!FXL || 24 * LAYER + 6 * N2 <= (SLOTS - 3 * N) * COLS, "late x faces must fit in the free slots");
