@@ -22,6 +22,8 @@ std::mutex g_basis_mutex;
 std::map<std::pair<int, int>, Basis1D> g_basis;
 std::mutex g_table_mutex;
 std::map<std::pair<int, std::string>, void*> g_tables;
+std::mutex g_child_mutex;
+std::map<int, std::vector<double>> g_child;   // key 2k + c: child_interp(k, c)
 }  // namespace
 
 const void* device_table(const std::string& key, const void* host, size_t bytes, hipError_t* err) {
@@ -479,8 +481,14 @@ static int transfer(const dg_op_desc* coarse, dg_dtype dtype, bool prolong, cons
   P.nyc = coarse->n_el[1];
   P.nzc = coarse->n_el[2];
   P.n_comp = coarse->n_comp;
-  P.P[0] = child_interp(P.k, 0);
-  P.P[1] = child_interp(P.k, 1);
+  {
+    std::lock_guard<std::mutex> lock(g_child_mutex);
+    for (int c = 0; c < 2; ++c) {
+      auto it = g_child.find(2 * P.k + c);
+      if (it == g_child.end()) it = g_child.emplace(2 * P.k + c, child_interp(P.k, c)).first;
+      P.P[c] = it->second;
+    }
+  }
   hipError_t e = launch_transfer(P, prolong, dtype == DG_F32, src, dst, (hipStream_t)hip_stream);
   if (e != hipSuccess) return hip_fail(e, prolong ? "prolongation kernel launch" : "restriction kernel launch");
   return ok();

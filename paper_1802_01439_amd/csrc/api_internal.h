@@ -1,6 +1,7 @@
 // Helpers shared by the C ABI translation units.
 #pragma once
 
+#include <cstring>
 #include <string>
 #include <vector>
 
@@ -50,12 +51,22 @@ namespace dgmf {
 // Kernels read it with uniform addresses through the scalar cache.
 const void* device_table(const std::string& key, const void* host, size_t bytes, hipError_t* err);
 
-// Content-addressed variant: the key is the table's own FNV-1a hash.
+// Content-addressed variant: the key is a 64-bit hash of the table's bytes
+// (FNV-1a steps over 8-byte words, each followed by a shift-xor so that high
+// bits reach the low ones; a byte-wise pass took microseconds per call for
+// the tables of the high degrees).
 template <typename Tab>
 const Tab* device_table_of(const char* kind, const Tab& host, hipError_t* err) {
   unsigned long long h = 1469598103934665603ULL;
   const unsigned char* p = reinterpret_cast<const unsigned char*>(&host);
-  for (size_t i = 0; i < sizeof(Tab); ++i) h = (h ^ p[i]) * 1099511628211ULL;
+  size_t i = 0;
+  for (; i + 8 <= sizeof(Tab); i += 8) {
+    unsigned long long w;
+    std::memcpy(&w, p + i, 8);
+    h = (h ^ w) * 1099511628211ULL;
+    h ^= h >> 29;
+  }
+  for (; i < sizeof(Tab); ++i) h = (h ^ p[i]) * 1099511628211ULL;
   return static_cast<const Tab*>(device_table(std::string(kind) + ":" + std::to_string(h), &host, sizeof(Tab), err));
 }
 

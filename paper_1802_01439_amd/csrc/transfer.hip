@@ -14,7 +14,11 @@
 // matrices are uniform (scalar loads).  Prolongation: the parent's column is
 // read once into registers; per child the z sweep runs on it, the y and x
 // sweeps on LDS pencils in place, and the child's z columns are stored
-// (3 barriers per child).  Restriction: per child a z sweep from the child's
+// (3 barriers per child).  Where that launch would have fewer than 1024
+// workgroups (about four per CU: the coarse levels of a V-cycle, the high
+// degrees) the eight children of a batch go to eight workgroups instead,
+// which shortens each workgroup's chain of barriers eightfold; the parent's
+// column is then read by each of them (from L2: they run on one XCD).  Restriction: per child a z sweep from the child's
 // column, a y sweep in LDS, and an x sweep whose result each thread
 // accumulates in registers for its own x pencil of the coarse element
 // (3 barriers per child).
@@ -43,7 +47,7 @@ struct LevelArgs {
   long long ncoarse;   // nxc * nyc * nzc
 };
 
-template <int N, typename T>
+template <int N, typename T, bool CP>
 __global__ void __launch_bounds__(LapCfgB<N>::THREADS)
 prolongate_kernel(const T* __restrict__ uc, T* __restrict__ uf, LevelArgs lv,
                   const TransferTab<N, T>* __restrict__ tab) {
@@ -53,7 +57,11 @@ prolongate_kernel(const T* __restrict__ uc, T* __restrict__ uf, LevelArgs lv,
   const int tid = threadIdx.x;
   const int le = tid / N2, p = tid - le * N2;
   const int p0 = p % N, p1 = p / N;
-  const long long e = (long long)xcd_remap(blockIdx.x, gridDim.x) * E + le;
+  // CP: one child per workgroup, logical id = batch * 8 + child, so that
+  // the eight children of a batch run on one XCD
+  const int lid = xcd_remap(blockIdx.x, gridDim.x);
+  const int ch0 = CP ? (lid & 7) : 0, ch1 = CP ? ch0 + 1 : 8;
+  const long long e = (long long)(CP ? lid >> 3 : lid) * E + le;
   const bool active = e < lv.ncoarse;
   const int comp = blockIdx.y;
   const long long nfine = 8 * lv.ncoarse;
@@ -71,7 +79,7 @@ prolongate_kernel(const T* __restrict__ uc, T* __restrict__ uf, LevelArgs lv,
     for (int c = 0; c < N; ++c) xp[c] = g[N2 * c];
   }
   T* Ue = U + le * ES;
-  for (int ch = 0; ch < 8; ++ch) {
+  for (int ch = ch0; ch < ch1; ++ch) {
     const int cx = ch & 1, cy = (ch >> 1) & 1, cz = ch >> 2;
     // z: P_cz on the parent column in registers.  The previous child's store
     // read only this thread's own column, so no barrier is needed before it.
@@ -226,11 +234,17 @@ hipError_t launch_n(const TransferPlan& P, bool prolong, const void* src, void* 
   LevelArgs lv{P.nxc, P.nyc, P.nzc, (long long)P.nxc * P.nyc * P.nzc};
   using C = LapCfgB<N>;
   const long long grid = (lv.ncoarse + C::E - 1) / C::E;
-  if (grid > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+  if (8 * grid > 0x7fffffffLL) return hipErrorInvalidConfiguration;
   if (grid == 0) return hipSuccess;
   const dim3 g((unsigned)grid, (unsigned)P.n_comp);
-  if (prolong)
-    hipLaunchKernelGGL((prolongate_kernel<N, T>), g, dim3(C::THREADS), 0, s, (const T*)src, (T*)dst, lv, dt);
+  // one child per workgroup below 1024 workgroups (measured: the V-cycle
+  // BDF2 step at k = 7, 24^3 1.5 % faster, the prolongation at k = 8, 10, 11
+  // on the sweep meshes 3-22 %; on larger grids the loop is 0-60 % faster)
+  if (prolong && grid * P.n_comp < 1024)
+    hipLaunchKernelGGL((prolongate_kernel<N, T, true>), dim3((unsigned)(8 * grid), (unsigned)P.n_comp),
+                       dim3(C::THREADS), 0, s, (const T*)src, (T*)dst, lv, dt);
+  else if (prolong)
+    hipLaunchKernelGGL((prolongate_kernel<N, T, false>), g, dim3(C::THREADS), 0, s, (const T*)src, (T*)dst, lv, dt);
   else
     hipLaunchKernelGGL((restrict_kernel<N, T>), g, dim3(C::THREADS), 0, s, (const T*)src, (T*)dst, lv, dt);
   return hipGetLastError();
