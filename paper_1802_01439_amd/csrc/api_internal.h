@@ -51,10 +51,10 @@ namespace dgmf {
 // Kernels read it with uniform addresses through the scalar cache.
 const void* device_table(const std::string& key, const void* host, size_t bytes, hipError_t* err);
 
-// Content-addressed variant: the key is a 64-bit hash of the table's bytes
-// (FNV-1a steps over 8-byte words, each followed by a shift-xor so that high
-// bits reach the low ones; a byte-wise pass took microseconds per call for
-// the tables of the high degrees).
+// Content-addressed variant: the key is the table's size and a 64-bit hash
+// of its bytes (FNV-1a steps over 8-byte words, each followed by a
+// shift-xor so that high bits reach the low ones; a byte-wise pass took
+// microseconds per call for the tables of the high degrees).
 template <typename Tab>
 const Tab* device_table_of(const char* kind, const Tab& host, hipError_t* err) {
   unsigned long long h = 1469598103934665603ULL;
@@ -67,7 +67,8 @@ const Tab* device_table_of(const char* kind, const Tab& host, hipError_t* err) {
     h ^= h >> 29;
   }
   for (; i < sizeof(Tab); ++i) h = (h ^ p[i]) * 1099511628211ULL;
-  return static_cast<const Tab*>(device_table(std::string(kind) + ":" + std::to_string(h), &host, sizeof(Tab), err));
+  const std::string key = std::string(kind) + ":" + std::to_string(sizeof(Tab)) + ":" + std::to_string(h);
+  return static_cast<const Tab*>(device_table(key, &host, sizeof(Tab), err));
 }
 
 }  // namespace dgmf
