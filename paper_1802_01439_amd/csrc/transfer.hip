@@ -73,7 +73,7 @@ prolongate_kernel(const T* __restrict__ uc, T* __restrict__ uf, LevelArgs lv,
     const long long r = e - (long long)ez * lv.nxc * lv.nyc;
     ey = (int)(r / lv.nxc);
     ex = (int)(r - (long long)ey * lv.nxc);
-    // the parent's column (a, b) = (p0, p1), read once for all eight children
+    // the parent's column (a, b) = (p0, p1), read once for this workgroup's children
     const T* g = uc + (size_t)comp * lv.ncoarse * N3 + (size_t)e * N3 + p0 + N * p1;
 #pragma unroll
     for (int c = 0; c < N; ++c) xp[c] = g[N2 * c];
