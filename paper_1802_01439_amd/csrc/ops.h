@@ -82,6 +82,8 @@ struct TransferPlan {
 };
 hipError_t launch_transfer(const TransferPlan& P, bool prolong, bool f32, const void* src, void* dst,
                            hipStream_t s);
+// dst += the prolongation of src (a V-cycle's coarse-grid correction)
+hipError_t launch_prolongate_add(const TransferPlan& P, bool f32, const void* src, void* dst, hipStream_t s);
 
 // pressure gradient: the divergence's 1D tables, G = -B^T
 hipError_t launch_gradient(const DivPlan& P, bool f32, const void* p, void* y, hipStream_t s);

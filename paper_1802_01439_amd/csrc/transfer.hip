@@ -47,7 +47,9 @@ struct LevelArgs {
   long long ncoarse;   // nxc * nyc * nzc
 };
 
-template <int N, typename T, bool CP>
+// ACC: uf += the prolongation (the coarse-grid correction of a V-cycle)
+// instead of uf = it.
+template <int N, typename T, bool CP, bool ACC>
 __global__ void __launch_bounds__(LapCfgB<N>::THREADS)
 prolongate_kernel(const T* __restrict__ uc, T* __restrict__ uf, LevelArgs lv,
                   const TransferTab<N, T>* __restrict__ tab) {
@@ -132,7 +134,10 @@ prolongate_kernel(const T* __restrict__ uc, T* __restrict__ uf, LevelArgs lv,
       T* g = uf + (size_t)comp * nfine * N3 + (size_t)f * N3 + p0 + N * p1;
       const int base = p0 + PX * p1;
 #pragma unroll
-      for (int l = 0; l < N; ++l) g[N2 * l] = Ue[base + PY * l];
+      for (int l = 0; l < N; ++l) {
+        if constexpr (ACC) g[N2 * l] += Ue[base + PY * l];
+        else g[N2 * l] = Ue[base + PY * l];
+      }
     }
   }
 }
@@ -222,8 +227,24 @@ restrict_kernel(const T* __restrict__ rf, T* __restrict__ rc, LevelArgs lv,
   }
 }
 
+template <int N, typename T, bool ACC>
+hipError_t launch_prolong(const TransferPlan& P, const void* src, void* dst, long long grid, const TransferTab<N, T>* dt,
+                          LevelArgs lv, hipStream_t s) {
+  using C = LapCfgB<N>;
+  // one child per workgroup below 1024 workgroups (measured: the V-cycle
+  // BDF2 step at k = 7, 24^3 1.5 % faster, the prolongation at k = 8, 10, 11
+  // on the sweep meshes 3-22 %; on larger grids the loop is 0-60 % faster)
+  if (grid * P.n_comp < 1024)
+    hipLaunchKernelGGL((prolongate_kernel<N, T, true, ACC>), dim3((unsigned)(8 * grid), (unsigned)P.n_comp),
+                       dim3(C::THREADS), 0, s, (const T*)src, (T*)dst, lv, dt);
+  else
+    hipLaunchKernelGGL((prolongate_kernel<N, T, false, ACC>), dim3((unsigned)grid, (unsigned)P.n_comp),
+                       dim3(C::THREADS), 0, s, (const T*)src, (T*)dst, lv, dt);
+  return hipGetLastError();
+}
+
 template <int N, typename T>
-hipError_t launch_n(const TransferPlan& P, bool prolong, const void* src, void* dst, hipStream_t s) {
+hipError_t launch_n(const TransferPlan& P, int mode, const void* src, void* dst, hipStream_t s) {
   TransferTab<N, T> t;
   for (int c = 0; c < 2; ++c)
     for (int i = 0; i < N; ++i)
@@ -236,34 +257,28 @@ hipError_t launch_n(const TransferPlan& P, bool prolong, const void* src, void* 
   const long long grid = (lv.ncoarse + C::E - 1) / C::E;
   if (8 * grid > 0x7fffffffLL) return hipErrorInvalidConfiguration;
   if (grid == 0) return hipSuccess;
-  const dim3 g((unsigned)grid, (unsigned)P.n_comp);
-  // one child per workgroup below 1024 workgroups (measured: the V-cycle
-  // BDF2 step at k = 7, 24^3 1.5 % faster, the prolongation at k = 8, 10, 11
-  // on the sweep meshes 3-22 %; on larger grids the loop is 0-60 % faster)
-  if (prolong && grid * P.n_comp < 1024)
-    hipLaunchKernelGGL((prolongate_kernel<N, T, true>), dim3((unsigned)(8 * grid), (unsigned)P.n_comp),
-                       dim3(C::THREADS), 0, s, (const T*)src, (T*)dst, lv, dt);
-  else if (prolong)
-    hipLaunchKernelGGL((prolongate_kernel<N, T, false>), g, dim3(C::THREADS), 0, s, (const T*)src, (T*)dst, lv, dt);
-  else
-    hipLaunchKernelGGL((restrict_kernel<N, T>), g, dim3(C::THREADS), 0, s, (const T*)src, (T*)dst, lv, dt);
+  if (mode == 1) return launch_prolong<N, T, false>(P, src, dst, grid, dt, lv, s);
+  if (mode == 2) return launch_prolong<N, T, true>(P, src, dst, grid, dt, lv, s);
+  hipLaunchKernelGGL((restrict_kernel<N, T>), dim3((unsigned)grid, (unsigned)P.n_comp), dim3(C::THREADS), 0, s,
+                     (const T*)src, (T*)dst, lv, dt);
   return hipGetLastError();
 }
 
+// mode 0: restriction, 1: prolongation, 2: prolongation added to dst
 template <typename T>
-hipError_t launch_t(const TransferPlan& P, bool prolong, const void* src, void* dst, hipStream_t s) {
+hipError_t launch_t(const TransferPlan& P, int mode, const void* src, void* dst, hipStream_t s) {
   switch (P.k) {
-    case 1: return launch_n<2, T>(P, prolong, src, dst, s);
-    case 2: return launch_n<3, T>(P, prolong, src, dst, s);
-    case 3: return launch_n<4, T>(P, prolong, src, dst, s);
-    case 4: return launch_n<5, T>(P, prolong, src, dst, s);
-    case 5: return launch_n<6, T>(P, prolong, src, dst, s);
-    case 6: return launch_n<7, T>(P, prolong, src, dst, s);
-    case 7: return launch_n<8, T>(P, prolong, src, dst, s);
-    case 8: return launch_n<9, T>(P, prolong, src, dst, s);
-    case 9: return launch_n<10, T>(P, prolong, src, dst, s);
-    case 10: return launch_n<11, T>(P, prolong, src, dst, s);
-    case 11: return launch_n<12, T>(P, prolong, src, dst, s);
+    case 1: return launch_n<2, T>(P, mode, src, dst, s);
+    case 2: return launch_n<3, T>(P, mode, src, dst, s);
+    case 3: return launch_n<4, T>(P, mode, src, dst, s);
+    case 4: return launch_n<5, T>(P, mode, src, dst, s);
+    case 5: return launch_n<6, T>(P, mode, src, dst, s);
+    case 6: return launch_n<7, T>(P, mode, src, dst, s);
+    case 7: return launch_n<8, T>(P, mode, src, dst, s);
+    case 8: return launch_n<9, T>(P, mode, src, dst, s);
+    case 9: return launch_n<10, T>(P, mode, src, dst, s);
+    case 10: return launch_n<11, T>(P, mode, src, dst, s);
+    case 11: return launch_n<12, T>(P, mode, src, dst, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -272,7 +287,12 @@ hipError_t launch_t(const TransferPlan& P, bool prolong, const void* src, void* 
 
 hipError_t launch_transfer(const TransferPlan& P, bool prolong, bool f32, const void* src, void* dst,
                            hipStream_t s) {
-  return f32 ? launch_t<float>(P, prolong, src, dst, s) : launch_t<double>(P, prolong, src, dst, s);
+  const int mode = prolong ? 1 : 0;
+  return f32 ? launch_t<float>(P, mode, src, dst, s) : launch_t<double>(P, mode, src, dst, s);
+}
+
+hipError_t launch_prolongate_add(const TransferPlan& P, bool f32, const void* src, void* dst, hipStream_t s) {
+  return f32 ? launch_t<float>(P, 2, src, dst, s) : launch_t<double>(P, 2, src, dst, s);
 }
 
 }  // namespace dgmf

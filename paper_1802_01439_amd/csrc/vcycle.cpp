@@ -164,8 +164,7 @@ struct MgRun {
     const TransferPlan TP = transfer_plan(l + 1);
     if ((e = launch_transfer(TP, false, F32, L.res, lv[l + 1].b, s)) != hipSuccess) return e;
     if ((e = cycle(l + 1)) != hipSuccess) return e;
-    if ((e = launch_transfer(TP, true, F32, lv[l + 1].x, L.t, s)) != hipSuccess) return e;
-    if ((e = mg_add(L.x, L.t, L.n, s)) != hipSuccess) return e;
+    if ((e = launch_prolongate_add(TP, F32, lv[l + 1].x, L.x, s)) != hipSuccess) return e;
     if ((e = mg_apply_residual<T>(L.plan, L.x, L.b, L.res, s)) != hipSuccess) return e;
     ++applies;
     if ((e = cheb(L, L.res, L.e, degree)) != hipSuccess) return e;
