@@ -84,6 +84,11 @@ hipError_t launch_transfer(const TransferPlan& P, bool prolong, bool f32, const 
                            hipStream_t s);
 // dst += the prolongation of src (a V-cycle's coarse-grid correction)
 hipError_t launch_prolongate_add(const TransferPlan& P, bool f32, const void* src, void* dst, hipStream_t s);
+// rc = the restriction of rf (one component) and the first step of a
+// zero-start Chebyshev smoother on it: d = x = scale * dinv[node] * rc, with
+// scale rounded to the transfer's precision
+hipError_t launch_restrict_cheb_first(const TransferPlan& P, bool f32, const void* rf, void* rc, const void* dinv,
+                                      double scale, void* d, void* x, hipStream_t s);
 
 // pressure gradient: the divergence's 1D tables, G = -B^T
 hipError_t launch_gradient(const DivPlan& P, bool f32, const void* p, void* y, hipStream_t s);

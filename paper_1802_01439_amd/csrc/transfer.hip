@@ -142,10 +142,20 @@ prolongate_kernel(const T* __restrict__ uc, T* __restrict__ uf, LevelArgs lv,
   }
 }
 
-template <int N, typename T>
+// First step of a zero-start Chebyshev smoother on the coarse level, taken
+// in the restriction's store: d = x = s D^-1 r_c (one component).
+template <typename T>
+struct ChebFirst {
+  const T* dinv;   // D^-1 at the n^3 nodes, the same in every element
+  T s;             // 1 / theta
+  T* d;
+  T* x;
+};
+
+template <int N, typename T, bool CF>
 __global__ void __launch_bounds__(LapCfgB<N>::THREADS)
 restrict_kernel(const T* __restrict__ rf, T* __restrict__ rc, LevelArgs lv,
-                const TransferTab<N, T>* __restrict__ tab) {
+                const TransferTab<N, T>* __restrict__ tab, ChebFirst<T> cf) {
   using C = LapCfgB<N>;
   constexpr int N2 = N * N, N3 = N * N * N, E = C::E, ES = C::ES, PX = C::PX, PY = C::PY;
   __shared__ T U[E * ES];
@@ -221,9 +231,16 @@ restrict_kernel(const T* __restrict__ rf, T* __restrict__ rc, LevelArgs lv,
   }
   // store the coarse x pencil (b, c) = (p0, p1)
   if (active) {
-    T* g = rc + (size_t)comp * lv.ncoarse * N3 + (size_t)e * N3 + N * p0 + N2 * p1;
+    const size_t o = (size_t)comp * lv.ncoarse * N3 + (size_t)e * N3 + N * p0 + N2 * p1;
 #pragma unroll
-    for (int a = 0; a < N; ++a) g[a] = acc[a];
+    for (int a = 0; a < N; ++a) {
+      rc[o + a] = acc[a];
+      if constexpr (CF) {
+        const T v = cf.s * cf.dinv[N * p0 + N2 * p1 + a] * acc[a];
+        cf.d[o + a] = v;
+        cf.x[o + a] = v;
+      }
+    }
   }
 }
 
@@ -243,8 +260,16 @@ hipError_t launch_prolong(const TransferPlan& P, const void* src, void* dst, lon
   return hipGetLastError();
 }
 
+struct ChebFirstArgs {
+  const void* dinv;
+  double s;
+  void* d;
+  void* x;
+};
+
 template <int N, typename T>
-hipError_t launch_n(const TransferPlan& P, int mode, const void* src, void* dst, hipStream_t s) {
+hipError_t launch_n(const TransferPlan& P, int mode, const void* src, void* dst, const ChebFirstArgs* cfa,
+                    hipStream_t s) {
   TransferTab<N, T> t;
   for (int c = 0; c < 2; ++c)
     for (int i = 0; i < N; ++i)
@@ -259,26 +284,35 @@ hipError_t launch_n(const TransferPlan& P, int mode, const void* src, void* dst,
   if (grid == 0) return hipSuccess;
   if (mode == 1) return launch_prolong<N, T, false>(P, src, dst, grid, dt, lv, s);
   if (mode == 2) return launch_prolong<N, T, true>(P, src, dst, grid, dt, lv, s);
-  hipLaunchKernelGGL((restrict_kernel<N, T>), dim3((unsigned)grid, (unsigned)P.n_comp), dim3(C::THREADS), 0, s,
-                     (const T*)src, (T*)dst, lv, dt);
+  const dim3 g((unsigned)grid, (unsigned)P.n_comp);
+  if (mode == 3) {
+    if (P.n_comp != 1 || !cfa) return hipErrorInvalidValue;
+    const ChebFirst<T> cf{(const T*)cfa->dinv, (T)cfa->s, (T*)cfa->d, (T*)cfa->x};
+    hipLaunchKernelGGL((restrict_kernel<N, T, true>), g, dim3(C::THREADS), 0, s, (const T*)src, (T*)dst, lv, dt, cf);
+  } else {
+    hipLaunchKernelGGL((restrict_kernel<N, T, false>), g, dim3(C::THREADS), 0, s, (const T*)src, (T*)dst, lv, dt,
+                       ChebFirst<T>{});
+  }
   return hipGetLastError();
 }
 
-// mode 0: restriction, 1: prolongation, 2: prolongation added to dst
+// mode 0: restriction, 1: prolongation, 2: prolongation added to dst,
+// 3: restriction and the first Chebyshev step on the coarse level
 template <typename T>
-hipError_t launch_t(const TransferPlan& P, int mode, const void* src, void* dst, hipStream_t s) {
+hipError_t launch_t(const TransferPlan& P, int mode, const void* src, void* dst, const ChebFirstArgs* cf,
+                    hipStream_t s) {
   switch (P.k) {
-    case 1: return launch_n<2, T>(P, mode, src, dst, s);
-    case 2: return launch_n<3, T>(P, mode, src, dst, s);
-    case 3: return launch_n<4, T>(P, mode, src, dst, s);
-    case 4: return launch_n<5, T>(P, mode, src, dst, s);
-    case 5: return launch_n<6, T>(P, mode, src, dst, s);
-    case 6: return launch_n<7, T>(P, mode, src, dst, s);
-    case 7: return launch_n<8, T>(P, mode, src, dst, s);
-    case 8: return launch_n<9, T>(P, mode, src, dst, s);
-    case 9: return launch_n<10, T>(P, mode, src, dst, s);
-    case 10: return launch_n<11, T>(P, mode, src, dst, s);
-    case 11: return launch_n<12, T>(P, mode, src, dst, s);
+    case 1: return launch_n<2, T>(P, mode, src, dst, cf, s);
+    case 2: return launch_n<3, T>(P, mode, src, dst, cf, s);
+    case 3: return launch_n<4, T>(P, mode, src, dst, cf, s);
+    case 4: return launch_n<5, T>(P, mode, src, dst, cf, s);
+    case 5: return launch_n<6, T>(P, mode, src, dst, cf, s);
+    case 6: return launch_n<7, T>(P, mode, src, dst, cf, s);
+    case 7: return launch_n<8, T>(P, mode, src, dst, cf, s);
+    case 8: return launch_n<9, T>(P, mode, src, dst, cf, s);
+    case 9: return launch_n<10, T>(P, mode, src, dst, cf, s);
+    case 10: return launch_n<11, T>(P, mode, src, dst, cf, s);
+    case 11: return launch_n<12, T>(P, mode, src, dst, cf, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -288,11 +322,17 @@ hipError_t launch_t(const TransferPlan& P, int mode, const void* src, void* dst,
 hipError_t launch_transfer(const TransferPlan& P, bool prolong, bool f32, const void* src, void* dst,
                            hipStream_t s) {
   const int mode = prolong ? 1 : 0;
-  return f32 ? launch_t<float>(P, mode, src, dst, s) : launch_t<double>(P, mode, src, dst, s);
+  return f32 ? launch_t<float>(P, mode, src, dst, nullptr, s) : launch_t<double>(P, mode, src, dst, nullptr, s);
 }
 
 hipError_t launch_prolongate_add(const TransferPlan& P, bool f32, const void* src, void* dst, hipStream_t s) {
-  return f32 ? launch_t<float>(P, 2, src, dst, s) : launch_t<double>(P, 2, src, dst, s);
+  return f32 ? launch_t<float>(P, 2, src, dst, nullptr, s) : launch_t<double>(P, 2, src, dst, nullptr, s);
+}
+
+hipError_t launch_restrict_cheb_first(const TransferPlan& P, bool f32, const void* rf, void* rc, const void* dinv,
+                                      double scale, void* d, void* x, hipStream_t s) {
+  const ChebFirstArgs cf{dinv, scale, d, x};
+  return f32 ? launch_t<float>(P, 3, rf, rc, &cf, s) : launch_t<double>(P, 3, rf, rc, &cf, s);
 }
 
 }  // namespace dgmf

@@ -106,12 +106,17 @@ struct MgRun {
     return e;
   }
 
-  // x = Cheb(b) on level l (deg steps, deg - 1 operator applications)
-  hipError_t cheb(MgLevel<T>& L, const T* b, T* x, int deg) {
+  // 1 / theta of level l's Chebyshev interval [lmax / range, lmax]
+  double cheb_scale(const MgLevel<T>& L) const { return 1.0 / (0.5 * (L.lmax + L.lmax / range)); }
+
+  // x = Cheb(b) on level l (deg steps, deg - 1 operator applications);
+  // first_done: the first step (d = x = D^-1 b / theta) was taken by the
+  // restriction that produced b
+  hipError_t cheb(MgLevel<T>& L, const T* b, T* x, int deg, bool first_done = false) {
     const double lmin = L.lmax / range;
     const double theta = 0.5 * (L.lmax + lmin), delta = 0.5 * (L.lmax - lmin);
     hipError_t e;
-    if ((e = mg_cheb_first(b, L.dinv, n3, (T)(1.0 / theta), L.d, x, L.n, s)) != hipSuccess) return e;
+    if (!first_done && (e = mg_cheb_first(b, L.dinv, n3, (T)cheb_scale(L), L.d, x, L.n, s)) != hipSuccess) return e;
     double rho_prev = delta / theta;
     int step = 1;
     if ((deg - 1) % 2 == 1) {
@@ -152,18 +157,21 @@ struct MgRun {
     return TP;
   }
 
-  // lv[l].x = cycle(l, lv[l].b)
-  hipError_t cycle(int l) {
+  // lv[l].x = cycle(l, lv[l].b); first_done: see cheb
+  hipError_t cycle(int l, bool first_done = false) {
     MgLevel<T>& L = lv[l];
     hipError_t e;
     const bool last = l + 1 == (int)lv.size();
-    if ((e = cheb(L, L.b, L.x, last ? coarse_degree : degree)) != hipSuccess) return e;
+    if ((e = cheb(L, L.b, L.x, last ? coarse_degree : degree, first_done)) != hipSuccess) return e;
     if (last) return hipSuccess;
     if ((e = mg_apply_residual<T>(L.plan, L.x, L.b, L.res, s)) != hipSuccess) return e;
     ++applies;
     const TransferPlan TP = transfer_plan(l + 1);
-    if ((e = launch_transfer(TP, false, F32, L.res, lv[l + 1].b, s)) != hipSuccess) return e;
-    if ((e = cycle(l + 1)) != hipSuccess) return e;
+    MgLevel<T>& Lc = lv[l + 1];
+    if ((e = launch_restrict_cheb_first(TP, F32, L.res, Lc.b, Lc.dinv, (double)(T)cheb_scale(Lc), Lc.d, Lc.x, s)) !=
+        hipSuccess)
+      return e;
+    if ((e = cycle(l + 1, true)) != hipSuccess) return e;
     if ((e = launch_prolongate_add(TP, F32, lv[l + 1].x, L.x, s)) != hipSuccess) return e;
     if ((e = mg_apply_residual<T>(L.plan, L.x, L.b, L.res, s)) != hipSuccess) return e;
     ++applies;
