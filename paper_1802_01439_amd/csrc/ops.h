@@ -40,6 +40,11 @@ hipError_t mg_apply_cheb(const LaplacePlan& P, const T* x, const T* b, const T* 
                          hipStream_t s);
 template <typename T>
 hipError_t mg_apply_residual(const LaplacePlan& P, const T* x, const T* b, T* res, hipStream_t s);
+// res = b - A x and the first step of a zero-start Chebyshev smoother on it,
+// d = e = scale * dinv[node] * res
+template <typename T>
+hipError_t mg_apply_residual_cheb_first(const LaplacePlan& P, const T* x, const T* b, const T* dinv, T scale, T* res,
+                                        T* d, T* e, hipStream_t s);
 
 // Convective form and its VJP: 1D tables on [0,1] and the cell/face scalings.
 struct ConvPlan {

@@ -173,9 +173,11 @@ struct MgRun {
       return e;
     if ((e = cycle(l + 1, true)) != hipSuccess) return e;
     if ((e = launch_prolongate_add(TP, F32, lv[l + 1].x, L.x, s)) != hipSuccess) return e;
-    if ((e = mg_apply_residual<T>(L.plan, L.x, L.b, L.res, s)) != hipSuccess) return e;
+    if ((e = mg_apply_residual_cheb_first<T>(L.plan, L.x, L.b, L.dinv, (T)cheb_scale(L), L.res, L.d, L.e, s)) !=
+        hipSuccess)
+      return e;
     ++applies;
-    if ((e = cheb(L, L.res, L.e, degree)) != hipSuccess) return e;
+    if ((e = cheb(L, L.res, L.e, degree, true)) != hipSuccess) return e;
     return mg_add(L.x, L.e, L.n, s);
   }
 };

@@ -2,6 +2,8 @@
 // (Sec. 3.3, the V-cycle's Chebyshev smoother), FP64 and FP32:
 //   Chebyshev step  d <- c1 d + c2 D^-1 (b - A x),  x' = x + d
 //   residual        res = b - A x
+//   residual and the first step of a zero-start Chebyshev smoother on it
+//                   res = b - A x,  d = e = s D^-1 res
 // The operand x is read for neighbour DoFs by other workgroups, so the new
 // iterate goes to a second buffer x'; d is read and written only by the
 // thread that owns each DoF, in place.  D^-1 is one element's diagonal
@@ -44,6 +46,28 @@ struct MgResIO {
   __device__ __forceinline__ void finish(void*) {}
 };
 
+template <typename T>
+struct MgResChebIO {
+  const T* __restrict__ x;
+  const T* __restrict__ b;
+  const T* __restrict__ dinv;
+  T* __restrict__ res;
+  T* __restrict__ d;
+  T* __restrict__ e;
+  T s;
+  __device__ __forceinline__ void begin() {}
+  __device__ __forceinline__ T load(size_t i, int) const { return x[i]; }
+  __device__ __forceinline__ void store(size_t i, int loc, T, T out) {
+    const T r = b[i] - out;
+    res[i] = r;
+    const T v = s * dinv[loc] * r;
+    d[i] = v;
+    e[i] = v;
+  }
+  template <int THREADS, size_t BYTES>
+  __device__ __forceinline__ void finish(void*) {}
+};
+
 template <typename T, typename IO>
 hipError_t dispatch(const LaplacePlan& P, const IO& io, hipStream_t s) {
   switch (P.k) {
@@ -77,11 +101,23 @@ hipError_t mg_apply_residual(const LaplacePlan& P, const T* x, const T* b, T* re
   return dispatch<T>(P, io, s);
 }
 
+template <typename T>
+hipError_t mg_apply_residual_cheb_first(const LaplacePlan& P, const T* x, const T* b, const T* dinv, T scale, T* res,
+                                        T* d, T* e, hipStream_t s) {
+  MgResChebIO<T> io{x, b, dinv, res, d, e, scale};
+  return dispatch<T>(P, io, s);
+}
+
 template hipError_t mg_apply_cheb<double>(const LaplacePlan&, const double*, const double*, const double*, double,
                                           double, double*, double*, hipStream_t);
 template hipError_t mg_apply_cheb<float>(const LaplacePlan&, const float*, const float*, const float*, float, float,
                                          float*, float*, hipStream_t);
 template hipError_t mg_apply_residual<double>(const LaplacePlan&, const double*, const double*, double*, hipStream_t);
 template hipError_t mg_apply_residual<float>(const LaplacePlan&, const float*, const float*, float*, hipStream_t);
+template hipError_t mg_apply_residual_cheb_first<double>(const LaplacePlan&, const double*, const double*,
+                                                         const double*, double, double*, double*, double*,
+                                                         hipStream_t);
+template hipError_t mg_apply_residual_cheb_first<float>(const LaplacePlan&, const float*, const float*, const float*,
+                                                        float, float*, float*, float*, hipStream_t);
 
 }  // namespace dgmf
