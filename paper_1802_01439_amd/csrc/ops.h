@@ -40,6 +40,11 @@ hipError_t mg_apply_cheb(const LaplacePlan& P, const T* x, const T* b, const T* 
                          hipStream_t s);
 template <typename T>
 hipError_t mg_apply_residual(const LaplacePlan& P, const T* x, const T* b, T* res, hipStream_t s);
+// the Chebyshev step of mg_apply_cheb with its new iterate added to y
+// (y += x + d') instead of stored
+template <typename T>
+hipError_t mg_apply_cheb_add(const LaplacePlan& P, const T* x, const T* b, const T* dinv, T c1, T c2, const T* d, T* y,
+                             hipStream_t s);
 // res = b - A x and the first step of a zero-start Chebyshev smoother on it,
 // d = e = scale * dinv[node] * res
 template <typename T>

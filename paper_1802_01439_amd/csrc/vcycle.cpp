@@ -111,8 +111,11 @@ struct MgRun {
 
   // x = Cheb(b) on level l (deg steps, deg - 1 operator applications);
   // first_done: the first step (d = x = D^-1 b / theta) was taken by the
-  // restriction that produced b
-  hipError_t cheb(MgLevel<T>& L, const T* b, T* x, int deg, bool first_done = false) {
+  // kernel that produced b.  add_to: the last step, where it is a fused
+  // step, adds its iterate to add_to instead of storing it (then *added)
+  hipError_t cheb(MgLevel<T>& L, const T* b, T* x, int deg, bool first_done = false, T* add_to = nullptr,
+                  bool* added = nullptr) {
+    if (added) *added = false;
     const double lmin = L.lmax / range;
     const double theta = 0.5 * (L.lmax + lmin), delta = 0.5 * (L.lmax - lmin);
     hipError_t e;
@@ -135,6 +138,14 @@ struct MgRun {
     T *cur = x, *nxt = L.t;
     for (; step < deg; ++step) {
       const double rho = 1.0 / (2.0 * theta / delta - rho_prev);
+      if (add_to && step == deg - 1) {
+        if ((e = mg_apply_cheb_add<T>(L.plan, cur, b, L.dinv, (T)(rho * rho_prev), (T)(2.0 * rho / delta), L.d, add_to,
+                                      s)) != hipSuccess)
+          return e;
+        ++applies;
+        if (added) *added = true;
+        return hipSuccess;
+      }
       if ((e = mg_apply_cheb<T>(L.plan, cur, b, L.dinv, (T)(rho * rho_prev), (T)(2.0 * rho / delta), L.d, nxt, s)) !=
           hipSuccess)
         return e;
@@ -177,8 +188,9 @@ struct MgRun {
         hipSuccess)
       return e;
     ++applies;
-    if ((e = cheb(L, L.res, L.e, degree, true)) != hipSuccess) return e;
-    return mg_add(L.x, L.e, L.n, s);
+    bool added = false;
+    if ((e = cheb(L, L.res, L.e, degree, true, L.x, &added)) != hipSuccess) return e;
+    return added ? hipSuccess : mg_add(L.x, L.e, L.n, s);
   }
 };
 

@@ -4,6 +4,8 @@
 //   residual        res = b - A x
 //   residual and the first step of a zero-start Chebyshev smoother on it
 //                   res = b - A x,  d = e = s D^-1 res
+//   last Chebyshev step of the post-smoothing, added to the level's iterate
+//                   y += x + (c1 d + c2 D^-1 (b - A x))
 // The operand x is read for neighbour DoFs by other workgroups, so the new
 // iterate goes to a second buffer x'; d is read and written only by the
 // thread that owns each DoF, in place.  D^-1 is one element's diagonal
@@ -42,6 +44,25 @@ struct MgResIO {
   __device__ __forceinline__ void begin() {}
   __device__ __forceinline__ T load(size_t i, int) const { return x[i]; }
   __device__ __forceinline__ void store(size_t i, int, T, T out) { res[i] = b[i] - out; }
+  template <int THREADS, size_t BYTES>
+  __device__ __forceinline__ void finish(void*) {}
+};
+
+template <typename T>
+struct MgChebAddIO {
+  const T* __restrict__ x;
+  const T* __restrict__ b;
+  const T* __restrict__ dinv;
+  const T* __restrict__ d;
+  T* __restrict__ y;
+  T c1, c2;
+  __device__ __forceinline__ void begin() {}
+  __device__ __forceinline__ T load(size_t i, int) const { return x[i]; }
+  __device__ __forceinline__ void store(size_t i, int loc, T in, T out) {
+    const T v = c1 * d[i] + c2 * dinv[loc] * (b[i] - out);
+    const T xn = in + v;
+    y[i] = y[i] + xn;
+  }
   template <int THREADS, size_t BYTES>
   __device__ __forceinline__ void finish(void*) {}
 };
@@ -102,6 +123,13 @@ hipError_t mg_apply_residual(const LaplacePlan& P, const T* x, const T* b, T* re
 }
 
 template <typename T>
+hipError_t mg_apply_cheb_add(const LaplacePlan& P, const T* x, const T* b, const T* dinv, T c1, T c2, const T* d, T* y,
+                             hipStream_t s) {
+  MgChebAddIO<T> io{x, b, dinv, d, y, c1, c2};
+  return dispatch<T>(P, io, s);
+}
+
+template <typename T>
 hipError_t mg_apply_residual_cheb_first(const LaplacePlan& P, const T* x, const T* b, const T* dinv, T scale, T* res,
                                         T* d, T* e, hipStream_t s) {
   MgResChebIO<T> io{x, b, dinv, res, d, e, scale};
@@ -114,6 +142,10 @@ template hipError_t mg_apply_cheb<float>(const LaplacePlan&, const float*, const
                                          float*, float*, hipStream_t);
 template hipError_t mg_apply_residual<double>(const LaplacePlan&, const double*, const double*, double*, hipStream_t);
 template hipError_t mg_apply_residual<float>(const LaplacePlan&, const float*, const float*, float*, hipStream_t);
+template hipError_t mg_apply_cheb_add<double>(const LaplacePlan&, const double*, const double*, const double*, double,
+                                              double, const double*, double*, hipStream_t);
+template hipError_t mg_apply_cheb_add<float>(const LaplacePlan&, const float*, const float*, const float*, float, float,
+                                             const float*, float*, hipStream_t);
 template hipError_t mg_apply_residual_cheb_first<double>(const LaplacePlan&, const double*, const double*,
                                                          const double*, double, double*, double*, double*,
                                                          hipStream_t);
