@@ -35,10 +35,16 @@ int laplace_lambda_max(const dg_op_desc* d, bool project, void* hip_stream, doub
 
 // FP64 CG with one V-cycle (T = cycle precision, DG_F64 or DG_F32) per
 // iteration, stopping at |r| <= max(rtol |b - mean b|, atol); the body of
-// dg_gmg_cg_solve (which passes atol = 0).
+// dg_gmg_cg_solve (which passes atol = 0 and true_residual).  Without
+// true_residual the report's true_rel_res is NaN and the operator apply and
+// residual that form it are skipped (callers that read iteration counts).
 int gmg_cg_solve(const dg_op_desc* desc, int levels, int degree, double smoothing_range, int coarse_degree,
                  const double* lambda_max, int cycle_dtype, const double* b, double* x, double rtol, double atol,
-                 int max_iter, dg_cg_report* report, void* hip_stream);
+                 int max_iter, dg_cg_report* report, void* hip_stream, bool true_residual = true);
+// dg_mass_pcg_solve with the same true_residual switch
+int mass_pcg_solve(const dg_op_desc* desc, int32_t op, double mass_factor, const double* tau_d, const double* tau_c,
+                   const double* b, double* x, double rtol, int32_t max_iter, dg_cg_report* report,
+                   void* hip_stream, bool true_residual);
 int default_conv_nq(int k);
 int make_conv_plan(const dg_op_desc* d, ConvPlan& P);
 

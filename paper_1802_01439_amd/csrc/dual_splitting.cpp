@@ -254,7 +254,7 @@ extern "C" int dg_dual_splitting_step(const dg_op_desc* desc, const dg_step_opts
       ++levels;
     }
     rc = gmg_cg_solve(&dp, levels, 5, 20.0, 10, nullptr, DG_F32, W.bp, p, opts->rtol_pressure, opts->atol_pressure,
-                      opts->max_iter, &cr, hip_stream);
+                      opts->max_iter, &cr, hip_stream, false);
   } else {
     dg_cg_opts co{};
     co.precond = DG_PC_CHEB_F32;
@@ -288,8 +288,8 @@ extern "C" int dg_dual_splitting_step(const dg_op_desc* desc, const dg_step_opts
   if ((e = hipMemcpyAsync(uhh, uhat, ub, hipMemcpyDeviceToDevice, s)) != hipSuccess)
     return hip_fail(e, "initial guess");
   dg_cg_report pr{};
-  rc = dg_mass_pcg_solve(&dv, DG_OP_PROJECTION, 0.0, W.tau, W.tau + nel, rhs3, uhh, opts->rtol_projection,
-                         opts->max_iter, &pr, hip_stream);
+  rc = mass_pcg_solve(&dv, DG_OP_PROJECTION, 0.0, W.tau, W.tau + nel, rhs3, uhh, opts->rtol_projection,
+                      opts->max_iter, &pr, hip_stream, false);
   if (rc) return step_fail(rc, "projection CG");
   // 4. viscous step
   if ((rc = dg_apply_helmholtz(&dm, DG_F64, g0 / dt, uhh, rhs4, s))) return rc;
@@ -298,8 +298,8 @@ extern "C" int dg_dual_splitting_step(const dg_op_desc* desc, const dg_step_opts
   dg_op_desc dvv = dv;
   dvv.scale = nu;
   dg_cg_report vr{};
-  rc = dg_mass_pcg_solve(&dvv, DG_OP_HELMHOLTZ, g0 / dt, nullptr, nullptr, rhs4, u_np1, opts->rtol_viscous,
-                         opts->max_iter, &vr, hip_stream);
+  rc = mass_pcg_solve(&dvv, DG_OP_HELMHOLTZ, g0 / dt, nullptr, nullptr, rhs4, u_np1, opts->rtol_viscous,
+                      opts->max_iter, &vr, hip_stream, false);
   if (rc) return step_fail(rc, "viscous CG");
   if (report) {
     double d2[2] = {0, 0};
