@@ -332,7 +332,7 @@ typedef struct {
  *   p: [N_el][k^3] doubles (device): in, the pressure solve's initial guess
  *   (e.g. the previous pressure); out, P^{n+1} (zero coefficient mean).
  *   u_np1 and p must not overlap each other or the inputs.
- * The library keeps seven velocity-sized work vectors per GPU.  Returns
+ * The library keeps five velocity-sized work vectors per GPU.  Returns
  * DG_OK, a negative error, or DG_NOT_CONVERGED / DG_ERR_BREAKDOWN of the
  * solve that failed (u_np1 then does not hold the step's result).  Blocks.
  */

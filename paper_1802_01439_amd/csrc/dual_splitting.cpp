@@ -35,7 +35,7 @@ namespace {
 
 struct StepWs {
   long long nu3 = 0, np = 0, nel = 0;
-  double* v[7] = {};        // velocity-sized work vectors
+  double* v[5] = {};        // velocity-sized work vectors
   double* bp = nullptr;     // pressure right-hand side
   double* tau = nullptr;    // tau_D (nel), tau_C (nel)
   double* partial = nullptr;   // 2 nel
@@ -206,7 +206,10 @@ extern "C" int dg_dual_splitting_step(const dg_op_desc* desc, const dg_step_opts
   if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
   StepWs& W = g_step[dev];
   if ((e = step_ensure(W, nu3, np, nel)) != hipSuccess) return hip_fail(e, "step workspace allocation");
-  double *C = W.v[0], *C2 = W.v[1], *uhat = W.v[2], *gp = W.v[3], *rhs3 = W.v[4], *uhh = W.v[5], *rhs4 = W.v[6];
+  double *C = W.v[0], *C2 = W.v[1], *gp = W.v[2], *rhs3 = W.v[3], *rhs4 = W.v[4];
+  // U^, U^^ and U^{n+1} are formed in u_np1 itself: each solve starts in
+  // place from the previous substep's velocity, its initial guess
+  double* const uhat = u_np1;
 
   // descriptors: velocity (3 components), pressure (degree k-1)
   dg_op_desc dv = *desc;
@@ -285,16 +288,12 @@ extern "C" int dg_dual_splitting_step(const dg_op_desc* desc, const dg_step_opts
     return hip_fail(e, "mixed gradient kernel launch");
   if ((e = launch_lincomb(rhs3, rhs3, gp, nullptr, 1.0, -dt / g0, 0.0, nu3, s)) != hipSuccess)
     return hip_fail(e, "lincomb");
-  if ((e = hipMemcpyAsync(uhh, uhat, ub, hipMemcpyDeviceToDevice, s)) != hipSuccess)
-    return hip_fail(e, "initial guess");
   dg_cg_report pr{};
-  rc = mass_pcg_solve(&dv, DG_OP_PROJECTION, 0.0, W.tau, W.tau + nel, rhs3, uhh, opts->rtol_projection,
+  rc = mass_pcg_solve(&dv, DG_OP_PROJECTION, 0.0, W.tau, W.tau + nel, rhs3, u_np1, opts->rtol_projection,
                       opts->max_iter, &pr, hip_stream, false);
   if (rc) return step_fail(rc, "projection CG");
   // 4. viscous step
-  if ((rc = dg_apply_helmholtz(&dm, DG_F64, g0 / dt, uhh, rhs4, s))) return rc;
-  if ((e = hipMemcpyAsync(u_np1, uhh, ub, hipMemcpyDeviceToDevice, s)) != hipSuccess)
-    return hip_fail(e, "initial guess");
+  if ((rc = dg_apply_helmholtz(&dm, DG_F64, g0 / dt, u_np1, rhs4, s))) return rc;
   dg_op_desc dvv = dv;
   dvv.scale = nu;
   dg_cg_report vr{};
