@@ -340,6 +340,23 @@ int dg_dual_splitting_step(const dg_op_desc* desc, const dg_step_opts* opts, con
                            const double* u_nm1, double* u_np1, double* p, dg_step_report* report,
                            void* hip_stream);
 
+/*
+ * The same step with the convective term kept across steps (Sec. 3.1: the
+ * BDF2 extrapolation uses C(U^n) and C(U^{n-1}), and C(U^{n-1}) is the
+ * previous step's C(U^n)):
+ *   conv_nm1: C(u_nm1) as returned by the previous call in its conv_n, or
+ *             NULL (then computed); ignored for order 1;
+ *   conv_n:   out, C(u_n) (the convective form of dg_apply_convective,
+ *             before the inverse mass), for the next call, or NULL;
+ *   both [3][N_el][(k+1)^3] doubles (device), overlapping neither each
+ *   other nor the velocities or p (DG_ERR_ALIAS).  With conv_nm1 from the
+ *   previous call the result is bit-identical to dg_dual_splitting_step;
+ *   a conv_nm1 that is not C(u_nm1) gives a different (wrong) step.
+ */
+int dg_dual_splitting_step_conv(const dg_op_desc* desc, const dg_step_opts* opts, const double* u_n,
+                                const double* u_nm1, const double* conv_nm1, double* conv_n, double* u_np1,
+                                double* p, dg_step_report* report, void* hip_stream);
+
 enum { DG_OP_HELMHOLTZ = 0, DG_OP_PROJECTION = 1 };
 
 /*

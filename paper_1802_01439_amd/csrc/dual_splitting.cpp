@@ -163,9 +163,13 @@ extern "C" int dg_tgv_diagnostics(const dg_op_desc* desc, const double* u, doubl
   return rc ? rc : ok();
 }
 
-extern "C" int dg_dual_splitting_step(const dg_op_desc* desc, const dg_step_opts* opts, const double* u_n,
-                                      const double* u_nm1, double* u_np1, double* p, dg_step_report* report,
-                                      void* hip_stream) {
+namespace {
+
+// The step of dg_dual_splitting_step; conv_nm1 (order 2, optional): C(u_nm1)
+// kept from the previous step, conv_n (optional): C(u_n) for the next one.
+int dual_splitting_step(const dg_op_desc* desc, const dg_step_opts* opts, const double* u_n, const double* u_nm1,
+                        const double* conv_nm1, double* conv_n, double* u_np1, double* p, dg_step_report* report,
+                        void* hip_stream) {
   const auto t0 = std::chrono::steady_clock::now();
   int rc = validate_mixed(desc);
   if (rc) return rc;
@@ -192,6 +196,15 @@ extern "C" int dg_dual_splitting_step(const dg_op_desc* desc, const dg_step_opts
   if (overlaps(u_np1, ub, u_n, ub) || (u_nm1 && overlaps(u_np1, ub, u_nm1, ub)) || overlaps(p, pb, u_np1, ub) ||
       overlaps(p, pb, u_n, ub) || (u_nm1 && overlaps(p, pb, u_nm1, ub)))
     return fail(DG_ERR_ALIAS, "u_np1 and p must not overlap each other or the inputs");
+  if (opts->order == 1) conv_nm1 = nullptr;
+  for (const double* c : {(const double*)conv_n, conv_nm1}) {
+    if (!c) continue;
+    if (overlaps(c, ub, u_n, ub) || (u_nm1 && overlaps(c, ub, u_nm1, ub)) || overlaps(c, ub, u_np1, ub) ||
+        overlaps(c, ub, p, pb))
+      return fail(DG_ERR_ALIAS, "conv_n and conv_nm1 must not overlap the velocities or p");
+  }
+  if (conv_n && conv_nm1 && overlaps(conv_n, ub, conv_nm1, ub))
+    return fail(DG_ERR_ALIAS, "conv_n must not overlap conv_nm1");
   if (report) *report = dg_step_report{};
 
   const double dt = opts->dt, nu = opts->nu;
@@ -229,13 +242,21 @@ extern "C" int dg_dual_splitting_step(const dg_op_desc* desc, const dg_step_opts
     return code < 0 ? code : fail(code, std::string(what) + " did not converge");
   };
 
-  // 1. convective step
-  if ((rc = dg_apply_convective(&dc, DG_F64, u_n, C, s))) return rc;
+  // 1. convective step: C(u_n) into conv_n where the caller keeps it, C(u_nm1)
+  // from conv_nm1 where the caller kept it
+  double* const cn = conv_n ? conv_n : C;
+  if ((rc = dg_apply_convective(&dc, DG_F64, u_n, cn, s))) return rc;
   if (bdf2) {
-    if ((rc = dg_apply_convective(&dc, DG_F64, u_nm1, C2, s))) return rc;
-    if ((e = launch_lincomb(C, C, C2, nullptr, b0, b1, 0.0, nu3, s)) != hipSuccess) return hip_fail(e, "lincomb");
+    const double* cm = conv_nm1;
+    if (!cm) {
+      if ((rc = dg_apply_convective(&dc, DG_F64, u_nm1, C2, s))) return rc;
+      cm = C2;
+    }
+    if ((e = launch_lincomb(C, cn, cm, nullptr, b0, b1, 0.0, nu3, s)) != hipSuccess) return hip_fail(e, "lincomb");
+    if ((rc = dg_apply_inverse_mass(&dv, DG_F64, C, C, s))) return rc;
+  } else {
+    if ((rc = dg_apply_inverse_mass(&dv, DG_F64, cn, C, s))) return rc;
   }
-  if ((rc = dg_apply_inverse_mass(&dv, DG_F64, C, C, s))) return rc;
   if ((e = launch_lincomb(uhat, u_n, bdf2 ? u_nm1 : nullptr, C, a0 / g0, a1 / g0, -dt / g0, nu3, s)) != hipSuccess)
     return hip_fail(e, "lincomb");
   // 2. pressure step: L P = -(gamma_0/dt) D U^
@@ -312,4 +333,18 @@ extern "C" int dg_dual_splitting_step(const dg_op_desc* desc, const dg_step_opts
   if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "step");
   if (report) report->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   return ok();
+}
+
+}  // namespace
+
+extern "C" int dg_dual_splitting_step(const dg_op_desc* desc, const dg_step_opts* opts, const double* u_n,
+                                      const double* u_nm1, double* u_np1, double* p, dg_step_report* report,
+                                      void* hip_stream) {
+  return dual_splitting_step(desc, opts, u_n, u_nm1, nullptr, nullptr, u_np1, p, report, hip_stream);
+}
+
+extern "C" int dg_dual_splitting_step_conv(const dg_op_desc* desc, const dg_step_opts* opts, const double* u_n,
+                                           const double* u_nm1, const double* conv_nm1, double* conv_n,
+                                           double* u_np1, double* p, dg_step_report* report, void* hip_stream) {
+  return dual_splitting_step(desc, opts, u_n, u_nm1, conv_nm1, conv_n, u_np1, p, report, hip_stream);
 }

@@ -27,8 +27,8 @@ DG_STEP_PC_GMG_F32, DG_STEP_PC_CHEB_F32 = 0, 1
 
 EXPORTS = ("dg_apply_laplace", "dg_apply_convective", "dg_vjp_convective", "dg_apply_divergence",
            "dg_apply_inverse_mass", "dg_apply_helmholtz", "dg_apply_projection", "dg_apply_gradient", "dg_prolongate", "dg_restrict", "dg_gmg_vcycle", "dg_gmg_cg_solve", "dg_cg_solve", "dg_cg_solve_noalloc", "dg_mass_pcg_solve", "dg_apply_divergence_mixed", "dg_apply_gradient_mixed",
-           "dg_tgv_diagnostics", "dg_dual_splitting_step", "dg_laplace_diagonal", "dg_lgl_nodes", "dg_error_string",
-           "dg_last_error")
+           "dg_tgv_diagnostics", "dg_dual_splitting_step", "dg_dual_splitting_step_conv", "dg_laplace_diagonal",
+           "dg_lgl_nodes", "dg_error_string", "dg_last_error")
 
 
 class OpDesc(ctypes.Structure):
@@ -111,6 +111,8 @@ def lib():
         L.dg_tgv_diagnostics.argtypes = [pd, vp, ctypes.c_double, dp, vp]
         L.dg_dual_splitting_step.argtypes = [pd, ctypes.POINTER(StepOpts), vp, vp, vp, vp,
                                              ctypes.POINTER(StepReport), vp]
+        L.dg_dual_splitting_step_conv.argtypes = [pd, ctypes.POINTER(StepOpts), vp, vp, vp, vp, vp, vp,
+                                                  ctypes.POINTER(StepReport), vp]
         L.dg_laplace_diagonal.argtypes = [pd, dp]
         L.dg_lgl_nodes.argtypes = [i32, dp]
         L.dg_error_string.argtypes = [ctypes.c_int]
@@ -120,7 +122,7 @@ def lib():
         for name in ("dg_apply_laplace", "dg_apply_convective", "dg_vjp_convective", "dg_apply_divergence",
                      "dg_apply_inverse_mass", "dg_apply_helmholtz", "dg_apply_projection", "dg_apply_gradient", "dg_prolongate", "dg_restrict", "dg_gmg_vcycle", "dg_gmg_cg_solve", "dg_cg_solve", "dg_cg_solve_noalloc", "dg_mass_pcg_solve",
                      "dg_apply_divergence_mixed", "dg_apply_gradient_mixed", "dg_tgv_diagnostics",
-                     "dg_dual_splitting_step", "dg_laplace_diagonal", "dg_lgl_nodes"):
+                     "dg_dual_splitting_step", "dg_dual_splitting_step_conv", "dg_laplace_diagonal", "dg_lgl_nodes"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -504,11 +506,15 @@ def tgv_diagnostics(desc, u, nu):
 
 def dual_splitting_step(desc, u_n, u_nm1=None, p=None, out=None, dt=1e-3, nu=1.0 / 1600, order=2,
                         zeta_d=1.0, zeta_c=1.0, rtol=1e-6, rtol_pressure=None, rtol_projection=None,
-                        rtol_viscous=None, atol_pressure=1e-12, max_iter=2000, pressure_precond=DG_STEP_PC_GMG_F32):
+                        rtol_viscous=None, atol_pressure=1e-12, max_iter=2000, pressure_precond=DG_STEP_PC_GMG_F32,
+                        conv_prev=None, conv_out=None):
     """One dual-splitting step; u_n, u_nm1, out: float64 [3, N_el, (k+1)^3];
     p: float64 [N_el, k^3], initial guess in, P^{n+1} out (zeros if None);
     pressure_precond: DG_STEP_PC_GMG_F32 (one FP32 V-cycle per pressure CG
     iteration, the default) or DG_STEP_PC_CHEB_F32 (FP32 Chebyshev(5)).
+    conv_prev: C(u_nm1) from the previous step's conv_out (order 2), or None;
+    conv_out: a [3, N_el, (k+1)^3] float64 tensor that receives C(u_n), or
+    None (dg_dual_splitting_step_conv when either is given).
     Returns (u_np1, p, report dict, return code)."""
     torch = _torch()
     k = desc.degree
@@ -535,9 +541,21 @@ def dual_splitting_step(desc, u_n, u_nm1=None, p=None, out=None, dt=1e-3, nu=1.0
     o.pressure_precond = int(pressure_precond)
     rep = StepReport()
     nm1 = ctypes.c_void_p(u_nm1.data_ptr()) if order == 2 else None
-    rc = _check(lib().dg_dual_splitting_step(ctypes.byref(desc), ctypes.byref(o), ctypes.c_void_p(u_n.data_ptr()),
-                                             nm1, ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(p.data_ptr()),
-                                             ctypes.byref(rep), _stream(u_n)), soft_ok=True)
+    if conv_prev is None and conv_out is None:
+        rc = _check(lib().dg_dual_splitting_step(ctypes.byref(desc), ctypes.byref(o), ctypes.c_void_p(u_n.data_ptr()),
+                                                 nm1, ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(p.data_ptr()),
+                                                 ctypes.byref(rep), _stream(u_n)), soft_ok=True)
+        return out, p, rep.as_dict(), rc
+    for t, nm in ((conv_prev, "conv_prev"), (conv_out, "conv_out")):
+        if t is not None:
+            _check_tensor(t, nm, vshape, like=u_n)
+            _placed(u_n, t)
+    cp = ctypes.c_void_p(conv_prev.data_ptr()) if conv_prev is not None and order == 2 else None
+    co = ctypes.c_void_p(conv_out.data_ptr()) if conv_out is not None else None
+    rc = _check(lib().dg_dual_splitting_step_conv(ctypes.byref(desc), ctypes.byref(o), ctypes.c_void_p(u_n.data_ptr()),
+                                                  nm1, cp, co, ctypes.c_void_p(out.data_ptr()),
+                                                  ctypes.c_void_p(p.data_ptr()), ctypes.byref(rep), _stream(u_n)),
+                soft_ok=True)
     return out, p, rep.as_dict(), rc
 
 

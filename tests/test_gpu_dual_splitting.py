@@ -127,3 +127,42 @@ def test_step_argument_errors():
     with pytest.raises(dgmf.DgError) as ei:
         dgmf.apply_divergence_mixed(d1, torch.zeros((3, N ** 3, 8), dtype=torch.float64, device="cuda"))
     assert ei.value.code == dgmf.DG_ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("pc", [dgmf.DG_STEP_PC_GMG_F32, dgmf.DG_STEP_PC_CHEB_F32])
+def test_step_with_kept_convective_term_is_bit_identical(pc):
+    """dg_dual_splitting_step_conv: three steps (BDF1, then BDF2 twice) that
+    hand C(u_n) to the next step give bit-for-bit the steps of
+    dg_dual_splitting_step, which recompute C(u_nm1)."""
+    k, N = 5, 4
+    msh = M.Mesh((N, N, N), (2 * np.pi,) * 3)
+    u0 = to_dev(inputs.tgv_plus_noise(basis.lgl_nodes(k), msh.n_el, msh.length, seed=1560 + k, noise_std=0.05))
+    d = dgmf.make_desc(k, N)
+    announce(f"step with kept convective term k={k} N={N} pc={pc}")
+    kw = dict(dt=2e-2, nu=1 / 1600, pressure_precond=pc)
+    ref = [u0]
+    p = None
+    for n in range(3):
+        u, p, _, rc = dgmf.dual_splitting_step(d, ref[-1], ref[-2] if n else None, p=p, order=2 if n else 1, **kw)
+        assert rc == dgmf.DG_OK
+        ref.append(u.clone())
+        p = p.clone()
+    pref = p
+    got = [u0]
+    p = None
+    conv = [torch.empty_like(u0), torch.empty_like(u0)]
+    for n in range(3):
+        u, p, _, rc = dgmf.dual_splitting_step(d, got[-1], got[-2] if n else None, p=p, order=2 if n else 1,
+                                               conv_prev=conv[(n + 1) % 2] if n else None, conv_out=conv[n % 2], **kw)
+        assert rc == dgmf.DG_OK
+        got.append(u.clone())
+        p = p.clone()
+    for a, b in zip(ref, got):
+        assert torch.equal(a, b)
+    assert torch.equal(pref, p)
+    # the kept term is C(u_n) of the last step's input
+    c = dgmf.apply_convective(d, got[-2])
+    assert torch.equal(c, conv[2 % 2])
+    with pytest.raises(dgmf.DgError) as ei:
+        dgmf.dual_splitting_step(d, got[-1], got[-2], p=p, order=2, conv_prev=conv[0], conv_out=conv[0], **kw)
+    assert ei.value.code == dgmf.DG_ERR_ALIAS
