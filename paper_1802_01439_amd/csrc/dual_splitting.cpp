@@ -243,7 +243,8 @@ int dual_splitting_step(const dg_op_desc* desc, const dg_step_opts* opts, const 
   };
 
   // 1. convective step: C(u_n) into conv_n where the caller keeps it, C(u_nm1)
-  // from conv_nm1 where the caller kept it
+  // from conv_nm1 where the caller kept it; the BDF combination, the inverse
+  // mass and U^ in one pass
   double* const cn = conv_n ? conv_n : C;
   if ((rc = dg_apply_convective(&dc, DG_F64, u_n, cn, s))) return rc;
   if (bdf2) {
@@ -252,13 +253,14 @@ int dual_splitting_step(const dg_op_desc* desc, const dg_step_opts* opts, const 
       if ((rc = dg_apply_convective(&dc, DG_F64, u_nm1, C2, s))) return rc;
       cm = C2;
     }
-    if ((e = launch_lincomb(C, cn, cm, nullptr, b0, b1, 0.0, nu3, s)) != hipSuccess) return hip_fail(e, "lincomb");
-    if ((rc = dg_apply_inverse_mass(&dv, DG_F64, C, C, s))) return rc;
+    if ((e = launch_convective_substep(k, inverse_mass_1d(k), 1.0 / cell_volume(&dv), 3 * nel, cn, cm, b0, b1, u_n,
+                                       u_nm1, a0 / g0, a1 / g0, -dt / g0, uhat, s)) != hipSuccess)
+      return hip_fail(e, "convective substep");
   } else {
-    if ((rc = dg_apply_inverse_mass(&dv, DG_F64, cn, C, s))) return rc;
+    if ((e = launch_convective_substep(k, inverse_mass_1d(k), 1.0 / cell_volume(&dv), 3 * nel, cn, nullptr, b0, b1,
+                                       u_n, nullptr, a0 / g0, a1 / g0, -dt / g0, uhat, s)) != hipSuccess)
+      return hip_fail(e, "convective substep");
   }
-  if ((e = launch_lincomb(uhat, u_n, bdf2 ? u_nm1 : nullptr, C, a0 / g0, a1 / g0, -dt / g0, nu3, s)) != hipSuccess)
-    return hip_fail(e, "lincomb");
   // 2. pressure step: L P = -(gamma_0/dt) D U^
   const DivPlan DP = make_div_plan(&dv);
   if ((e = launch_mixed(DP, false, false, uhat, W.bp, -g0 / dt, s)) != hipSuccess)

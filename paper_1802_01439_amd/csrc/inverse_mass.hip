@@ -209,6 +209,97 @@ hipError_t launch_pcg_n(const std::vector<double>& Minv, double scale, long long
   return hipGetLastError();
 }
 
+// Convective substep of the dual-splitting scheme in one pass (FP64):
+//   C = b0 cn + b1 cm (cm optional),  C' = M^-1 C,
+//   uhat = a0 un + a1 unm1 + a2 C' (unm1 optional),
+// each combination with the operations of the step's separate linear
+// combination kernel (a product, then fused multiply-adds), so the result is
+// the one of the three separate passes; C and C' never go to memory.
+template <int N>
+__global__ void __launch_bounds__(LapCfgB<N>::THREADS)
+conv_substep_kernel(const double* __restrict__ cn, const double* __restrict__ cm, double b0, double b1,
+                    const double* __restrict__ un, const double* __restrict__ unm1, double a0, double a1, double a2,
+                    double* __restrict__ uhat, long long nblocks, const InvMassTab<N, double>* __restrict__ tab) {
+  using C = LapCfgB<N>;
+  constexpr int N2 = N * N, N3 = N * N * N, E = C::E, ES = C::ES, PX = C::PX, PY = C::PY;
+  __shared__ double U[E * ES];
+  const int tid = threadIdx.x;
+  const int le = tid / N2, p = tid - le * N2;
+  const int p0 = p % N, p1 = p / N;
+  const long long blk = (long long)blockIdx.x * E + le;
+  const bool active = blk < nblocks;
+  double* Ue = U + le * ES;
+  double x[N], y[N];
+  if (active) {
+    const auto& t = *fresh(tab);
+    const size_t o = blk * N3 + p0 + N * p1;
+#pragma unroll
+    for (int c = 0; c < N; ++c) {
+      if (cm) {
+        double v = b0 * cn[o + N2 * c];
+        x[c] = fma(b1, cm[o + N2 * c], v);
+      } else {
+        x[c] = cn[o + N2 * c];
+      }
+    }
+    mv<N, double>(t.A, x, y);
+    const int base = p0 + PX * p1;
+#pragma unroll
+    for (int c = 0; c < N; ++c) Ue[base + PY * c] = y[c];
+  }
+  __syncthreads();
+  if (active) {
+    const auto& t = *fresh(tab);
+    const int base = p0 + PY * p1;
+#pragma unroll
+    for (int b = 0; b < N; ++b) x[b] = Ue[base + PX * b];
+    mv<N, double>(t.A, x, y);
+#pragma unroll
+    for (int b = 0; b < N; ++b) Ue[base + PX * b] = y[b];
+  }
+  __syncthreads();
+  if (active) {
+    const auto& t = *fresh(tab);
+    const int base = PX * p0 + PY * p1;
+#pragma unroll
+    for (int a = 0; a < N; ++a) x[a] = Ue[base + a];
+    mv<N, double>(t.A, x, y);
+#pragma unroll
+    for (int a = 0; a < N; ++a) Ue[base + a] = t.scale * y[a];
+  }
+  __syncthreads();
+  if (active) {
+    const size_t o = blk * N3 + p0 + N * p1;
+    const int base = p0 + PX * p1;
+#pragma unroll
+    for (int c = 0; c < N; ++c) {
+      double v = a0 * un[o + N2 * c];
+      if (unm1) v = fma(a1, unm1[o + N2 * c], v);
+      uhat[o + N2 * c] = fma(a2, Ue[base + PY * c], v);
+    }
+  }
+}
+
+template <int N>
+hipError_t launch_substep_n(const std::vector<double>& Minv, double scale, long long nblocks, const double* cn,
+                            const double* cm, double b0, double b1, const double* un, const double* unm1, double a0,
+                            double a1, double a2, double* uhat, hipStream_t s) {
+  InvMassTab<N, double> t;
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j) t.A[i][j] = Minv[i * N + j];
+  t.scale = scale;
+  hipError_t err;
+  const InvMassTab<N, double>* dt = device_table_of("inverse_mass", t, &err);
+  if (!dt) return err;
+  using C = LapCfgB<N>;
+  const long long grid = (nblocks + C::E - 1) / C::E;
+  if (grid > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+  if (grid == 0) return hipSuccess;
+  hipLaunchKernelGGL((conv_substep_kernel<N>), dim3((unsigned)grid), dim3(C::THREADS), 0, s, cn, cm, b0, b1, un, unm1,
+                     a0, a1, a2, uhat, nblocks, dt);
+  return hipGetLastError();
+}
+
 template <int N, typename T>
 hipError_t launch_n(const std::vector<double>& Minv, double scale, long long nblocks, const void* src, void* dst,
                     hipStream_t s) {
@@ -286,6 +377,21 @@ hipError_t launch_pcg_precond(int k, const std::vector<double>& Minv, double sca
     case 9: return launch_pcg_n<10>(Minv, scale, nblocks, x, r, p, q, z, st, partial, s);
     case 10: return launch_pcg_n<11>(Minv, scale, nblocks, x, r, p, q, z, st, partial, s);
     case 11: return launch_pcg_n<12>(Minv, scale, nblocks, x, r, p, q, z, st, partial, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_convective_substep(int k, const std::vector<double>& Minv, double scale, long long nblocks,
+                                    const double* cn, const double* cm, double b0, double b1, const double* un,
+                                    const double* unm1, double a0, double a1, double a2, double* uhat,
+                                    hipStream_t s) {
+  switch (k) {
+#define DG_SUBSTEP_CASE(K) \
+  case K: return launch_substep_n<K + 1>(Minv, scale, nblocks, cn, cm, b0, b1, un, unm1, a0, a1, a2, uhat, s);
+    DG_SUBSTEP_CASE(1) DG_SUBSTEP_CASE(2) DG_SUBSTEP_CASE(3) DG_SUBSTEP_CASE(4) DG_SUBSTEP_CASE(5)
+    DG_SUBSTEP_CASE(6) DG_SUBSTEP_CASE(7) DG_SUBSTEP_CASE(8) DG_SUBSTEP_CASE(9) DG_SUBSTEP_CASE(10)
+    DG_SUBSTEP_CASE(11)
+#undef DG_SUBSTEP_CASE
     default: return hipErrorInvalidValue;
   }
 }

@@ -121,6 +121,13 @@ long long projection_grid(const ProjPlan& P);
 // mass on [0,1] (n x n row major), scale = 1/(h_x h_y h_z).
 hipError_t launch_inverse_mass(int k, const std::vector<double>& Minv, double scale, long long nblocks, bool f32,
                                const void* src, void* dst, hipStream_t s);
+// FP64, nblocks element blocks: uhat = a0 un + a1 unm1 + a2 M^-1 (b0 cn + b1 cm),
+// cm and unm1 optional (then their terms are absent); the operations of
+// launch_lincomb, launch_inverse_mass, launch_lincomb in one pass
+hipError_t launch_convective_substep(int k, const std::vector<double>& Minv, double scale, long long nblocks,
+                                    const double* cn, const double* cm, double b0, double b1, const double* un,
+                                    const double* unm1, double a0, double a1, double a2, double* uhat,
+                                    hipStream_t s);
 
 int vjp_max_degree(bool f32);
 
